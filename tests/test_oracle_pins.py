@@ -1,0 +1,643 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check here compares the oracle with something other than itself:
+values printed in the paper (golden fixtures with citations), closed forms,
+invariants, or finite differences.  None of these tests needs a GPU.
+"""
+import copy
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _free(cfg):
+    cfg = copy.deepcopy(cfg)
+    cfg["mesh"]["bc"] = 2
+    return cfg
+
+
+def _grid_coords(cfg):
+    """Reference coordinates of the structured generator (for perturbation)."""
+    o = oracle.Oracle(cfg)
+    return o.get(oracle.COORDS).reshape(-1, 3)
+
+
+def _elastic(mat):
+    m = dict(mat)
+    m["law"] = W.LAW_ELASTIC
+    return m
+
+
+AS4_ELASTIC = dict(W.material_isotropic(1.0, 0.0, 1590.0),
+                   E1=128.0e9, E2=7.63e9, E3=7.63e9, nu12=0.35, nu13=0.35, nu23=0.45,
+                   G12=4.358e9, G13=4.358e9, G23=2.631e9)
+
+
+# ---------------------------------------------------------------------------
+# mesh generator: Table 3 counts (and Eq. mmu)
+# ---------------------------------------------------------------------------
+
+def _table3_mesh(level):
+    g = json.load(open(os.path.join(GOLD, "table3_mesh_counts.json")))
+    lv = g["levels"][level]
+    t = g["cluster_thickness_mm"] * 1e-3
+    mesh = W._mesh(lv["nx"], lv["ny"], 8, lv["elements_per_cluster"], 0.150, 0.100, t,
+                   g["cluster_angles_deg"], cohesive=1)
+    return g, lv, mesh
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_table3_counts(level):
+    g, lv, mesh = _table3_mesh(level)
+    c = oracle.mesh_counts(mesh)
+    assert c["n_bulk"] + c["n_cohesive"] == lv["n_elements"]
+    assert c["n_nodes"] == lv["n_nodes"]
+
+
+def test_eq_mmu_element_count():
+    """Eq. (mmu): n_e = 8 n_e^0 - 4 n_e,ELINT^0 with n_e^0 all base elements."""
+    _, _, m0 = _table3_mesh(0)
+    _, lv1, _ = _table3_mesh(1)
+    c0 = oracle.mesh_counts(m0)
+    n0 = c0["n_bulk"] + c0["n_cohesive"]
+    assert 8 * n0 - 4 * c0["n_cohesive"] == lv1["n_elements"]
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_table3_stable_increment_sanity(level):
+    """Loose check (+-15%) of the critical step against Table 3's printed value,
+    AS4/8552 elastic constants of Table 1, undamaged stiffness, no safety factor."""
+    g, lv, mesh = _table3_mesh(level)
+    h = lv["element_size_mm"] * 1e-3
+    small = W._mesh(6, 6, 8, lv["elements_per_cluster"], 6 * h, 6 * h,
+                    g["cluster_thickness_mm"] * 1e-3, g["cluster_angles_deg"], cfl_safety=1.0)
+    cfg = dict(mesh=small, materials=[AS4_ELASTIC], impactor=W.impactor(8e-3, 1.0, v0=1.0))
+    dt = oracle.Oracle(cfg).dt
+    assert 0.85 < lv["stable_dt_s"] / dt < 1.15
+
+
+def test_config_counts():
+    assert oracle.mesh_counts(W.config1()["mesh"])["n_nodes"] == 21 * 21 * 5
+    c3 = oracle.mesh_counts(W.config3()["mesh"])
+    assert c3["n_planes"] == 23 and c3["n_bulk"] == 15360000 and c3["n_cohesive"] == 5760000
+    assert c3["n_nodes"] == 22126023
+
+
+# ---------------------------------------------------------------------------
+# element: patch test, finite differences, rigid rotation, mass
+# ---------------------------------------------------------------------------
+
+def _distorted(cfg, amp, seed):
+    X = _grid_coords(cfg)
+    m = cfg["mesh"]
+    nx, ny = m["nx"], m["ny"]
+    K = oracle.mesh_counts(m)["n_planes"]
+    g = np.random.default_rng(seed)
+    h = min(m["lx"] / nx, m["ly"] / ny, m["ply_thickness"] / m["elems_per_ply"])
+    Xd = X.copy()
+    for k in range(1, K - 1):
+        for j in range(1, ny):
+            for i in range(1, nx):
+                n = i + (nx + 1) * (j + (ny + 1) * k)
+                Xd[n] += g.uniform(-amp, amp, 3) * h
+    return Xd
+
+
+def _homog_cfg(angle=30.0, n=3):
+    mat = _elastic(W.material_cfrp(True, 1e-3))
+    cfg = dict(mesh=W._mesh(n, n, n, 1, n * 1e-3, n * 1e-3, 1e-3, [angle] * n, bc=2, gravity=0.0),
+               materials=[mat], impactor=W.impactor(4e-3, 1.0, v0=0.0, gap=1.0))
+    return cfg
+
+
+def test_patch_test_distorted_large_deformation():
+    """A linear displacement field on a distorted mesh leaves interior nodes in
+    equilibrium (uniform F, E and S; hourglass forces vanish)."""
+    cfg = _homog_cfg()
+    Xd = _distorted(cfg, 0.2, 1)
+    o = oracle.Oracle(cfg, node_coords=Xd.reshape(-1))
+    A = np.array([[0.04, 0.01, -0.02], [0.015, -0.03, 0.01], [0.02, 0.005, 0.05]])
+    u = Xd @ A.T + np.array([1e-4, -2e-4, 3e-4])
+    o.set(oracle.DISP, u.reshape(-1))
+    o.step(0)
+    f = o.get(oracle.FINT).reshape(-1, 3)
+    m = cfg["mesh"]
+    interior = [i + 4 * (j + 4 * k) for k in (1, 2) for j in (1, 2) for i in (1, 2)]
+    scale = np.abs(f).max()
+    assert scale > 0
+    assert np.abs(f[interior]).max() <= 1e-12 * scale
+    # equilibrium of the whole body (internal forces sum to zero)
+    assert np.abs(f.sum(axis=0)).max() <= 1e-12 * scale
+
+
+def _one_hex(seed, amp=0.15, h=1e-3):
+    g = np.random.default_rng(seed)
+    X = np.array([[W_XI, W_ETA, W_ZETA] for W_XI, W_ETA, W_ZETA in
+                  zip([-1, 1, 1, -1, -1, 1, 1, -1], [-1, -1, 1, 1, -1, -1, 1, 1],
+                      [-1, -1, -1, -1, 1, 1, 1, 1])], dtype=float) * 0.5 * h
+    return X + g.uniform(-amp, amp, X.shape) * h
+
+
+@pytest.mark.parametrize("angle", [0.0, 30.0, 90.0])
+def test_element_force_is_energy_gradient(angle):
+    """f = dW/du (W = SVK strain energy + hourglass energy), central differences."""
+    X = _one_hex(3)
+    mat = _elastic(W.material_cfrp(False, 1e-3))
+    g = np.random.default_rng(5)
+    u = g.uniform(-1, 1, (8, 3)) * 2e-5
+    f, _ = oracle.hex8_force_elastic(X, u, mat, angle, 0.05)
+    fd = np.zeros(24)
+    du = 1e-9
+    uf = u.reshape(-1)
+    for k in range(24):
+        up, um = uf.copy(), uf.copy()
+        up[k] += du
+        um[k] -= du
+        fd[k] = (oracle.hex8_force_elastic(X, up, mat, angle, 0.05)[1]
+                 - oracle.hex8_force_elastic(X, um, mat, angle, 0.05)[1]) / (2 * du)
+    assert np.abs(fd - f.reshape(-1)).max() <= 1e-6 * np.abs(f).max()
+
+
+def test_hourglass_energy_gradient_pure_mode():
+    """With a pure hourglass mode the stress part is tiny; the force is still the
+    gradient of the hourglass energy and is non-zero."""
+    X = _one_hex(11, amp=0.0)
+    mat = _elastic(W.material_isotropic(70e9, 0.3, 2700.0))
+    xi = np.array([-1, 1, 1, -1, -1, 1, 1, -1.0])
+    eta = np.array([-1, -1, 1, 1, -1, -1, 1, 1.0])
+    zeta = np.array([-1, -1, -1, -1, 1, 1, 1, 1.0])
+    u = np.zeros((8, 3))
+    u[:, 0] = 1e-6 * xi * eta * zeta
+    f0, W0 = oracle.hex8_force_elastic(X, u, mat, 0.0, 0.0)
+    f1, W1 = oracle.hex8_force_elastic(X, u, mat, 0.0, 0.05)
+    assert np.abs(f0).max() < 1e-6 * np.abs(f1).max()   # 1-point element: zero energy mode
+    assert W1 > 0 and np.abs(f1).max() > 0
+
+
+def test_rigid_rotation_gives_zero_force():
+    X = _one_hex(7)
+    mat = _elastic(W.material_cfrp(True, 1e-3))
+    ax = np.array([1.0, 2.0, 3.0]) / math.sqrt(14.0)
+    th = math.pi / 2
+    Kx = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    R = np.eye(3) + math.sin(th) * Kx + (1 - math.cos(th)) * Kx @ Kx
+    u = X @ (R - np.eye(3)).T
+    f, Wr = oracle.hex8_force_elastic(X, u, mat, 30.0, 0.05)
+    fs, _ = oracle.hex8_force_elastic(X, X * 0.01, mat, 30.0, 0.05)
+    assert np.abs(f).max() <= 1e-11 * np.abs(fs).max()
+
+
+def test_mean_gradient_reproduces_linear_fields():
+    X = _one_hex(13)
+    b, V, gam = oracle.hex8_geometry(X)
+    assert np.allclose(X.T @ b, np.eye(3), atol=1e-12)
+    assert np.abs(gam @ X).max() < 1e-15 and np.abs(gam.sum(axis=1)).max() < 1e-15
+
+
+def test_lumped_mass_sums_to_rho_V():
+    cfg = _homog_cfg(n=3)
+    Xd = _distorted(cfg, 0.25, 2)
+    o = oracle.Oracle(cfg, node_coords=Xd.reshape(-1))
+    m = o.get(oracle.MASS)
+    rho = cfg["materials"][0]["rho"]
+    assert abs(m.sum() - rho * 3e-3 * 3e-3 * 3e-3) <= 1e-13 * m.sum()
+    assert (m > 0).all()
+
+
+# ---------------------------------------------------------------------------
+# integrator: 1D-strain column dispersion, TW identity, RK4
+# ---------------------------------------------------------------------------
+
+def _column(N=40, L=0.02, phi=1.0):
+    h = L / N
+    mat = W.material_isotropic(70e9, 0.3, 2700.0)
+    cfg = dict(mesh=W._mesh(1, 1, 1, N, h, h, L, [0.0], bc=2, gravity=0.0, phi=phi),
+               materials=[mat], impactor=W.impactor(1e-3, 1.0, v0=0.0, gap=1.0))
+    o = oracle.Oracle(cfg)
+    nn = o.nn
+    fix = np.zeros((nn, 3))
+    fix[:, 0] = fix[:, 1] = 1
+    for n in range(nn):
+        k = n // 4
+        if k == 0 or k == N:
+            fix[n, 2] = 1
+    o.set(oracle.FIX, fix.reshape(-1))
+    return o, cfg, h, mat
+
+
+def _mode_amp(d, N, L, k):
+    z = np.arange(N + 1) * (L / N)
+    uz = d.reshape(-1, 3)[:, 2].reshape(N + 1, 4).mean(axis=1)
+    s = np.sin(k * math.pi * z / L)
+    return (uz @ s) / (s @ s), uz
+
+
+@pytest.mark.parametrize("k", [1, 7, 39])
+def test_column_discrete_dispersion(k):
+    """Lumped-mass 1-point hex column in 1D strain = discrete chain:
+    omega_k = 2 (c_D/h) sin(k pi / 2N); CD gives u^{n+1} + u^{n-1} = (2 - omega^2 dt^2) u^n."""
+    N, L = 40, 0.02
+    o, cfg, h, mat = _column(N, L)
+    E, nu, rho = 70e9, 0.3, 2700.0
+    cD = math.sqrt(E * (1 - nu) / ((1 + nu) * (1 - 2 * nu)) / rho)
+    dt = o.dt
+    assert abs(dt - 0.9 * h / cD) <= 1e-12 * dt
+    A = 1e-5 * L / (k * math.pi)        # peak strain 1e-5: round-off and O(eps^2) both ~1e-10
+    z = (np.arange(o.nn) // 4) * (L / N)
+    d0 = np.zeros((o.nn, 3))
+    d0[:, 2] = A * np.sin(k * math.pi * z / L)
+    o.set(oracle.DISP, d0.reshape(-1))
+    amps = []
+    for n in range(60):
+        a, uz = _mode_amp(o.get(oracle.DISP), N, L, k)
+        amps.append(a)
+        o.step(1)
+    amps = np.array(amps)
+    om = 2 * cD / h * math.sin(k * math.pi / (2 * N))
+    res = amps[2:] + amps[:-2] - (2 - (om * dt) ** 2) * amps[1:-1]
+    assert np.abs(res).max() <= 1e-8 * np.abs(amps).max()
+    # continuum limit for k = 1, N = 40, L = 20 mm, dt = 0.9 h / c_D
+    if k == 1:
+        Om = 2 / dt * math.asin(om * dt / 2)
+        assert abs(Om - math.pi * cD / L) / (math.pi * cD / L) < 1e-4
+
+
+def test_tw_phi1_is_central_difference():
+    """With phi = 1, d^{n+1} - d^n = dt v^{n+1} (central-difference velocity)."""
+    o, cfg, h, mat = _column(10, 0.005)
+    d0 = np.zeros((o.nn, 3))
+    z = (np.arange(o.nn) // 4) * 0.0005
+    d0[:, 2] = 1e-9 * np.sin(3 * math.pi * z / 0.005)
+    o.set(oracle.DISP, d0.reshape(-1))
+    o.step(1)
+    dt = o.dt
+    for _ in range(20):
+        d_prev = o.get(oracle.DISP)
+        o.step(1)
+        d, v = o.get(oracle.DISP), o.get(oracle.VEL)
+        assert np.abs(d - d_prev - dt * v).max() <= 1e-14 * np.abs(d).max() + 1e-30
+
+
+def test_tw_phi_above_one_damps_highest_mode():
+    """phi = 1.033 (Section 2.2.1) damps the highest-frequency mode; phi = 1 does not."""
+    amps = {}
+    for phi in (1.0, 1.033):
+        o, cfg, h, mat = _column(20, 0.01, phi)
+        z = (np.arange(o.nn) // 4) * 0.0005
+        d0 = np.zeros((o.nn, 3))
+        d0[:, 2] = 1e-10 * np.sin(19 * math.pi * z / 0.01)
+        o.set(oracle.DISP, d0.reshape(-1))
+        o.step(400)
+        e = o.energies()
+        amps[phi] = e["ke_plate"] + e["u_el"]
+    assert amps[1.033] < 0.5 * amps[1.0]
+
+
+def test_rk4_constant_force_exact():
+    a0 = -9.81 + 123.0
+    y = np.array([0.01, -2.0])
+    dt = 1e-3
+    t = 0.0
+    for _ in range(200):
+        y = oracle.rk4(lambda tt, yy: np.array([yy[1], a0]), t, y, dt)
+        t += dt
+    x_ex = 0.01 - 2.0 * t + 0.5 * a0 * t * t
+    v_ex = -2.0 + a0 * t
+    assert abs(y[0] - x_ex) <= 1e-13 * 1.0 and abs(y[1] - v_ex) <= 1e-12
+
+
+def test_rk4_fourth_order():
+    """Harmonic oscillator: halving dt divides the error by ~16 (k3/3 weight; the
+    printed k3/4 makes the weights sum to 11/12 and the method inconsistent)."""
+    w = 3.0
+
+    def run(dt):
+        y = np.array([1.0, 0.0])
+        t = 0.0
+        for _ in range(int(round(1.0 / dt))):
+            y = oracle.rk4(lambda tt, yy: np.array([yy[1], -w * w * yy[0]]), t, y, dt)
+            t += dt
+        return abs(y[0] - math.cos(w * 1.0))
+
+    e1, e2 = run(0.005), run(0.0025)
+    assert 3.85 < math.log2(e1 / e2) < 4.15
+
+
+# ---------------------------------------------------------------------------
+# intralaminar law (Algorithm 4 reading)
+# ---------------------------------------------------------------------------
+
+def _compliance(m):
+    """Textbook compliance of a transversely isotropic solid (engineering constants)."""
+    S = np.zeros((6, 6))
+    S[0, 0], S[1, 1], S[2, 2] = 1 / m["E1"], 1 / m["E2"], 1 / m["E3"]
+    S[0, 1] = S[1, 0] = -m["nu12"] / m["E1"]
+    S[0, 2] = S[2, 0] = -m["nu13"] / m["E1"]
+    S[1, 2] = S[2, 1] = -m["nu23"] / m["E2"]
+    S[3, 3], S[4, 4], S[5, 5] = 1 / m["G23"], 1 / m["G13"], 1 / m["G12"]
+    return S
+
+
+def test_cdm_undamaged_is_inverse_compliance():
+    m = W.material_cfrp(False, 0.5e-3)
+    S = _compliance(m)
+    Cm = np.zeros((6, 6))
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = 1e-7
+        sig, r, d = oracle.cdm(m, 1e-4, e, np.ones(4))
+        Cm[:, j] = sig / 1e-7
+        assert (r == 1).all() and (d == 0).all()
+    assert np.abs(Cm @ S - np.eye(6)).max() < 1e-12
+
+
+LC3 = (0.125e-3 * 0.125e-3 * 0.25e-3) ** (1 / 3)
+
+
+@pytest.mark.parametrize("mode,sgn,strength", [(0, 1, "XT"), (0, -1, "XC"), (1, 1, "YT"),
+                                               (1, -1, "YC"), (5, 1, "SL")])
+def test_cdm_peak_stress_uniaxial(mode, sgn, strength):
+    """Uniaxial-stress / pure-shear paths: the peak stress equals the strength
+    (onset at d = 0, where effective and nominal stress coincide)."""
+    m = W.material_cfrp(True, 0.5e-3)
+    X = m[strength]
+    S = _compliance(m)
+    r = np.ones(4)
+    peak = 0.0
+    for s in np.concatenate([np.linspace(0, 1, 201)[1:], 1 + np.linspace(0, 0.3, 61)[1:]]):
+        sv = np.zeros(6)
+        sv[mode] = sgn * s * X
+        sig, r, d = oracle.cdm(m, LC3, S @ sv, r)
+        peak = max(peak, sgn * sig[mode])
+    assert abs(peak - X) <= 1e-9 * X
+
+
+def _nu0(m):
+    m = dict(m)
+    m["nu12"] = m["nu13"] = m["nu23"] = 0.0
+    return m
+
+
+@pytest.mark.parametrize("mode,sgn,G,n", [(0, 1, "GXT", 400000), (0, -1, "GXC", 400000),
+                                          (1, 1, "GYT", 400000), (1, -1, "GYC", 400000),
+                                          (5, 1, "GSL", 400000)])
+def test_cdm_dissipated_energy_crack_band(mode, sgn, G, n):
+    """Monotonic strain path to full failure dissipates G / l_c per unit volume
+    (crack band; exact with zero Poisson coupling)."""
+    m = _nu0(W.material_cfrp(True, 0.5e-3))
+    lc = LC3
+    E = {0: m["E1"], 1: m["E2"], 5: m["G12"]}[mode]
+    Xs = {("GXT"): m["XT"], "GXC": m["XC"], "GYT": m["YT"], "GYC": m["YC"], "GSL": m["SL"]}[G]
+    e0 = Xs / E
+    emax = e0 * (60.0 if mode != 0 else 1.0)
+    if mode == 0:
+        g = m[G] / lc
+        fX = m["fXT"] if sgn > 0 else m["fXC"]
+        fG = m["fGT"] if sgn > 0 else m["fGC"]
+        emax = 1.05 * 2 * (1 - fG) * g / (fX * Xs)
+    else:
+        A = 2 * lc * Xs * Xs / (2 * E * m[G] - lc * Xs * Xs)
+        emax = e0 * (1 + 45.0 / A) * 1.2
+    es = np.linspace(0, emax, n)
+    r = np.ones(4)
+    sig = np.zeros(n)
+    idx = {(0, 1): 0, (0, -1): 1, (1, 1): 2, (1, -1): 3, (5, 1): 4}[(mode, sgn)]
+    stop = n
+    for k, e in enumerate(es):
+        eps = np.zeros(6)
+        eps[mode] = sgn * e
+        s, r, d = oracle.cdm(m, lc, eps, r)
+        sig[k] = sgn * s[mode]
+        if d[idx] >= 1.0 - 1.0000001e-6:     # saturated: only the residual stiffness is left
+            stop = k + 1
+            break
+    work = np.trapezoid(sig[:stop], es[:stop])
+    assert abs(work - m[G] / lc) <= 2e-5 * m[G] / lc
+
+
+def test_cdm_irreversible_secant_unloading():
+    m = _nu0(W.material_cfrp(False, 0.5e-3))
+    e0 = m["YT"] / m["E2"]
+    path = np.concatenate([np.linspace(0, 2 * e0, 50), np.linspace(2 * e0, 0, 50),
+                           np.linspace(0, 3 * e0, 50), np.linspace(3 * e0, 0.5 * e0, 50)])
+    r = np.ones(4)
+    rs, secant = [], []
+    for e in path:
+        eps = np.zeros(6)
+        eps[1] = e
+        s, r, d = oracle.cdm(m, LC3, eps, r)
+        rs.append(r.copy())
+        secant.append(s[1] / e if e > 0 else np.nan)
+    rs = np.array(rs)
+    assert (np.diff(rs, axis=0) >= 0).all()
+    un = np.array(secant[51:99])
+    assert np.nanmax(np.abs(un - un[0])) <= 1e-12 * abs(un[0])
+
+
+# ---------------------------------------------------------------------------
+# cohesive law (Algorithm 5 reading)
+# ---------------------------------------------------------------------------
+
+def _path_work(m, direction, smax, n=200000):
+    r = 0.0
+    ss = np.linspace(0, smax, n)
+    taus = np.zeros((n, 3))
+    for k, s in enumerate(ss):
+        tau, r, D = oracle.czm(m, s * np.asarray(direction), r)
+        taus[k] = tau
+    work = np.trapezoid(taus @ np.asarray(direction), ss)
+    return work, taus, ss
+
+
+def test_czm_mode_I_peak_and_toughness():
+    m = W.material_cfrp(True, 0.5e-3)
+    do = m["tauI"] / m["KI"]
+    tau, r, D = oracle.czm(m, [0, 0, do], 0.0)
+    assert abs(tau[2] - m["tauI"]) <= 1e-12 * m["tauI"] and D == 0
+    dc = 2 * m["GIc"] / m["tauI"]
+    work, taus, ss = _path_work(m, [0, 0, 1], 1.5 * dc)
+    assert abs(work - m["GIc"]) <= 1e-4 * m["GIc"]
+    assert abs(taus[-1, 2]) < 1e-6 * m["tauI"]      # no tensile traction after D = 1
+
+
+def test_czm_mode_II_toughness_and_peak():
+    m = W.material_cfrp(True, 0.5e-3)
+    dc = 2 * m["GIIc"] / m["tauII"]
+    work, taus, ss = _path_work(m, [1, 0, 0], 1.5 * dc)
+    assert abs(work - m["GIIc"]) <= 1e-4 * m["GIIc"]
+    assert abs(taus[:, 0].max() - m["tauII"]) <= 1e-3 * m["tauII"]
+
+
+@pytest.mark.parametrize("a,b", [(1.0, 1.0), (0.3, 1.0), (1.0, 0.2)])
+def test_czm_mixed_mode_bk_toughness(a, b):
+    """Proportional mixed-mode opening dissipates the Benzeggagh-Kenane toughness."""
+    m = W.material_cfrp(True, 0.5e-3)
+    Ksh = m["KI"] * (m["GIc"] / m["GIIc"]) * (m["tauII"] / m["tauI"]) ** 2
+    n = np.array([a, 0.0, b]) / math.hypot(a, b)
+    B = Ksh * n[0] ** 2 / (Ksh * n[0] ** 2 + m["KI"] * n[2] ** 2)
+    Gc = m["GIc"] + (m["GIIc"] - m["GIc"]) * B ** m["eta_bk"]
+    smax = 3 * 2 * m["GIIc"] / m["tauI"]
+    work, taus, ss = _path_work(m, n, smax)
+    assert abs(work - Gc) <= 2e-4 * Gc
+
+
+def test_czm_compression_is_penalty_contact():
+    m = W.material_cfrp(True, 0.5e-3)
+    tau, r, D = oracle.czm(m, [0, 0, 1.0], 0.0)            # fully broken in tension
+    assert r == 1.0
+    tau, r2, D = oracle.czm(m, [0, 0, -1e-7], r)
+    assert abs(tau[2] - m["KI"] * -1e-7) <= 1e-12 * abs(tau[2])
+
+
+def test_czm_t800_equal_penalties_table1():
+    """Table 1 T800S/M21 interface strengths were set (footnote d) so that the
+    shear and normal penalties coincide: K_sh/K_I = (G_Ic/G_IIc)(tau_II/tau_I)^2 = 1."""
+    g = json.load(open(os.path.join(GOLD, "table1_t800_interface.json")))
+    m = W.material_cfrp(True, 0.5e-3)
+    m.update(tauI=g["tauI_MPa"] * 1e6, tauII=g["tauII_MPa"] * 1e6,
+             GIc=g["GIc_N_per_mm"] * 1e3, GIIc=g["GIIc_N_per_mm"] * 1e3)
+    tau1, _, _ = oracle.czm(m, [1e-9, 0, 0], 0.0)
+    tau3, _, _ = oracle.czm(m, [0, 0, 1e-9], 0.0)
+    assert abs(tau1[0] / tau3[2] - 1.0) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# integration: energy, contact conditions, momentum, release
+# ---------------------------------------------------------------------------
+
+def test_config1_energy_identity():
+    o = oracle.Oracle(W.config1())
+    o.step(2000)
+    e = o.energies()
+    assert e["level"] == 1999
+    assert abs(e["residual"]) <= 1e-6 * e["ke0"]
+    assert abs(e["residual"]) <= 1e-12 * e["ke0"]        # the oracle closes to round-off
+    t, f, x = o.history()
+    assert len(f) == 2000 and f.max() > 0
+    # elastic: internal work equals the stored secant energy (no dissipation)
+    assert abs(e["w_int"] - e["u_el"]) <= 1e-5 * e["ke0"]
+
+
+def test_free_vibration_conserves_energy():
+    cfg = W.tiny(4, 4, 2, 2, gravity=0.0, isotropic=True)
+    cfg["mesh"]["bc"] = 2
+    cfg["impactor"]["gap"] = 1.0
+    o = oracle.Oracle(cfg)
+    # smooth field: the trapezoidal work is exact for the quadratic part of the
+    # energy; the cubic (geometric) part errs by O(strain * (omega dt)^2)
+    X = o.get(oracle.COORDS).reshape(-1, 3)
+    lx, ly = cfg["mesh"]["lx"], cfg["mesh"]["ly"]
+    d0 = np.zeros_like(X)
+    d0[:, 2] = 1e-8 * np.sin(np.pi * X[:, 0] / lx) * np.sin(np.pi * X[:, 1] / ly)
+    d0[:, 0] = 2e-9 * np.cos(np.pi * X[:, 1] / ly)
+    o.set(oracle.DISP, d0.reshape(-1))
+    o.step(1)
+    u0 = o.energies()["u_el"]
+    o.step(300)
+    e = o.energies()
+    assert abs(e["ke_plate"] + e["u_el"] - u0) <= 1e-8 * u0
+
+
+def _contact_cfg():
+    cfg = W.tiny(6, 6, 2, 2, isotropic=True, v0=5.0, mass=0.2, R=3e-3)
+    cfg["mesh"]["lx"] = cfg["mesh"]["ly"] = 12e-3
+    return cfg
+
+
+def test_non_penetration_and_eq2_every_step():
+    cfg = _contact_cfg()
+    o = oracle.Oracle(cfg)
+    R = cfg["impactor"]["radius"]
+    X = o.get(oracle.COORDS).reshape(-1, 3)
+    top = np.arange(o.nn - 49, o.nn)
+    seen = 0
+    for _ in range(400):
+        o.step(1)
+        d = o.get(oracle.DISP).reshape(-1, 3)
+        c = o.impactor_state()["centre"]
+        x = X[top] + d[top]
+        dist = np.linalg.norm(x - c, axis=1)
+        act = o.get(oracle.ACTIVE)[top] > 0
+        below = x[:, 2] <= c[2]
+        assert (np.abs(dist[act] - R) <= 1e-12 * R).all()
+        assert (dist[below & ~act] - R >= -1e-12 * R).all()
+        fc = o.get(oracle.FCONTACT).reshape(-1, 3)[top]
+        nvec = (x - c) / dist[:, None]
+        fn = (fc * nvec).sum(axis=1)
+        assert (fn[act] >= 0).all()                    # Eq. 2 on the contact set
+        seen += act.sum()
+    assert seen > 0
+
+
+def test_free_plate_momentum_closure():
+    cfg = _contact_cfg()
+    cfg["mesh"]["bc"] = 2
+    cfg["mesh"]["gravity"] = 0.0
+    o = oracle.Oracle(cfg)
+    m = o.get(oracle.MASS)
+    ms = cfg["impactor"]["mass"]
+    P0 = -ms * cfg["impactor"]["v0"]
+    for _ in range(300):
+        o.step(1)
+        v = o.get(oracle.VEL).reshape(-1, 3)
+        st = o.impactor_state()
+        Pp = (m * v[:, 2]).sum()
+        Ps = ms * st["velocity"][2]
+        pending = st["force"][2] * o.dt
+        assert abs(Pp + Ps - pending - P0) <= 1e-12 * abs(P0)
+
+
+def test_forced_adhesion_releases_nodes():
+    cfg = _contact_cfg()
+    o = oracle.Oracle(cfg)
+    while o.stats()["active"] < 1:
+        o.step(1)
+        assert o.stats()["steps"] < 2000
+    o.step(5)
+    assert o.stats()["active"] >= 1
+    imp = dict(cfg["impactor"])
+    imp["v0"] = -cfg["impactor"]["v0"]          # striker now moves away
+    o.set_impactor(imp)
+    before = o.stats()
+    o.step(1)
+    after = o.stats()
+    assert after["released"] > before["released"]
+    assert after["max_passes"] == 2
+    assert after["reset_passes"] - before["reset_passes"] == 2
+
+
+def test_cohesive_interface_uniform_opening():
+    """Uniform normal opening delta < onset of a two-ply plate: the interface
+    carries K_I delta over the whole area, equal and opposite on the two plies,
+    and stores 0.5 K_I delta^2 A."""
+    mats = W.ply_materials(2, 1e-3)
+    for m in mats:
+        m["law"] = W.LAW_ELASTIC
+    cfg = dict(mesh=W._mesh(3, 2, 2, 1, 3e-3, 2e-3, 1e-3, [0.0, 90.0], cohesive=1, bc=2,
+                            gravity=0.0),
+               materials=mats, impactor=W.impactor(4e-3, 1.0, v0=0.0, gap=1.0))
+    o = oracle.Oracle(cfg)
+    assert o.nc == 6
+    delta = 0.5 * mats[0]["tauI"] / mats[0]["KI"]
+    X = o.get(oracle.COORDS).reshape(-1, 3)
+    nplane = 4 * 3
+    d = np.zeros_like(X)
+    d[2 * nplane:, 2] = delta                      # planes 2, 3 (upper ply) move up
+    o.set(oracle.DISP, d.reshape(-1))
+    o.step(0)
+    f = o.get(oracle.FINT).reshape(-1, 3)
+    A = 3e-3 * 2e-3
+    top = f[2 * nplane:, 2].sum()
+    bot = f[:2 * nplane, 2].sum()
+    assert abs(top - mats[0]["KI"] * delta * A) <= 1e-12 * abs(top)
+    assert abs(top + bot) <= 1e-12 * abs(top)
+    o.step(1)
+    assert abs(o.energies()["u_el"] - 0.5 * mats[0]["KI"] * delta ** 2 * A) <= 1e-10 * 0.5 * mats[0]["KI"] * delta ** 2 * A

@@ -1,0 +1,271 @@
+"""Workload definitions and seeded input generators.
+
+This module is shared by the oracle harness and the HIP path's binding, so it
+holds inputs only: mesh sizes, ply layups, material constants, impactor data
+and seeded random numbers.  It contains none of the method's arithmetic (no
+kinematics, no constitutive law, no time integration); the oracle and the
+library each derive everything else (impact velocity from energy, stable time
+step, stiffness, ...) in their own code.
+
+Sources of the numbers:
+  * Table 1 (material properties, AS4/8552 column) of the paper for strengths,
+    toughness, softening shape factors and interface properties;
+  * the elastic constants the workloads state (E1 = 130 GPa, E2 = E3 = 8 GPa,
+    G12 = 4.5 GPa, nu12 = 0.3), with nu23 = 0.45 and rho = 1590 kg/m^3 from the
+    AS4/8552 column and G23 = E2 / (2 (1 + nu23)) as Table 1's own G23 entries
+    follow (7630/2.9 = 2631, 8540/2.9 = 2945);
+  * Section 3.2 (ASTM D7136 set-up): 150 x 100 mm coupon, 125 x 75 mm frame
+    cut-out, clamps at the four corners, 0.01 mm initial gap, gravity 9.81.
+All values are SI (m, kg, s, N, Pa, J/m^2).
+"""
+from __future__ import annotations
+
+import copy
+import math
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# seeded generators
+# ---------------------------------------------------------------------------
+
+_MASK64 = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 (Steele, Lea, Flood 2014), the published 64-bit mixer."""
+
+    def __init__(self, seed: int):
+        self.state = seed & _MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & _MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self) -> float:
+        """Double in [0, 1) from the top 53 bits."""
+        return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Integer uniform on [lo, hi] inclusive."""
+        return lo + int(self.uniform() * (hi - lo + 1))
+
+
+def rng(seed: int) -> np.random.Generator:
+    """numpy generator for synthetic states (parity inputs)."""
+    return np.random.default_rng(seed)
+
+
+# ---------------------------------------------------------------------------
+# materials
+# ---------------------------------------------------------------------------
+
+LAW_ELASTIC = 0
+LAW_CDM = 1
+LAW_CDM_SURROGATE = 2
+
+BC_CLAMPED_EDGES = 0
+BC_ASTM_WINDOW = 1
+
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+
+def material_isotropic(E: float, nu: float, rho: float) -> dict:
+    """Isotropic elastic solid written in the transversely isotropic fields."""
+    G = E / (2.0 * (1.0 + nu))
+    return dict(E1=E, E2=E, E3=E, nu12=nu, nu13=nu, nu23=nu, G12=G, G13=G, G23=G,
+                rho=rho, law=LAW_ELASTIC,
+                XT=0.0, XC=0.0, YT=0.0, YC=0.0, SL=0.0, alpha0_deg=53.0,
+                GXT=0.0, GXC=0.0, GYT=0.0, GYC=0.0, GSL=0.0,
+                fXT=0.0, fGT=0.0, fXC=0.0, fGC=0.0,
+                KI=0.0, tauI=0.0, tauII=0.0, GIc=0.0, GIIc=0.0, eta_bk=1.0)
+
+
+def material_cfrp(outer: bool, ply_thickness: float, law: int = LAW_CDM) -> dict:
+    """Carbon/epoxy ply: workload elastic constants + Table 1 AS4/8552 damage data.
+
+    ``outer`` selects the outer-ply in-situ strengths (Y_T = 74.2, S_L = 94.4 MPa)
+    instead of the embedded-ply ones (Y_T = 117.5, S_L = 120.8 MPa).  The
+    interface penalty is K_I = 50 E2 / t_ply (Section 2.3.2's lower bound), since
+    Table 1's AS4 value violates that bound.
+    """
+    E2 = 8.0e9
+    nu23 = 0.45
+    m = dict(E1=130.0e9, E2=E2, E3=E2, nu12=0.3, nu13=0.3, nu23=nu23,
+             G12=4.5e9, G13=4.5e9, G23=E2 / (2.0 * (1.0 + nu23)), rho=1590.0,
+             law=law,
+             XT=2300.0e6, XC=1531.0e6,
+             YT=(74.2e6 if outer else 117.5e6), YC=199.8e6,
+             SL=(94.4e6 if outer else 120.8e6), alpha0_deg=53.0,
+             GXT=81.5e3, GXC=106.3e3, GYT=280.0, GYC=1313.0, GSL=790.0,
+             fXT=0.1, fGT=0.6, fXC=0.1, fGC=0.9,
+             KI=50.0 * E2 / ply_thickness, tauI=74.2e6, tauII=94.36e6,
+             GIc=280.0, GIIc=790.0, eta_bk=1.45)
+    return m
+
+
+def ply_materials(n_plies: int, ply_thickness: float, law: int = LAW_CDM) -> list:
+    return [material_cfrp(p == 0 or p == n_plies - 1, ply_thickness, law)
+            for p in range(n_plies)]
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def _mesh(nx, ny, n_plies, elems_per_ply, lx, ly, ply_thickness, angles, *,
+          cohesive=0, bc=BC_CLAMPED_EDGES, window_lx=0.0, window_ly=0.0,
+          clamp_radius=0.0, precision=PREC_FP64, phi=1.0, cfl_safety=0.9,
+          gravity=9.81, hourglass_kappa=0.05):
+    return dict(nx=nx, ny=ny, n_plies=n_plies, elems_per_ply=elems_per_ply,
+                lx=lx, ly=ly, ply_thickness=ply_thickness,
+                ply_angle_deg=[float(a) for a in angles], cohesive=cohesive,
+                bc=bc, window_lx=window_lx, window_ly=window_ly,
+                clamp_radius=clamp_radius, precision=precision, phi=phi,
+                cfl_safety=cfl_safety, gravity=gravity,
+                hourglass_kappa=hourglass_kappa)
+
+
+def impactor(R, mass, *, v0=0.0, energy=0.0, gap=1.0e-5, x0=None, y0=None):
+    """Rigid hemispherical striker; x0/y0 None = plate centre."""
+    return dict(radius=R, mass=mass, v0=v0, energy=energy, gap=gap,
+                x0=(float('nan') if x0 is None else x0),
+                y0=(float('nan') if y0 is None else y0))
+
+
+LAYUP_QI8 = [0, 45, -45, 90, 90, -45, 45, 0]      # [0/45/-45/90]s
+
+
+def config1() -> dict:
+    """Isotropic plate 20x20x4, 50x50x2 mm, clamped edges, 0.5 kg at 2 m/s."""
+    return dict(
+        name="plain-fp64-isotropic-20x20x4",
+        mesh=_mesh(20, 20, 1, 4, 0.05, 0.05, 0.002, [0.0]),
+        materials=[material_isotropic(70.0e9, 0.3, 2700.0)],
+        impactor=impactor(8.0e-3, 0.5, v0=2.0),
+        steps=2000)
+
+
+def config2(precision=PREC_MIXED) -> dict:
+    """[0/45/-45/90]s, 150x100 mm, 300x200x8, CDM, 5.5 kg at 15 J."""
+    t = 0.5e-3
+    return dict(
+        name="cdm-qi8-300x200x8",
+        mesh=_mesh(300, 200, 8, 1, 0.150, 0.100, t, LAYUP_QI8,
+                   bc=BC_ASTM_WINDOW, window_lx=0.125, window_ly=0.075,
+                   clamp_radius=5.0e-3, precision=precision),
+        materials=ply_materials(8, t),
+        impactor=impactor(8.0e-3, 5.5, energy=15.0),
+        steps=61000)
+
+
+def config3(precision=PREC_MIXED) -> dict:
+    """Same laminate at 1200x800x16 (2 elements/ply) with cohesive interfaces, 25 J."""
+    t = 0.5e-3
+    return dict(
+        name="cdm-czm-qi8-1200x800x16",
+        mesh=_mesh(1200, 800, 8, 2, 0.150, 0.100, t, LAYUP_QI8, cohesive=1,
+                   bc=BC_ASTM_WINDOW, window_lx=0.125, window_ly=0.075,
+                   clamp_radius=5.0e-3, precision=precision),
+        materials=ply_materials(8, t),
+        impactor=impactor(8.0e-3, 5.5, energy=25.0),
+        steps=20000)
+
+
+def config5(precision=PREC_MIXED) -> dict:
+    c = config3(precision)
+    c["name"] = "surrogate-qi8-1200x800x16"
+    for m in c["materials"]:
+        m["law"] = LAW_CDM_SURROGATE
+    return c
+
+
+def config4_cases(n_cases=64, base_seed=0x9D5EED00) -> list:
+    """Uneven batch: per case s, SplitMix64(base_seed + s) draws, in this order,
+    plies P ~ U{4..16}, P angles from {0, 45, -45, 90}, target elements
+    N_e ~ U[20k, 400k], impact energy ~ U[5, 40] J and mass ~ U[1, 6] kg."""
+    cases = []
+    t = 0.25e-3
+    for s in range(n_cases):
+        g = SplitMix64(base_seed + s)
+        P = g.randint(4, 16)
+        angles = [(0, 45, -45, 90)[g.randint(0, 3)] for _ in range(P)]
+        Ne = 20000 + g.uniform() * 380000.0
+        energy = 5.0 + 35.0 * g.uniform()
+        mass = 1.0 + 5.0 * g.uniform()
+        nx = max(2, int(round(math.sqrt(1.5 * Ne / P))))
+        ny = max(2, int(round(Ne / (P * nx))))
+        cases.append(dict(
+            name=f"batch-case-{s}",
+            mesh=_mesh(nx, ny, P, 1, 0.150, 0.100, t, angles,
+                       bc=BC_ASTM_WINDOW, window_lx=0.125, window_ly=0.075,
+                       clamp_radius=5.0e-3, precision=PREC_MIXED),
+            materials=ply_materials(P, t),
+            impactor=impactor(8.0e-3, mass, energy=energy),
+            steps=1000))
+    return cases
+
+
+def scaled(cfg: dict, nx: int, ny: int, lx: float = None, ly: float = None,
+           precision: int = None, **mesh_over) -> dict:
+    """Copy of a workload on a smaller in-plane grid (same physics per element
+    when lx/ly shrink with nx/ny)."""
+    c = copy.deepcopy(cfg)
+    m = c["mesh"]
+    m["nx"], m["ny"] = nx, ny
+    if lx is not None:
+        m["lx"] = lx
+    if ly is not None:
+        m["ly"] = ly
+    if precision is not None:
+        m["precision"] = precision
+    m.update(mesh_over)
+    return c
+
+
+def tiny(nx=4, ny=4, n_plies=2, elems_per_ply=1, *, angles=None, cohesive=0,
+         law=LAW_ELASTIC, precision=PREC_FP64, lx=8.0e-3, ly=8.0e-3,
+         ply_thickness=1.0e-3, bc=BC_CLAMPED_EDGES, energy=0.0, v0=3.0,
+         mass=0.05, R=4.0e-3, gravity=9.81, isotropic=False) -> dict:
+    """Small mesh for brute-force and parity cases."""
+    if angles is None:
+        angles = [0.0 if p % 2 == 0 else 90.0 for p in range(n_plies)]
+    if isotropic:
+        mats = [material_isotropic(70.0e9, 0.3, 2700.0) for _ in range(n_plies)]
+    else:
+        mats = ply_materials(n_plies, ply_thickness, law)
+    return dict(
+        name=f"tiny-{nx}x{ny}x{n_plies * elems_per_ply}",
+        mesh=_mesh(nx, ny, n_plies, elems_per_ply, lx, ly, ply_thickness, angles,
+                   cohesive=cohesive, bc=bc, window_lx=0.75 * lx,
+                   window_ly=0.75 * ly, clamp_radius=0.1 * min(lx, ly),
+                   precision=precision, gravity=gravity),
+        materials=mats,
+        impactor=impactor(R, mass, v0=v0, energy=energy),
+        steps=50)
+
+
+# ---------------------------------------------------------------------------
+# synthetic states (seeded) for one-step parity at any size
+# ---------------------------------------------------------------------------
+
+def synthetic_state(n_nodes: int, n_gp: int, n_coh_pairs: int, seed: int,
+                    disp_amp: float, vel_amp: float, r_max: float = 1.0,
+                    rd_max: float = 0.0) -> dict:
+    """Random nodal displacement/velocity and damage thresholds.
+
+    disp:  3*n_nodes, uniform in [-disp_amp, disp_amp]
+    vel:   3*n_nodes, uniform in [-vel_amp, vel_amp]
+    r:     4*n_gp thresholds (r1+, r1-, r2+, r2-), 1 + U[0, r_max - 1]
+    rd:    n_coh_pairs cohesive thresholds, U[0, rd_max]
+    """
+    g = rng(seed)
+    d = g.uniform(-disp_amp, disp_amp, 3 * n_nodes)
+    v = g.uniform(-vel_amp, vel_amp, 3 * n_nodes)
+    r = 1.0 + g.uniform(0.0, max(r_max - 1.0, 0.0), 4 * n_gp)
+    rd = g.uniform(0.0, rd_max, n_coh_pairs)
+    return dict(disp=d, vel=v, r=r, rd=rd)
