@@ -390,19 +390,23 @@ static double hex8_force(const double *b, double V, const double *gam, const dou
                          const orc_material *m, double angle_deg, double kappa, double lc,
                          double *r, double f[24])
 {
-    double F[3][3];
+    /* F = I + H with H = sum_a u_a (x) b_a; the Green strain E = (F^T F - I)/2
+     * is evaluated as (H + H^T + H^T H)/2, the same tensor without the
+     * cancellation of 1 + small - 1 at small strain */
+    double H[3][3], F[3][3];
     for (int i = 0; i < 3; ++i)
         for (int J = 0; J < 3; ++J) {
-            double s = (i == J) ? 1.0 : 0.0;
+            double s = 0.0;
             for (int a = 0; a < 8; ++a) s += u[3 * a + i] * b[3 * a + J];
-            F[i][J] = s;
+            H[i][J] = s;
+            F[i][J] = s + ((i == J) ? 1.0 : 0.0);
         }
     double E[3][3];
     for (int I = 0; I < 3; ++I)
         for (int J = 0; J < 3; ++J) {
             double s = 0;
-            for (int k = 0; k < 3; ++k) s += F[k][I] * F[k][J];
-            E[I][J] = 0.5 * (s - (I == J ? 1.0 : 0.0));
+            for (int k = 0; k < 3; ++k) s += H[k][I] * H[k][J];
+            E[I][J] = 0.5 * (H[I][J] + H[J][I] + s);
         }
     /* material axes: fibre at angle theta about Z; Q rows = material axes */
     double th = angle_deg * M_PI / 180.0, c = cos(th), s = sin(th);
