@@ -1,0 +1,172 @@
+/*
+ * pdn.h -- C-ABI of the MI355X explicit PDN impact step (libpdn.so).
+ *
+ * The library advances a low-velocity impact of a rigid hemispherical striker
+ * on a laminated plate with the partial Dirichlet-Neumann (PDN) contact
+ * method of Guillamet et al., "Application of the partial Dirichlet-Neumann
+ * contact algorithm to simulate low-velocity impact events on composite
+ * structures": explicit Tchamwa-Wielgosz / central-difference integration
+ * with lumped mass (Section 2.2.1), a point-mass striker advanced by RK4
+ * with the contact force frozen over the step (Section 2.2.2), kinematic
+ * contact with node release and step repetition (Section 2.1, Eqs. 2-3,
+ * Algorithms 1-2), intralaminar damage (Section 2.3.1, Algorithm 4) and
+ * cohesive interfaces (Section 2.3.2, Algorithm 5).  Every step runs in HIP
+ * kernels on one gfx950 device.
+ *
+ * Conventions (all calls):
+ *  - host values are SI (m, kg, s, N, Pa, J/m^2) in double precision;
+ *  - node n = i + (nx+1) * (j + (ny+1) * k), i, j in-plane grid indices,
+ *    k the node plane (bottom 0); an interface between plies of different
+ *    angle duplicates its plane;  nodal vectors are x,y,z interleaved;
+ *  - bulk element e = i + nx * (j + ny * l), l the bulk element layer;
+ *  - cohesive node pair p = i + (nx+1) * (j + (ny+1) * c), c the interface;
+ *  - the impact direction is -Z; gravity acts along -Z;
+ *  - all input structs and arrays are copied during the call; outputs go to
+ *    caller-owned host buffers of capacity `cap` elements; when `cap` is too
+ *    small the call returns PDN_ERANGE and sets *n_out to the size needed;
+ *  - a context is used by one host thread at a time; it owns its device
+ *    memory and stream work;
+ *  - errors are negative return codes; pdn_last_error() gives the message.
+ */
+#ifndef PDN_H
+#define PDN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdn_ctx pdn_ctx;
+typedef struct pdn_batch pdn_batch;
+
+enum {
+    PDN_OK = 0,
+    PDN_EINVAL = -1,      /* invalid argument (sizes, material constants, snap-back) */
+    PDN_ENOMEM = -2,      /* device or host allocation failed */
+    PDN_EDEVICE = -3,     /* HIP runtime error */
+    PDN_ESTATE = -4,      /* call out of order (mesh -> materials -> impactor -> step) */
+    PDN_EUNSTABLE = -5,   /* non-finite state found; the context accepts only info/destroy */
+    PDN_ERANGE = -6       /* output buffer too small, or contact left the search window */
+};
+
+enum { PDN_FP64 = 0, PDN_MIXED = 1 };     /* MIXED: FP32 element arithmetic and GP state,
+                                             FP64 nodal, contact, striker and energies */
+enum { PDN_BC_CLAMPED_EDGES = 0, PDN_BC_ASTM_WINDOW = 1, PDN_BC_FREE = 2 };
+enum { PDN_LAW_ELASTIC = 0, PDN_LAW_CDM = 1, PDN_LAW_CDM_SURROGATE = 2 };
+enum { PDN_DMG_FIBRE = 0, PDN_DMG_MATRIX = 1, PDN_DMG_SHEAR = 2, PDN_DMG_COHESIVE = 3,
+       PDN_DMG_PROJ_FIBRE = 4, PDN_DMG_PROJ_MATRIX = 5, PDN_DMG_PROJ_COHESIVE = 6 };
+enum { PDN_ARR_DISP = 0,    /* 3 * n_nodes: displacement at the last completed level */
+       PDN_ARR_VEL = 1,     /* 3 * n_nodes: velocity (TW velocity = CD half-step velocity) */
+       PDN_ARR_GP_R = 2,    /* 4 * n_bulk: damage thresholds r1+, r1-, r2+, r2- per element */
+       PDN_ARR_COH_R = 3,   /* n_pairs: cohesive damage threshold per interface node pair */
+       PDN_ARR_MASS = 4 };  /* n_nodes: lumped mass (get only) */
+
+/* Plate description (Section 3.2 set-up): nx*ny element columns on lx*ly,
+ * n_plies plies of ply_thickness each split into elems_per_ply hex8 layers. */
+typedef struct {
+    int32_t nx, ny, n_plies, elems_per_ply;
+    double lx, ly, ply_thickness;
+    const double *ply_angle_deg;   /* n_plies, bottom to top (fibre angle about Z) */
+    int32_t cohesive;              /* 1 = zero-thickness interface where adjacent angles differ */
+    int32_t bc;                    /* PDN_BC_*: clamped lateral faces; ASTM D7136 cut-out
+                                      window (u_z = 0 on its edges, bottom plane) with corner
+                                      clamps (u = 0 within clamp_radius of each corner); free */
+    double window_lx, window_ly, clamp_radius;
+    int32_t precision;             /* PDN_FP64 or PDN_MIXED */
+    double phi;                    /* TW parameter: 1.0 = central difference */
+    double cfl_safety;             /* stable-step fraction, e.g. 0.9 */
+    double gravity;                /* m/s^2 along -Z on plate and striker (0 = off) */
+    double hourglass_kappa;        /* Flanagan-Belytschko stiffness coefficient, e.g. 0.05 */
+    const double *x_coords;        /* optional nx+1 graded grid lines (NULL = uniform) */
+    const double *y_coords;        /* optional ny+1 graded grid lines (NULL = uniform) */
+    int32_t device;                /* HIP device ordinal */
+    void *stream;                  /* hipStream_t to run on; NULL = the context's own */
+} pdn_mesh_desc;
+
+/* Ply material (Table 1 fields).  law = PDN_LAW_ELASTIC uses only the elastic
+ * constants.  The interface fields describe the cohesive interface lying on
+ * top of this ply.  Strengths whose crack-band softening would snap back at
+ * the element size (l_c X^2 >= 2 E G) are lowered to l_c X^2 = 0.9 * 2 E G. */
+typedef struct {
+    double E1, E2, E3, nu12, nu13, nu23, G12, G13, G23, rho;
+    int32_t law;
+    double XT, XC, YT, YC, SL, alpha0_deg;
+    double GXT, GXC, GYT, GYC, GSL;
+    double fXT, fGT, fXC, fGC;
+    double KI, tauI, tauII, GIc, GIIc, eta_bk;
+} pdn_material;
+
+/* Rigid striker (Section 3.2): radius, mass, initial tip gap above the top
+ * surface, impact velocity v0 or energy (energy > 0 gives v0 = sqrt(2E/m)),
+ * impact point x0/y0 (NaN = plate centre).  Lateral motion is constrained. */
+typedef struct {
+    double radius, mass, v0, energy, gap, x0, y0;
+} pdn_impactor;
+
+/* Energy books at the last complete time level L (one step behind the state).
+ * Identity: ke_plate + ke_striker + w_int + d_pdn = ke0 + w_grav. */
+typedef struct {
+    double level;
+    double ke_plate;         /* 0.5 sum m v^L . v^{L+1} */
+    double ke_striker;       /* 0.5 m_s |V^L|^2 */
+    double w_int;            /* trapezoidal work of internal forces (incl. hourglass, cohesive) */
+    double w_grav;           /* work of gravity on plate and striker */
+    double w_contact_plate;  /* trapezoidal work of the contact forces on the plate */
+    double w_striker;        /* work of the frozen contact force on the striker */
+    double d_pdn;            /* w_striker - w_contact_plate */
+    double ke0;              /* striker kinetic energy at t = 0 */
+    double u_el;             /* secant energy 0.5 sigma.eps V + hourglass + cohesive */
+    double residual;         /* left side minus right side of the identity */
+} pdn_energy;
+
+typedef struct {
+    double dt;
+    int64_t n_nodes, n_bulk, n_cohesive, n_pairs, n_planes, n_layers, n_candidates;
+    int64_t steps, reset_passes, released, active, max_passes;
+    double fallback_fraction;     /* surrogate: fraction of GP updates by the exact law */
+    int32_t precision, tile_x, tile_y, blocks;
+} pdn_info;
+
+/* Build the plate mesh and allocate device state on desc->device. */
+int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out);
+/* Set the material of one ply (ply = -1: all plies).  EINVAL on non-positive
+ * stiffness or a fibre softening law that is not ordered at this element size. */
+int pdn_material_set(pdn_ctx *ctx, int32_t ply, const pdn_material *m);
+/* Set the striker.  Before the first step: places it at gap above the plate
+ * centre (or x0, y0).  Later: replaces only its velocity (v0 along -Z). */
+int pdn_impactor_set(pdn_ctx *ctx, const pdn_impactor *imp);
+/* Advance n explicit steps (Algorithm 1) on the context's stream; returns
+ * after the stream has drained.  PDN_ERANGE if contact reached the edge of the
+ * contact search window; PDN_EUNSTABLE on non-finite state. */
+int pdn_step(pdn_ctx *ctx, int64_t n);
+/* Contact-force history, one entry per step: time, contact force on the plate
+ * along -Z, striker displacement along -Z. Any of t/force/imp_disp may be NULL. */
+int pdn_contact_force(const pdn_ctx *ctx, double *t, double *force, double *imp_disp,
+                      int64_t cap, int64_t *n_out);
+/* Damage field: per bulk element (FIBRE/MATRIX/SHEAR: max of the mode pair),
+ * per cohesive element (COHESIVE: max over its 4 nodal points), or projected
+ * nx*ny maps (PROJ_*: max over the thickness). */
+int pdn_damage_field(const pdn_ctx *ctx, int32_t kind, double *out, int64_t cap, int64_t *n_out);
+int pdn_energies(const pdn_ctx *ctx, pdn_energy *out);
+int pdn_info_get(const pdn_ctx *ctx, pdn_info *out);
+/* Read (get) or replace (set) a state array (PDN_ARR_*), host double values.
+ * A set makes the next step restart the explicit scheme from that state. */
+int pdn_array_get(const pdn_ctx *ctx, int32_t kind, double *out, int64_t cap, int64_t *n_out);
+int pdn_array_set(pdn_ctx *ctx, int32_t kind, const double *in, int64_t n);
+/* Checkpoint: opaque blob of every device array, striker, books and history. */
+int pdn_state_save(const pdn_ctx *ctx, void *buf, int64_t cap, int64_t *n_out);
+int pdn_state_load(pdn_ctx *ctx, const void *buf, int64_t n);
+/* Element-tile shape of the element/node kernel (autotuner hook): 0 = default. */
+int pdn_set_tile(pdn_ctx *ctx, int32_t tile_x, int32_t tile_y);
+/* Mean device time per step of the element/node kernel and of the contact
+ * kernel over the last pdn_step call, from HIP events (0 if not timed). */
+int pdn_kernel_times(const pdn_ctx *ctx, double *elem_node_ms, double *contact_ms);
+int pdn_set_timing(pdn_ctx *ctx, int32_t on);
+const char *pdn_last_error(const pdn_ctx *ctx);
+void pdn_destroy(pdn_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

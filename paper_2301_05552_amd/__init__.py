@@ -1,0 +1,241 @@
+"""MI355X explicit PDN impact step: thin ctypes binding of libpdn.so.
+
+Each method marshals arguments for the C call of the same name in
+include/pdn.h; every step of the method runs in the library's HIP kernels.
+Loading fails loudly when the library is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdn.so")
+_lib = None
+
+PDN_OK, PDN_EINVAL, PDN_ENOMEM, PDN_EDEVICE, PDN_ESTATE, PDN_EUNSTABLE, PDN_ERANGE = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED = 0, 1
+BC_CLAMPED_EDGES, BC_ASTM_WINDOW, BC_FREE = 0, 1, 2
+LAW_ELASTIC, LAW_CDM, LAW_CDM_SURROGATE = 0, 1, 2
+DMG_FIBRE, DMG_MATRIX, DMG_SHEAR, DMG_COHESIVE, DMG_PROJ_FIBRE, DMG_PROJ_MATRIX, DMG_PROJ_COHESIVE = range(7)
+ARR_DISP, ARR_VEL, ARR_GP_R, ARR_COH_R, ARR_MASS = range(5)
+
+EXPORTS = ["pdn_mesh_create", "pdn_material_set", "pdn_impactor_set", "pdn_step", "pdn_contact_force",
+           "pdn_damage_field", "pdn_energies", "pdn_info_get", "pdn_array_get", "pdn_array_set",
+           "pdn_state_save", "pdn_state_load", "pdn_set_tile", "pdn_kernel_times", "pdn_set_timing",
+           "pdn_last_error", "pdn_destroy"]
+
+
+class PdnError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"pdn error {code}: {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("n_plies", C.c_int32), ("elems_per_ply", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("ply_thickness", C.c_double),
+                ("ply_angle_deg", C.POINTER(C.c_double)), ("cohesive", C.c_int32), ("bc", C.c_int32),
+                ("window_lx", C.c_double), ("window_ly", C.c_double), ("clamp_radius", C.c_double),
+                ("precision", C.c_int32), ("phi", C.c_double), ("cfl_safety", C.c_double),
+                ("gravity", C.c_double), ("hourglass_kappa", C.c_double),
+                ("x_coords", C.POINTER(C.c_double)), ("y_coords", C.POINTER(C.c_double)),
+                ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+_MAT = ["E1", "E2", "E3", "nu12", "nu13", "nu23", "G12", "G13", "G23", "rho", "law",
+        "XT", "XC", "YT", "YC", "SL", "alpha0_deg", "GXT", "GXC", "GYT", "GYC", "GSL",
+        "fXT", "fGT", "fXC", "fGC", "KI", "tauI", "tauII", "GIc", "GIIc", "eta_bk"]
+
+
+class Material(C.Structure):
+    _fields_ = [(f, C.c_int32 if f == "law" else C.c_double) for f in _MAT]
+
+
+class Impactor(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("radius", "mass", "v0", "energy", "gap", "x0", "y0")]
+
+
+class Energy(C.Structure):
+    _fields_ = [(f, C.c_double) for f in ("level", "ke_plate", "ke_striker", "w_int", "w_grav",
+                                          "w_contact_plate", "w_striker", "d_pdn", "ke0", "u_el", "residual")]
+
+
+class Info(C.Structure):
+    _fields_ = [("dt", C.c_double)] + [(f, C.c_int64) for f in (
+        "n_nodes", "n_bulk", "n_cohesive", "n_pairs", "n_planes", "n_layers", "n_candidates",
+        "steps", "reset_passes", "released", "active", "max_passes")] + [
+        ("fallback_fraction", C.c_double), ("precision", C.c_int32), ("tile_x", C.c_int32),
+        ("tile_y", C.c_int32), ("blocks", C.c_int32)]
+
+
+def lib():
+    """Load libpdn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libpdn.so not built at {LIB_PATH}: run `python -m paper_2301_05552_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, vp, dp, i64 = C.POINTER, C.c_void_p, C.POINTER(C.c_double), C.c_int64
+        sig = {
+            "pdn_mesh_create": [P(MeshDesc), P(vp)],
+            "pdn_material_set": [vp, C.c_int32, P(Material)],
+            "pdn_impactor_set": [vp, P(Impactor)],
+            "pdn_step": [vp, i64],
+            "pdn_contact_force": [vp, dp, dp, dp, i64, P(i64)],
+            "pdn_damage_field": [vp, C.c_int32, dp, i64, P(i64)],
+            "pdn_energies": [vp, P(Energy)],
+            "pdn_info_get": [vp, P(Info)],
+            "pdn_array_get": [vp, C.c_int32, dp, i64, P(i64)],
+            "pdn_array_set": [vp, C.c_int32, dp, i64],
+            "pdn_state_save": [vp, vp, i64, P(i64)],
+            "pdn_state_load": [vp, vp, i64],
+            "pdn_set_tile": [vp, C.c_int32, C.c_int32],
+            "pdn_kernel_times": [vp, dp, dp],
+            "pdn_set_timing": [vp, C.c_int32],
+            "pdn_last_error": [vp],
+            "pdn_destroy": [vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.pdn_last_error.restype = C.c_char_p
+        L.pdn_destroy.restype = None
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Simulation:
+    """One impact simulation on one device (see include/pdn.h)."""
+
+    def __init__(self, cfg: dict, device: int = 0, stream=None, x_coords=None, y_coords=None,
+                 precision: int | None = None, tile: tuple | None = None):
+        L = lib()
+        m = cfg["mesh"]
+        self._ang = np.ascontiguousarray(m["ply_angle_deg"], dtype=np.float64)
+        self._xc = None if x_coords is None else np.ascontiguousarray(x_coords, dtype=np.float64)
+        self._yc = None if y_coords is None else np.ascontiguousarray(y_coords, dtype=np.float64)
+        prec = m["precision"] if precision is None else precision
+        d = MeshDesc(nx=m["nx"], ny=m["ny"], n_plies=m["n_plies"], elems_per_ply=m["elems_per_ply"],
+                     lx=m["lx"], ly=m["ly"], ply_thickness=m["ply_thickness"], ply_angle_deg=_dp(self._ang),
+                     cohesive=m["cohesive"], bc=m["bc"], window_lx=m["window_lx"], window_ly=m["window_ly"],
+                     clamp_radius=m["clamp_radius"], precision=prec, phi=m["phi"],
+                     cfl_safety=m["cfl_safety"], gravity=m["gravity"], hourglass_kappa=m["hourglass_kappa"],
+                     x_coords=None if self._xc is None else _dp(self._xc),
+                     y_coords=None if self._yc is None else _dp(self._yc),
+                     device=device, stream=stream)
+        h = C.c_void_p()
+        rc = L.pdn_mesh_create(C.byref(d), C.byref(h))
+        if rc != 0:
+            raise PdnError(rc, "pdn_mesh_create failed")
+        self.h = h
+        self.cfg = cfg
+        if tile is not None:
+            self.set_tile(*tile)
+        mats = cfg["materials"]
+        if len(mats) == 1:
+            self.material_set(-1, mats[0])
+        else:
+            for p, mt in enumerate(mats):
+                self.material_set(p, mt)
+        if cfg.get("impactor") is not None:
+            self.impactor_set(cfg["impactor"])
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise PdnError(rc, lib().pdn_last_error(self.h).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pdn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- the six boundary calls ------------------------------------------------
+    def material_set(self, ply: int, mat: dict):
+        m = Material(**{f: (int(mat[f]) if f == "law" else float(mat[f])) for f in _MAT})
+        self._chk(lib().pdn_material_set(self.h, ply, C.byref(m)))
+
+    def impactor_set(self, imp: dict):
+        x0 = imp.get("x0", float("nan"))
+        y0 = imp.get("y0", float("nan"))
+        s = Impactor(radius=imp["radius"], mass=imp["mass"], v0=imp.get("v0", 0.0),
+                     energy=imp.get("energy", 0.0), gap=imp.get("gap", 1e-5),
+                     x0=float("nan") if x0 is None else x0, y0=float("nan") if y0 is None else y0)
+        self._chk(lib().pdn_impactor_set(self.h, C.byref(s)))
+
+    def step(self, n: int = 1):
+        return self._chk(lib().pdn_step(self.h, int(n)))
+
+    def contact_force(self):
+        n = C.c_int64()
+        lib().pdn_contact_force(self.h, None, None, None, 0, C.byref(n))
+        k = max(n.value, 1)
+        t, f, x = np.zeros(k), np.zeros(k), np.zeros(k)
+        self._chk(lib().pdn_contact_force(self.h, _dp(t), _dp(f), _dp(x), k, C.byref(n)))
+        return t[:n.value], f[:n.value], x[:n.value]
+
+    def damage_field(self, kind: int):
+        n = C.c_int64()
+        lib().pdn_damage_field(self.h, kind, None, 0, C.byref(n))
+        out = np.zeros(max(n.value, 1))
+        self._chk(lib().pdn_damage_field(self.h, kind, _dp(out), out.size, C.byref(n)))
+        return out[:n.value]
+
+    # ---- extensions --------------------------------------------------------------
+    def energies(self) -> dict:
+        e = Energy()
+        self._chk(lib().pdn_energies(self.h, C.byref(e)))
+        return {f: getattr(e, f) for f, _ in Energy._fields_}
+
+    def info(self) -> dict:
+        i = Info()
+        self._chk(lib().pdn_info_get(self.h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    def array_get(self, kind: int) -> np.ndarray:
+        n = C.c_int64()
+        lib().pdn_array_get(self.h, kind, None, 0, C.byref(n))
+        out = np.zeros(max(n.value, 1))
+        self._chk(lib().pdn_array_get(self.h, kind, _dp(out), out.size, C.byref(n)))
+        return out[:n.value]
+
+    def array_set(self, kind: int, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        self._chk(lib().pdn_array_set(self.h, kind, _dp(a), a.size))
+
+    def state_save(self) -> bytes:
+        n = C.c_int64()
+        lib().pdn_state_save(self.h, None, 0, C.byref(n))
+        buf = C.create_string_buffer(max(n.value, 1))
+        self._chk(lib().pdn_state_save(self.h, buf, n.value, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def state_load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        self._chk(lib().pdn_state_load(self.h, buf, len(blob)))
+
+    def set_tile(self, tx: int, ty: int):
+        self._chk(lib().pdn_set_tile(self.h, tx, ty))
+
+    def set_timing(self, on: bool):
+        self._chk(lib().pdn_set_timing(self.h, 1 if on else 0))
+
+    def kernel_times(self):
+        a, b = C.c_double(), C.c_double()
+        self._chk(lib().pdn_kernel_times(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value

@@ -1,0 +1,1067 @@
+// pdn_api.cpp -- host side of libpdn: the C-ABI of include/pdn.h.
+//
+// The host builds the structured plate (grid lines, layer table, support
+// masks), the per-ply constants and the time step, owns the device buffers
+// and launches the kernels; every step of the method runs on the device.
+#include "pdn.h"
+#include "pdn_internal.h"
+#include "pdn_launch.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+struct Buf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct pdn_ctx {
+    std::string err;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // description
+    int nx = 0, ny = 0, P = 0, epp = 0, NL = 0, K = 0, cohesive = 0, bc = 0, precision = 0;
+    double lx = 0, ly = 0, tply = 0, phi = 1, safety = 0.9, grav = 0, kappa = 0.05;
+    double wlx = 0, wly = 0, clamp_r = 0;
+    std::vector<double> ang, xs, ys, zk;
+    std::vector<LayerInfo> layers;
+    std::vector<int> bulk_layer, coh_layer;
+    int64_t nn = 0, ne = 0, nce = 0, npairs = 0, plane = 0;
+    // materials / striker
+    std::vector<pdn_material> mat;
+    std::vector<int> mat_set;
+    bool have_imp = false;
+    pdn_impactor imp{};
+    double v0 = 0;
+    // derived
+    double dt = 0;
+    std::vector<double> mx, my, mz, imx, imy, imz;
+    int ci0 = 0, ci1 = 0, cj0 = 0, cj1 = 0;
+    int tile = PDN_TILE_16x16, tiles_x = 1, tiles_y = 1;
+    // state
+    bool ready = false, needs_init = true, broken = false, loaded_state = false;
+    int cur = 0;                      // buffer with the last completed level
+    DevGlobals gl{};
+    // device buffers
+    double *d[2] = {nullptr, nullptr}, *v[2] = {nullptr, nullptr};
+    void *r = nullptr, *rd = nullptr;
+    void *hx = nullptr, *hy = nullptr, *ply = nullptr;
+    double *xs_d = nullptr, *ys_d = nullptr, *mx_d = nullptr, *my_d = nullptr, *mz_d = nullptr;
+    double *imx_d = nullptr, *imy_d = nullptr, *imz_d = nullptr, *blk_d = nullptr;
+    LayerInfo *layers_d = nullptr;
+    int *bulk_layer_d = nullptr, *coh_layer_d = nullptr;
+    uint8_t *bcb_d = nullptr;
+    uint8_t *active_d = nullptr;
+    double *vprev_d = nullptr, *fcprev_d = nullptr, *fside_d = nullptr;
+    double *partials_d = nullptr;
+    int nblocks = 0;
+    DevGlobals *gl_d = nullptr;
+    double *hist_d = nullptr;
+    int64_t hist_cap = 0;
+    double *dmg_d = nullptr;
+    size_t dmg_n = 0;
+    std::vector<uint8_t> bcb;
+    // timing
+    bool timing = false;
+    double t_en_ms = 0, t_ct_ms = 0;
+};
+
+namespace {
+
+int set_err(pdn_ctx *c, int code, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                       \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return set_err(ctx, e_ == hipErrorOutOfMemory ? PDN_ENOMEM : PDN_EDEVICE, "%s: %s", \
+                           #call, hipGetErrorString(e_));                                       \
+    } while (0)
+
+size_t rsize(const pdn_ctx *c) { return c->precision == PDN_MIXED ? sizeof(float) : sizeof(double); }
+
+int dalloc(pdn_ctx *c, void **p, size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return set_err(c, PDN_ENOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+    return PDN_OK;
+}
+
+template <typename T>
+int upload(pdn_ctx *c, T *dst, const std::vector<T> &src)
+{
+    if (src.empty()) return PDN_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return PDN_OK;
+}
+
+// inverse of the symmetric 3x3 normal compliance block (adjugate / det)
+void inv3(const double H[3][3], double C[3][3])
+{
+    double a00 = H[1][1] * H[2][2] - H[1][2] * H[2][1];
+    double a01 = H[0][2] * H[2][1] - H[0][1] * H[2][2];
+    double a02 = H[0][1] * H[1][2] - H[0][2] * H[1][1];
+    double a11 = H[0][0] * H[2][2] - H[0][2] * H[2][0];
+    double a12 = H[0][2] * H[1][0] - H[0][0] * H[1][2];
+    double a22 = H[0][0] * H[1][1] - H[0][1] * H[1][0];
+    double det = H[0][0] * a00 + H[0][1] * (H[1][2] * H[2][0] - H[1][0] * H[2][2]) + H[0][2] * (H[1][0] * H[2][1] - H[1][1] * H[2][0]);
+    C[0][0] = a00 / det; C[0][1] = a01 / det; C[0][2] = a02 / det;
+    C[1][0] = C[0][1]; C[1][1] = a11 / det; C[1][2] = a12 / det;
+    C[2][0] = C[0][2]; C[2][1] = C[1][2]; C[2][2] = a22 / det;
+}
+
+double stiffness_max(const pdn_material &m, double C[3][3])
+{
+    double H[3][3] = {{1 / m.E1, -m.nu12 / m.E1, -m.nu13 / m.E1},
+                      {-m.nu12 / m.E1, 1 / m.E2, -m.nu23 / m.E2},
+                      {-m.nu13 / m.E1, -m.nu23 / m.E2, 1 / m.E3}};
+    inv3(H, C);
+    double mx = std::max({m.G23, m.G13, m.G12});
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) mx = std::max(mx, std::fabs(C[i][j]));
+    return mx;
+}
+
+template <typename R>
+PlyC<R> make_ply(const pdn_material &m, double ang_deg)
+{
+    PlyC<R> P{};
+    double C[3][3];
+    double cm = stiffness_max(m, C);
+    P.C11 = (R)C[0][0]; P.C12 = (R)C[0][1]; P.C13 = (R)C[0][2];
+    P.C22 = (R)C[1][1]; P.C23 = (R)C[1][2]; P.C33 = (R)C[2][2];
+    P.G23 = (R)m.G23; P.G13 = (R)m.G13; P.G12 = (R)m.G12;
+    P.iE1 = (R)(1 / m.E1); P.iE2 = (R)(1 / m.E2); P.iE3 = (R)(1 / m.E3);
+    P.mn12 = (R)(-m.nu12 / m.E1); P.mn13 = (R)(-m.nu13 / m.E1); P.mn23 = (R)(-m.nu23 / m.E2);
+    const double th = ang_deg * M_PI / 180.0;
+    P.c = (R)std::cos(th);
+    P.s = (R)std::sin(th);
+    P.cmax = (R)cm;
+    P.E1 = (R)m.E1; P.E2 = (R)m.E2; P.G12v = (R)m.G12;
+    P.XT = (R)m.XT; P.XC = (R)m.XC; P.YT = (R)m.YT; P.YC = (R)m.YC; P.SL = (R)m.SL;
+    P.GXT = (R)m.GXT; P.GXC = (R)m.GXC; P.GYT = (R)m.GYT; P.GYC = (R)m.GYC; P.GSL = (R)m.GSL;
+    P.fXT = (R)m.fXT; P.fGT = (R)m.fGT; P.fXC = (R)m.fXC; P.fGC = (R)m.fGC;
+    const double a0 = m.alpha0_deg * M_PI / 180.0;
+    P.sa0 = (R)std::sin(a0);
+    P.ca0 = (R)std::cos(a0);
+    P.kST = (R)(std::cos(a0) * (std::sin(a0) + std::cos(a0) / std::tan(2 * a0)));
+    P.etaT = (R)(-1.0 / std::tan(2 * a0));
+    P.kEtaL = (R)(-std::cos(2 * a0) / (std::cos(a0) * std::cos(a0)));
+    P.rho = (R)m.rho;
+    P.law = m.law == PDN_LAW_ELASTIC ? 0 : 1;
+    if (P.law) {
+        const double kst = std::cos(a0) * (std::sin(a0) + std::cos(a0) / std::tan(2 * a0));
+        const double etat = -1.0 / std::tan(2 * a0);
+        P.kE1XT = (R)(m.E1 / m.XT);
+        P.kE1XC = (R)(m.E1 / m.XC);
+        P.iYT = (R)(1.0 / m.YT);
+        P.iYC = (R)(1.0 / m.YC);
+        P.iSL = (R)(1.0 / m.SL);
+        P.iST = (R)(1.0 / (kst * m.YC));
+        P.etaL0 = (R)(-std::cos(2 * a0) / (std::cos(a0) * std::cos(a0)) * m.SL / m.YC);
+        P.kT = (R)(std::cos(a0) * (std::sin(a0) + std::fabs(etat) * std::cos(a0)));
+        // largest crack band without a strength cap: l_c X^2 <= 1.8 E G for all three modes
+        const double l1 = 1.8 * m.E2 * m.GYT / (m.YT * m.YT);
+        const double l2 = 1.8 * m.E2 * m.GYC / (m.YC * m.YC);
+        const double l3 = 1.8 * m.G12 * m.GSL / (m.SL * m.SL);
+        const double lm = std::min({l1, l2, l3});
+        P.vol_nocap = (R)(lm * lm * lm * (1.0 - 1e-6));
+    }
+    P.KI = (R)m.KI;
+    const double ksh = (m.tauI > 0 && m.GIIc > 0) ? m.KI * (m.GIc / m.GIIc) * (m.tauII / m.tauI) * (m.tauII / m.tauI) : m.KI;
+    P.Ksh = (R)ksh;
+    P.tauI = (R)m.tauI; P.GIc = (R)m.GIc; P.GIIc = (R)m.GIIc; P.eta_bk = (R)m.eta_bk;
+    P.GIo = (R)(m.KI > 0 ? m.tauI * m.tauI / (2 * m.KI) : 0.0);
+    return P;
+}
+
+bool all_set(const pdn_ctx *c)
+{
+    for (int p = 0; p < c->P; ++p)
+        if (!c->mat_set[p]) return false;
+    return true;
+}
+
+int window_index(int n, double len, double win)
+{
+    double q = n * (len - win) / (2.0 * len);
+    return (int)std::floor(q + 0.5 + 1e-9);
+}
+
+// mass factors, time step, tables, globals; done once before the first step
+int prepare(pdn_ctx *c)
+{
+    const int nx = c->nx, ny = c->ny;
+    c->mx.assign(nx + 1, 0.0);
+    c->my.assign(ny + 1, 0.0);
+    c->mz.assign(c->K, 0.0);
+    for (int i = 0; i <= nx; ++i)
+        c->mx[i] = 0.5 * ((i > 0 ? c->xs[i] - c->xs[i - 1] : 0.0) + (i < nx ? c->xs[i + 1] - c->xs[i] : 0.0));
+    for (int j = 0; j <= ny; ++j)
+        c->my[j] = 0.5 * ((j > 0 ? c->ys[j] - c->ys[j - 1] : 0.0) + (j < ny ? c->ys[j + 1] - c->ys[j] : 0.0));
+    for (int k = 0; k < c->K; ++k) {
+        double s = 0;
+        if (k > 0 && c->layers[k - 1].type == 0) s += c->mat[c->layers[k - 1].ply].rho * c->layers[k - 1].hz;
+        if (k < c->NL && c->layers[k].type == 0) s += c->mat[c->layers[k].ply].rho * c->layers[k].hz;
+        c->mz[k] = 0.5 * s;
+    }
+    // stable step (Section 2.3.1: l_c / c_D with l_c = V / A_max; 2.3.2: interface springs)
+    double hxmin = 1e300, hymin = 1e300;
+    for (int i = 0; i < nx; ++i) hxmin = std::min(hxmin, c->xs[i + 1] - c->xs[i]);
+    for (int j = 0; j < ny; ++j) hymin = std::min(hymin, c->ys[j + 1] - c->ys[j]);
+    double dtb = 1e300, dtc = 1e300;
+    for (int l = 0; l < c->NL; ++l) {
+        const LayerInfo &L = c->layers[l];
+        const pdn_material &m = c->mat[L.ply];
+        if (L.type == 0) {
+            double C[3][3];
+            double cm = stiffness_max(m, C);
+            double lc = std::min({hxmin, hymin, L.hz});
+            dtb = std::min(dtb, lc * std::sqrt(m.rho / cm));
+        } else {
+            double a = c->mz[l], b = c->mz[l + 1];
+            dtc = std::min(dtc, 2.0 * std::sqrt((a * b / (a + b)) / m.KI));
+        }
+    }
+    c->dt = c->nce > 0 ? c->safety / std::sqrt(1.0 / (dtb * dtb) + 1.0 / (dtc * dtc)) : c->safety * dtb;
+
+    int rc;
+    if ((rc = upload(c, c->mx_d, c->mx))) return rc;
+    if ((rc = upload(c, c->my_d, c->my))) return rc;
+    if ((rc = upload(c, c->mz_d, c->mz))) return rc;
+    c->imx.resize(nx + 1);
+    c->imy.resize(ny + 1);
+    c->imz.resize(c->K);
+    for (int i = 0; i <= nx; ++i) c->imx[i] = 1.0 / c->mx[i];
+    for (int j = 0; j <= ny; ++j) c->imy[j] = 1.0 / c->my[j];
+    for (int k = 0; k < c->K; ++k) c->imz[k] = c->mz[k] > 0 ? 1.0 / c->mz[k] : 0.0;
+    if ((rc = upload(c, c->imx_d, c->imx))) return rc;
+    if ((rc = upload(c, c->imy_d, c->imy))) return rc;
+    if ((rc = upload(c, c->imz_d, c->imz))) return rc;
+    if (c->precision == PDN_MIXED) {
+        std::vector<PlyC<float>> pc;
+        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<float>(c->mat[p], c->ang[p]));
+        HIPCHK(c, hipMemcpyAsync(c->ply, pc.data(), pc.size() * sizeof(pc[0]), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<PlyC<double>> pc;
+        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<double>(c->mat[p], c->ang[p]));
+        HIPCHK(c, hipMemcpyAsync(c->ply, pc.data(), pc.size() * sizeof(pc[0]), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->ready = true;
+    return PDN_OK;
+}
+
+int ensure_history(pdn_ctx *c, int64_t need)
+{
+    if (need <= c->hist_cap) return PDN_OK;
+    int64_t cap = std::max<int64_t>(need, std::max<int64_t>(2 * c->hist_cap, 4096));
+    double *nh = nullptr;
+    int rc = dalloc(c, (void **)&nh, 3 * cap * sizeof(double));
+    if (rc) return rc;
+    if (c->hist_d) {
+        HIPCHK(c, hipMemcpyAsync(nh, c->hist_d, 3 * c->hist_cap * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        HIPCHK(c, hipFree(c->hist_d));
+    }
+    c->hist_d = nh;
+    c->hist_cap = cap;
+    c->gl.hist_cap = cap;
+    HIPCHK(c, hipMemcpyAsync(&c->gl_d->hist_cap, &cap, sizeof cap, hipMemcpyHostToDevice, c->stream));
+    return PDN_OK;
+}
+
+template <typename R>
+ElemArgs<R> elem_args(pdn_ctx *c, int in, int out)
+{
+    ElemArgs<R> a{};
+    a.nx = c->nx; a.ny = c->ny; a.K = c->K; a.NL = c->NL;
+    a.tiles_x = c->tiles_x; a.tiles_y = c->tiles_y;
+    a.clamp_lateral = c->bc == PDN_BC_CLAMPED_EDGES;
+    a.ci0 = c->ci0; a.ci1 = c->ci1; a.cj0 = c->cj0; a.cj1 = c->cj1;
+    a.dt = c->dt; a.phi = c->phi; a.grav = c->grav;
+    a.kappa = (R)c->kappa;
+    a.d_in = c->d[in]; a.v_in = c->v[in]; a.d_out = c->d[out]; a.v_out = c->v[out];
+    a.r = (R *)c->r; a.rd = (R *)c->rd;
+    a.hx = (const R *)c->hx; a.hy = (const R *)c->hy;
+    a.mx = c->mx_d; a.my = c->my_d; a.mz = c->mz_d;
+    a.imx = c->imx_d; a.imy = c->imy_d; a.imz = c->imz_d;
+    a.layers = c->layers_d;
+    a.ply = (const PlyC<R> *)c->ply;
+    a.bc_bottom = c->bcb_d;
+    a.fside = c->fside_d;
+    a.partials = c->partials_d;
+    return a;
+}
+
+ContactArgs contact_args(pdn_ctx *c, int buf)
+{
+    ContactArgs a{};
+    a.gl = c->gl_d;
+    a.d = c->d[buf]; a.v = c->v[buf];
+    a.xs = c->xs_d; a.ys = c->ys_d; a.mx = c->mx_d; a.my = c->my_d;
+    a.ztop = c->zk[c->K - 1];
+    a.mztop = c->mz[c->K - 1];
+    a.nx = c->nx; a.ny = c->ny; a.K = c->K;
+    a.clamp_lateral = c->bc == PDN_BC_CLAMPED_EDGES;
+    a.ci0 = c->ci0; a.ci1 = c->ci1; a.cj0 = c->cj0; a.cj1 = c->cj1;
+    a.active = c->active_d; a.vprev = c->vprev_d; a.fcprev = c->fcprev_d; a.fside = c->fside_d;
+    a.partials = c->partials_d; a.nblocks = c->nblocks;
+    a.hist = c->hist_d;
+    a.blk = c->blk_d;
+    return a;
+}
+
+int launch_en(pdn_ctx *c, int in, int out)
+{
+    hipError_t e;
+    if (c->precision == PDN_MIXED) e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out), c->tile, c->stream);
+    else e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out), c->tile, c->stream);
+    if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "element/node kernel launch: %s", hipGetErrorString(e));
+    return PDN_OK;
+}
+
+void set_tiles(pdn_ctx *c)
+{
+    const int TX = pdn_tile_dims[c->tile][0], TY = pdn_tile_dims[c->tile][1];
+    c->tiles_x = std::max(1, (c->nx - 1 + TX - 2) / (TX - 1));
+    c->tiles_y = std::max(1, (c->ny - 1 + TY - 2) / (TY - 1));
+    c->nblocks = c->tiles_x * c->tiles_y;
+}
+
+// restart the explicit scheme from the state in buffer c->cur
+int init_level(pdn_ctx *c, bool reset_contact)
+{
+    const int in = c->cur, out = 1 - c->cur;
+    int rc = launch_en(c, in, out);
+    if (rc) return rc;
+    if (reset_contact) {
+        hipError_t e = pdn::launch_contact_init(contact_args(c, in), 1, c->stream);
+        if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "contact init: %s", hipGetErrorString(e));
+    }
+    c->needs_init = false;
+    return PDN_OK;
+}
+
+void free_all(pdn_ctx *c)
+{
+    void *ps[] = {c->d[0], c->d[1], c->v[0], c->v[1], c->r, c->rd, c->hx, c->hy, c->ply, c->xs_d, c->ys_d,
+                  c->mx_d, c->my_d, c->mz_d, c->imx_d, c->imy_d, c->imz_d, c->blk_d,
+                  c->layers_d, c->bulk_layer_d, c->coh_layer_d, c->bcb_d,
+                  c->active_d, c->vprev_d, c->fcprev_d, c->fside_d, c->partials_d, c->gl_d, c->hist_d, c->dmg_d};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+}
+
+int alloc_contact_window(pdn_ctx *c)
+{
+    // candidate window: top-surface node columns within 1.25 R + one element of the impact point
+    const double x0 = std::isnan(c->imp.x0) ? 0.5 * (c->xs[0] + c->xs[c->nx]) : c->imp.x0;
+    const double y0 = std::isnan(c->imp.y0) ? 0.5 * (c->ys[0] + c->ys[c->ny]) : c->imp.y0;
+    double hmax = 0;
+    for (int i = 0; i < c->nx; ++i) hmax = std::max(hmax, c->xs[i + 1] - c->xs[i]);
+    for (int j = 0; j < c->ny; ++j) hmax = std::max(hmax, c->ys[j + 1] - c->ys[j]);
+    const double Rc = 1.25 * c->imp.radius + hmax;
+    int ci0 = 0, ci1 = c->nx + 1, cj0 = 0, cj1 = c->ny + 1;
+    while (ci0 < c->nx && c->xs[ci0] < x0 - Rc) ++ci0;
+    while (ci1 > ci0 + 1 && c->xs[ci1 - 1] > x0 + Rc) --ci1;
+    while (cj0 < c->ny && c->ys[cj0] < y0 - Rc) ++cj0;
+    while (cj1 > cj0 + 1 && c->ys[cj1 - 1] > y0 + Rc) --cj1;
+    c->ci0 = ci0; c->ci1 = ci1; c->cj0 = cj0; c->cj1 = cj1;
+    const size_t nc = (size_t)(ci1 - ci0) * (cj1 - cj0);
+    int rc;
+    if (c->active_d) { (void)hipFree(c->active_d); (void)hipFree(c->vprev_d); (void)hipFree(c->fcprev_d); (void)hipFree(c->fside_d); (void)hipFree(c->blk_d); }
+    if ((rc = dalloc(c, (void **)&c->active_d, nc))) return rc;
+    if ((rc = dalloc(c, (void **)&c->vprev_d, 3 * nc * sizeof(double)))) return rc;
+    if ((rc = dalloc(c, (void **)&c->fcprev_d, 3 * nc * sizeof(double)))) return rc;
+    if ((rc = dalloc(c, (void **)&c->fside_d, 3 * nc * sizeof(double)))) return rc;
+    HIPCHK(c, hipMemsetAsync(c->active_d, 0, nc, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->fside_d, 0, 3 * nc * sizeof(double), c->stream));
+    {
+        ContactArgs ca{};
+        ca.ci0 = ci0; ca.ci1 = ci1; ca.cj0 = cj0; ca.cj1 = cj1;
+        if ((rc = dalloc(c, (void **)&c->blk_d, (size_t)PDN_CQ * pdn::contact_blocks(ca) * sizeof(double)))) return rc;
+    }
+    return PDN_OK;
+}
+
+int sync_globals_from_device(pdn_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(&c->gl, c->gl_d, sizeof(DevGlobals), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDN_OK;
+}
+
+int push_globals(pdn_ctx *c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->gl_d, &c->gl, sizeof(DevGlobals), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDN_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+
+extern "C" {
+
+int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
+{
+    if (!desc || !out) return PDN_EINVAL;
+    *out = nullptr;
+    const pdn_mesh_desc &D = *desc;
+    if (D.nx < 1 || D.ny < 1 || D.n_plies < 1 || D.n_plies > PDN_MAX_PLIES || D.elems_per_ply < 1 ||
+        !(D.lx > 0) || !(D.ly > 0) || !(D.ply_thickness > 0) || !D.ply_angle_deg ||
+        (D.precision != PDN_FP64 && D.precision != PDN_MIXED) || D.bc < 0 || D.bc > 2 ||
+        !(D.cfl_safety > 0) || !(D.phi >= 1.0) || D.hourglass_kappa < 0)
+        return PDN_EINVAL;
+    pdn_ctx *c = new pdn_ctx();
+    c->device = D.device;
+    c->nx = D.nx; c->ny = D.ny; c->P = D.n_plies; c->epp = D.elems_per_ply;
+    c->cohesive = D.cohesive; c->bc = D.bc; c->precision = D.precision;
+    c->lx = D.lx; c->ly = D.ly; c->tply = D.ply_thickness; c->phi = D.phi; c->safety = D.cfl_safety;
+    c->grav = D.gravity; c->kappa = D.hourglass_kappa;
+    c->wlx = D.window_lx; c->wly = D.window_ly; c->clamp_r = D.clamp_radius;
+    c->ang.assign(D.ply_angle_deg, D.ply_angle_deg + D.n_plies);
+    c->mat.assign(c->P, pdn_material{});
+    c->mat_set.assign(c->P, 0);
+    // grid lines
+    c->xs.resize(c->nx + 1);
+    c->ys.resize(c->ny + 1);
+    for (int i = 0; i <= c->nx; ++i) c->xs[i] = D.x_coords ? D.x_coords[i] : D.lx * i / D.nx;
+    for (int j = 0; j <= c->ny; ++j) c->ys[j] = D.y_coords ? D.y_coords[j] : D.ly * j / D.ny;
+    for (int i = 0; i < c->nx; ++i)
+        if (!(c->xs[i + 1] > c->xs[i])) { delete c; return PDN_EINVAL; }
+    for (int j = 0; j < c->ny; ++j)
+        if (!(c->ys[j + 1] > c->ys[j])) { delete c; return PDN_EINVAL; }
+    // layers: plies split into elements, interfaces where the angle changes
+    const double hz = D.ply_thickness / D.elems_per_ply;
+    int nb = 0, ncl = 0;
+    for (int p = 0; p < c->P; ++p) {
+        for (int e = 0; e < c->epp; ++e) {
+            c->layers.push_back(LayerInfo{0, p, nb++, 0, hz});
+            c->bulk_layer.push_back((int)c->layers.size() - 1);
+        }
+        if (p + 1 < c->P && c->cohesive && c->ang[p] != c->ang[p + 1]) {
+            c->layers.push_back(LayerInfo{1, p, ncl++, 0, 0.0});
+            c->coh_layer.push_back((int)c->layers.size() - 1);
+        }
+    }
+    c->NL = (int)c->layers.size();
+    c->K = c->NL + 1;
+    c->zk.assign(c->K, 0.0);
+    for (int l = 0; l < c->NL; ++l) c->zk[l + 1] = c->zk[l] + c->layers[l].hz;
+    c->plane = (int64_t)(c->nx + 1) * (c->ny + 1);
+    c->nn = c->plane * c->K;
+    c->ne = (int64_t)c->nx * c->ny * nb;
+    c->nce = (int64_t)c->nx * c->ny * ncl;
+    c->npairs = c->plane * ncl;
+    // supports of the bottom plane
+    c->bcb.assign(c->plane, 0);
+    if (c->bc == PDN_BC_ASTM_WINDOW) {
+        const int ilo = window_index(c->nx, c->xs[c->nx] - c->xs[0], D.window_lx), ihi = c->nx - ilo;
+        const int jlo = window_index(c->ny, c->ys[c->ny] - c->ys[0], D.window_ly), jhi = c->ny - jlo;
+        const double r2 = D.clamp_radius * D.clamp_radius * (1.0 + 1e-9);
+        for (int j = 0; j <= c->ny; ++j)
+            for (int i = 0; i <= c->nx; ++i) {
+                uint8_t b = 0;
+                if (((i == ilo || i == ihi) && j >= jlo && j <= jhi) || ((j == jlo || j == jhi) && i >= ilo && i <= ihi)) b |= 4;
+                const int ci[2] = {ilo, ihi}, cj[2] = {jlo, jhi};
+                for (int a = 0; a < 2; ++a)
+                    for (int q = 0; q < 2; ++q) {
+                        const double dx = c->xs[i] - c->xs[ci[a]], dy = c->ys[j] - c->ys[cj[q]];
+                        if (dx * dx + dy * dy <= r2) b = 7;
+                    }
+                c->bcb[i + (int64_t)(c->nx + 1) * j] = b;
+            }
+    }
+    // device
+    hipError_t he = hipSetDevice(c->device);
+    if (he != hipSuccess) { set_err(c, PDN_EDEVICE, "hipSetDevice: %s", hipGetErrorString(he)); delete c; return PDN_EDEVICE; }
+    if (D.stream) c->stream = (hipStream_t)D.stream;
+    else {
+        he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (he != hipSuccess) { delete c; return PDN_EDEVICE; }
+        c->own_stream = true;
+    }
+    set_tiles(c);
+    int rc = PDN_OK;
+    const size_t rs = rsize(c);
+    for (int b = 0; b < 2 && !rc; ++b) {
+        rc = dalloc(c, (void **)&c->d[b], 3 * c->nn * sizeof(double));
+        if (!rc) rc = dalloc(c, (void **)&c->v[b], 3 * c->nn * sizeof(double));
+    }
+    if (!rc) rc = dalloc(c, &c->r, 4 * c->ne * rs);
+    if (!rc) rc = dalloc(c, &c->rd, c->npairs * rs);
+    if (!rc) rc = dalloc(c, &c->hx, c->nx * rs);
+    if (!rc) rc = dalloc(c, &c->hy, c->ny * rs);
+    if (!rc) rc = dalloc(c, &c->ply, c->P * std::max(sizeof(PlyC<float>), sizeof(PlyC<double>)));
+    if (!rc) rc = dalloc(c, (void **)&c->xs_d, (c->nx + 1) * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->ys_d, (c->ny + 1) * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->mx_d, (c->nx + 1) * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->my_d, (c->ny + 1) * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->mz_d, c->K * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->imx_d, (c->nx + 1) * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->imy_d, (c->ny + 1) * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->imz_d, c->K * sizeof(double));
+    if (!rc) rc = dalloc(c, (void **)&c->layers_d, c->NL * sizeof(LayerInfo));
+    if (!rc) rc = dalloc(c, (void **)&c->bulk_layer_d, std::max<size_t>(1, c->bulk_layer.size()) * sizeof(int));
+    if (!rc) rc = dalloc(c, (void **)&c->coh_layer_d, std::max<size_t>(1, c->coh_layer.size()) * sizeof(int));
+    if (!rc) rc = dalloc(c, (void **)&c->bcb_d, c->plane);
+    if (!rc) rc = dalloc(c, (void **)&c->gl_d, sizeof(DevGlobals));
+    if (!rc) rc = dalloc(c, (void **)&c->partials_d, (size_t)PDN_NTERMS * std::max(1, c->nblocks) * sizeof(double));
+    if (rc) { free_all(c); if (c->own_stream) (void)hipStreamDestroy(c->stream); delete c; return rc; }
+    // tables
+    std::vector<double> hxv(c->nx), hyv(c->ny);
+    for (int i = 0; i < c->nx; ++i) hxv[i] = c->xs[i + 1] - c->xs[i];
+    for (int j = 0; j < c->ny; ++j) hyv[j] = c->ys[j + 1] - c->ys[j];
+    if (c->precision == PDN_MIXED) {
+        std::vector<float> a(hxv.begin(), hxv.end()), b(hyv.begin(), hyv.end());
+        rc = upload(c, (float *)c->hx, a);
+        if (!rc) rc = upload(c, (float *)c->hy, b);
+        if (!rc) rc = hipStreamSynchronize(c->stream) == hipSuccess ? PDN_OK : PDN_EDEVICE;
+    } else {
+        rc = upload(c, (double *)c->hx, hxv);
+        if (!rc) rc = upload(c, (double *)c->hy, hyv);
+    }
+    if (!rc) rc = upload(c, c->xs_d, c->xs);
+    if (!rc) rc = upload(c, c->ys_d, c->ys);
+    if (!rc) rc = upload(c, c->layers_d, c->layers);
+    if (!rc) rc = upload(c, c->bulk_layer_d, c->bulk_layer);
+    if (!rc) rc = upload(c, c->coh_layer_d, c->coh_layer);
+    if (!rc) rc = upload(c, c->bcb_d, c->bcb);
+    // zero state, thresholds r = 1 (Algorithm 4 initial state), r_D = 0
+    if (!rc) {
+        for (int b = 0; b < 2; ++b) {
+            (void)hipMemsetAsync(c->d[b], 0, 3 * c->nn * sizeof(double), c->stream);
+            (void)hipMemsetAsync(c->v[b], 0, 3 * c->nn * sizeof(double), c->stream);
+        }
+        (void)hipMemsetAsync(c->rd, 0, std::max<int64_t>(1, c->npairs) * rs, c->stream);
+        if (c->ne > 0) {
+            if (c->precision == PDN_MIXED) {
+                std::vector<float> ones(4 * c->ne, 1.0f);
+                rc = upload(c, (float *)c->r, ones);
+                if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = PDN_EDEVICE;
+            } else {
+                std::vector<double> ones(4 * c->ne, 1.0);
+                rc = upload(c, (double *)c->r, ones);
+                if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = PDN_EDEVICE;
+            }
+        }
+    }
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = set_err(c, PDN_EDEVICE, "mesh upload failed");
+    if (rc) { free_all(c); if (c->own_stream) (void)hipStreamDestroy(c->stream); delete c; return rc; }
+    *out = c;
+    return PDN_OK;
+}
+
+int pdn_material_set(pdn_ctx *c, int32_t ply, const pdn_material *m)
+{
+    if (!c || !m) return PDN_EINVAL;
+    if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
+    if (ply < -1 || ply >= c->P) return set_err(c, PDN_EINVAL, "ply index %d out of range", ply);
+    if (!(m->E1 > 0 && m->E2 > 0 && m->E3 > 0 && m->G12 > 0 && m->G13 > 0 && m->G23 > 0 && m->rho > 0))
+        return set_err(c, PDN_EINVAL, "elastic constants and density must be positive");
+    if (m->law < 0 || m->law > 2) return set_err(c, PDN_EINVAL, "unknown law %d", m->law);
+    if (m->law != PDN_LAW_ELASTIC) {
+        if (!(m->XT > 0 && m->XC > 0 && m->YT > 0 && m->YC > 0 && m->SL > 0 && m->GXT > 0 && m->GXC > 0 &&
+              m->GYT > 0 && m->GYC > 0 && m->GSL > 0 && m->fXT > 0 && m->fXC > 0 && m->fGT > 0 && m->fGC > 0 &&
+              m->fGT < 1 && m->fGC < 1))
+            return set_err(c, PDN_EINVAL, "damage law needs positive strengths, toughness and shape factors");
+        // fibre bilinear softening must stay ordered at the largest crack band of the ply
+        double hxm = 0, hym = 0;
+        for (int i = 0; i < c->nx; ++i) hxm = std::max(hxm, c->xs[i + 1] - c->xs[i]);
+        for (int j = 0; j < c->ny; ++j) hym = std::max(hym, c->ys[j + 1] - c->ys[j]);
+        const double lc = std::cbrt(hxm * hym * c->tply / c->epp);
+        const double X[2] = {m->XT, m->XC}, G[2] = {m->GXT, m->GXC}, fx[2] = {m->fXT, m->fXC}, fg[2] = {m->fGT, m->fGC};
+        for (int k = 0; k < 2; ++k) {
+            double e0 = X[k] / m->E1, g = G[k] / lc;
+            double eB = 2 * fg[k] * g / X[k] + fx[k] * e0, eC = 2 * (1 - fg[k]) * g / (fx[k] * X[k]);
+            if (!(eB > e0 && eC > eB)) return set_err(c, PDN_EINVAL, "fibre softening not ordered at element size");
+        }
+    }
+    if (c->cohesive && m->KI < 0) return set_err(c, PDN_EINVAL, "interface penalty must be positive");
+    for (int p = 0; p < c->P; ++p)
+        if (ply < 0 || p == ply) { c->mat[p] = *m; c->mat_set[p] = 1; }
+    c->ready = false;
+    if (c->gl.step > 0) c->needs_init = true;
+    return PDN_OK;
+}
+
+int pdn_impactor_set(pdn_ctx *c, const pdn_impactor *imp)
+{
+    if (!c || !imp) return PDN_EINVAL;
+    if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
+    if (!(imp->radius > 0 && imp->mass > 0 && imp->gap >= 0)) return set_err(c, PDN_EINVAL, "bad striker");
+    if (!all_set(c)) return set_err(c, PDN_ESTATE, "set the materials of every ply first");
+    (void)hipSetDevice(c->device);
+    const double v0 = imp->energy > 0 ? std::sqrt(2.0 * imp->energy / imp->mass) : imp->v0;
+    if (!c->have_imp || c->gl.step == 0) {
+        c->imp = *imp;
+        c->have_imp = true;
+        int rc = alloc_contact_window(c);
+        if (rc) return rc;
+        DevGlobals &G = c->gl;
+        std::memset(&G, 0, sizeof G);
+        const double x0 = std::isnan(imp->x0) ? 0.5 * (c->xs[0] + c->xs[c->nx]) : imp->x0;
+        const double y0 = std::isnan(imp->y0) ? 0.5 * (c->ys[0] + c->ys[c->ny]) : imp->y0;
+        G.c0[0] = x0; G.c0[1] = y0; G.c0[2] = c->zk[c->K - 1] + imp->radius + imp->gap;
+        std::memcpy(G.c, G.c0, sizeof G.c);
+        G.V[2] = -v0;
+        G.ms = imp->mass; G.R = imp->radius; G.g = c->grav; G.phi = c->phi;
+        G.first = 1;
+        G.ke0 = 0.5 * imp->mass * v0 * v0;
+        G.e_kes = G.ke0;
+        G.hist_cap = c->hist_cap;
+        c->v0 = v0;
+        c->needs_init = true;
+        c->loaded_state = false;
+        return PDN_OK;
+    }
+    // mid-run: only the velocity changes
+    int rc = sync_globals_from_device(c);
+    if (rc) return rc;
+    c->gl.V[0] = 0; c->gl.V[1] = 0; c->gl.V[2] = -v0;
+    return push_globals(c);
+}
+
+int pdn_step(pdn_ctx *c, int64_t n)
+{
+    if (!c || n < 0) return PDN_EINVAL;
+    if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
+    if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "materials and striker must be set first");
+    (void)hipSetDevice(c->device);
+    int rc;
+    if (!c->ready) {
+        if ((rc = prepare(c))) return rc;
+        c->gl.dt = c->dt;
+        if (c->gl.step == 0 && !c->loaded_state) {
+            if ((rc = push_globals(c))) return rc;
+        } else {
+            // material changed mid-run: keep the device books, refresh dt
+            if ((rc = sync_globals_from_device(c))) return rc;
+            c->gl.dt = c->dt;
+            if ((rc = push_globals(c))) return rc;
+        }
+    }
+    if (c->needs_init) {
+        const bool reset_contact = !c->loaded_state;
+        if ((rc = init_level(c, reset_contact))) return rc;
+        c->loaded_state = false;
+    }
+    if ((rc = ensure_history(c, c->gl.step + n))) return rc;
+    std::vector<hipEvent_t> ev;
+    if (c->timing && n > 0) {
+        ev.resize(3 * n);
+        for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    }
+    for (int64_t s = 0; s < n; ++s) {
+        const int pred = 1 - c->cur;
+        if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s], c->stream));
+        hipError_t e = pdn::launch_contact(contact_args(c, pred), c->stream);
+        if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "contact kernel launch: %s", hipGetErrorString(e));
+        if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s + 1], c->stream));
+        if ((rc = launch_en(c, pred, c->cur))) return rc;
+        if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s + 2], c->stream));
+        c->cur = pred;
+    }
+    if ((rc = sync_globals_from_device(c))) return rc;
+    if (c->timing && n > 0) {
+        double a = 0, b = 0;
+        for (int64_t s = 0; s < n; ++s) {
+            float t1 = 0, t2 = 0;
+            HIPCHK(c, hipEventElapsedTime(&t1, ev[3 * s], ev[3 * s + 1]));
+            HIPCHK(c, hipEventElapsedTime(&t2, ev[3 * s + 1], ev[3 * s + 2]));
+            b += t1;
+            a += t2;
+        }
+        for (auto &e : ev) (void)hipEventDestroy(e);
+        c->t_en_ms = a / n;
+        c->t_ct_ms = b / n;
+    }
+    if (c->gl.flag_unstable) {
+        c->broken = true;
+        return set_err(c, PDN_EUNSTABLE, "non-finite displacement at step %lld", (long long)c->gl.step);
+    }
+    if (c->gl.flag_overflow)
+        return set_err(c, PDN_ERANGE, "contact reached the edge of the contact search window");
+    return PDN_OK;
+}
+
+int pdn_contact_force(const pdn_ctx *c, double *t, double *force, double *disp, int64_t cap, int64_t *n_out)
+{
+    if (!c) return PDN_EINVAL;
+    pdn_ctx *m = const_cast<pdn_ctx *>(c);
+    const int64_t n = c->gl.step;
+    if (n_out) *n_out = n;
+    if (cap < n) return set_err(m, PDN_ERANGE, "history needs %lld entries", (long long)n);
+    if (n == 0) return PDN_OK;
+    (void)hipSetDevice(c->device);
+    std::vector<double> h(3 * n);
+    HIPCHK(m, hipMemcpyAsync(h.data(), c->hist_d, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(m, hipStreamSynchronize(c->stream));
+    for (int64_t i = 0; i < n; ++i) {
+        if (t) t[i] = h[3 * i];
+        if (force) force[i] = h[3 * i + 1];
+        if (disp) disp[i] = h[3 * i + 2];
+    }
+    return PDN_OK;
+}
+
+int pdn_damage_field(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int64_t *n_out)
+{
+    if (!cc || kind < 0 || kind > 6) return PDN_EINVAL;
+    pdn_ctx *c = const_cast<pdn_ctx *>(cc);
+    const bool proj = kind >= PDN_DMG_PROJ_FIBRE;
+    const int base = proj ? kind - 4 : kind;
+    const int64_t ncol = (int64_t)c->nx * c->ny;
+    const int64_t nelem = base == PDN_DMG_COHESIVE ? c->nce : c->ne;
+    const int64_t n = proj ? ncol : nelem;
+    if (n_out) *n_out = n;
+    if (cap < n) return set_err(c, PDN_ERANGE, "damage field needs %lld values", (long long)n);
+    if (n == 0) return PDN_OK;
+    if (!c->ready) {
+        for (int64_t i = 0; i < n; ++i) out[i] = 0;
+        return PDN_OK;
+    }
+    (void)hipSetDevice(c->device);
+    const size_t need = (size_t)(nelem + ncol);
+    if (c->dmg_n < need) {
+        if (c->dmg_d) (void)hipFree(c->dmg_d);
+        c->dmg_d = nullptr;
+        int rc = dalloc(c, (void **)&c->dmg_d, need * sizeof(double));
+        if (rc) return rc;
+        c->dmg_n = need;
+    }
+    hipError_t e;
+    if (base == PDN_DMG_COHESIVE) {
+        if (c->precision == PDN_MIXED)
+            e = pdn::launch_damage_coh<float>((const float *)c->rd, c->d[c->cur], c->layers_d, c->coh_layer_d,
+                                              (const PlyC<float> *)c->ply, c->nx, c->ny, nelem, c->dmg_d, c->stream);
+        else
+            e = pdn::launch_damage_coh<double>((const double *)c->rd, c->d[c->cur], c->layers_d, c->coh_layer_d,
+                                               (const PlyC<double> *)c->ply, c->nx, c->ny, nelem, c->dmg_d, c->stream);
+    } else {
+        if (c->precision == PDN_MIXED)
+            e = pdn::launch_damage_bulk<float>((const float *)c->r, c->layers_d, c->bulk_layer_d,
+                                               (const PlyC<float> *)c->ply, (const float *)c->hx,
+                                               (const float *)c->hy, c->nx, c->ny, nelem, base, c->dmg_d, c->stream);
+        else
+            e = pdn::launch_damage_bulk<double>((const double *)c->r, c->layers_d, c->bulk_layer_d,
+                                                (const PlyC<double> *)c->ply, (const double *)c->hx,
+                                                (const double *)c->hy, c->nx, c->ny, nelem, base, c->dmg_d, c->stream);
+    }
+    if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "damage kernel: %s", hipGetErrorString(e));
+    const double *src = c->dmg_d;
+    if (proj) {
+        const int nl = (int)(nelem / std::max<int64_t>(1, ncol));
+        e = pdn::launch_project_max(c->dmg_d, ncol, nl, c->dmg_d + nelem, c->stream);
+        if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "projection kernel: %s", hipGetErrorString(e));
+        src = c->dmg_d + nelem;
+    }
+    HIPCHK(c, hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDN_OK;
+}
+
+int pdn_energies(const pdn_ctx *c, pdn_energy *o)
+{
+    if (!c || !o) return PDN_EINVAL;
+    const DevGlobals &G = c->gl;
+    o->level = G.e_level;
+    o->ke_plate = G.e_kep;
+    o->ke_striker = G.e_kes;
+    o->w_int = G.e_wint;
+    o->w_grav = G.e_wgp + G.e_wgs;
+    o->w_contact_plate = G.e_wc;
+    o->w_striker = G.e_ws;
+    o->d_pdn = G.e_ws - G.e_wc;
+    o->ke0 = G.ke0;
+    o->u_el = G.e_uel;
+    o->residual = o->ke_plate + o->ke_striker + o->w_int + o->d_pdn - (o->ke0 + o->w_grav);
+    return PDN_OK;
+}
+
+int pdn_info_get(const pdn_ctx *c, pdn_info *o)
+{
+    if (!c || !o) return PDN_EINVAL;
+    std::memset(o, 0, sizeof *o);
+    o->dt = c->dt;
+    o->n_nodes = c->nn; o->n_bulk = c->ne; o->n_cohesive = c->nce; o->n_pairs = c->npairs;
+    o->n_planes = c->K; o->n_layers = c->NL;
+    o->n_candidates = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
+    o->steps = c->gl.step; o->reset_passes = c->gl.reset_passes; o->released = c->gl.released;
+    o->active = c->gl.active; o->max_passes = c->gl.max_passes;
+    o->fallback_fraction = (c->gl.step > 0 && c->ne > 0) ? c->gl.fallback_gp / ((double)c->gl.step * c->ne) : 0.0;
+    o->precision = c->precision;
+    o->tile_x = pdn_tile_dims[c->tile][0];
+    o->tile_y = pdn_tile_dims[c->tile][1];
+    o->blocks = c->nblocks;
+    return PDN_OK;
+}
+
+int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int64_t *n_out)
+{
+    if (!cc) return PDN_EINVAL;
+    pdn_ctx *c = const_cast<pdn_ctx *>(cc);
+    int64_t n;
+    switch (kind) {
+    case PDN_ARR_DISP: case PDN_ARR_VEL: n = 3 * c->nn; break;
+    case PDN_ARR_GP_R: n = 4 * c->ne; break;
+    case PDN_ARR_COH_R: n = c->npairs; break;
+    case PDN_ARR_MASS: n = c->nn; break;
+    default: return set_err(c, PDN_EINVAL, "unknown array kind %d", kind);
+    }
+    if (n_out) *n_out = n;
+    if (cap < n) return set_err(c, PDN_ERANGE, "array needs %lld values", (long long)n);
+    if (n == 0) return PDN_OK;
+    (void)hipSetDevice(c->device);
+    if (kind == PDN_ARR_MASS) {
+        if (!c->ready) return set_err(c, PDN_ESTATE, "mass is known after the first step");
+        for (int k = 0; k < c->K; ++k)
+            for (int j = 0; j <= c->ny; ++j)
+                for (int i = 0; i <= c->nx; ++i)
+                    out[i + (int64_t)(c->nx + 1) * (j + (int64_t)(c->ny + 1) * k)] = c->mx[i] * c->my[j] * c->mz[k];
+        return PDN_OK;
+    }
+    if (kind == PDN_ARR_DISP || kind == PDN_ARR_VEL) {
+        const double *src = kind == PDN_ARR_DISP ? c->d[c->cur] : c->v[c->cur];
+        HIPCHK(c, hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return PDN_OK;
+    }
+    const void *src = kind == PDN_ARR_GP_R ? c->r : c->rd;
+    if (c->precision == PDN_MIXED) {
+        std::vector<float> tmp(n);
+        HIPCHK(c, hipMemcpyAsync(tmp.data(), src, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int64_t i = 0; i < n; ++i) out[i] = tmp[i];
+    } else {
+        HIPCHK(c, hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return PDN_OK;
+}
+
+int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
+{
+    if (!c || !in) return PDN_EINVAL;
+    if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
+    int64_t need;
+    switch (kind) {
+    case PDN_ARR_DISP: case PDN_ARR_VEL: need = 3 * c->nn; break;
+    case PDN_ARR_GP_R: need = 4 * c->ne; break;
+    case PDN_ARR_COH_R: need = c->npairs; break;
+    default: return set_err(c, PDN_EINVAL, "array kind %d cannot be set", kind);
+    }
+    if (n != need) return set_err(c, PDN_EINVAL, "array needs %lld values, got %lld", (long long)need, (long long)n);
+    (void)hipSetDevice(c->device);
+    if (kind == PDN_ARR_DISP || kind == PDN_ARR_VEL) {
+        // supported DOFs stay at rest
+        std::vector<double> tmp(in, in + n);
+        for (int k = 0; k < c->K; ++k)
+            for (int j = 0; j <= c->ny; ++j)
+                for (int i = 0; i <= c->nx; ++i) {
+                    const int64_t col = i + (int64_t)(c->nx + 1) * j, nd = col + c->plane * k;
+                    int bits = (c->bc == PDN_BC_CLAMPED_EDGES && (i == 0 || i == c->nx || j == 0 || j == c->ny)) ? 7 : 0;
+                    if (k == 0) bits |= c->bcb[col];
+                    for (int q = 0; q < 3; ++q)
+                        if ((bits >> q) & 1) tmp[3 * nd + q] = 0.0;
+                }
+        double *dst = kind == PDN_ARR_DISP ? c->d[c->cur] : c->v[c->cur];
+        HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        void *dst = kind == PDN_ARR_GP_R ? c->r : c->rd;
+        if (c->precision == PDN_MIXED) {
+            std::vector<float> tmp(in, in + n);
+            HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        } else {
+            HIPCHK(c, hipMemcpyAsync(dst, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
+    c->needs_init = true;
+    c->loaded_state = false;
+    // the books restart from this state
+    if (c->have_imp) {
+        int rc = c->gl.step > 0 ? sync_globals_from_device(c) : PDN_OK;
+        if (rc) return rc;
+        DevGlobals &G = c->gl;
+        G.first = 1;
+        G.e_wint = G.e_wgp = G.e_wc = G.half_int = 0;
+        if (c->ready) return push_globals(c);
+    }
+    return PDN_OK;
+}
+
+// ---- checkpoint ----------------------------------------------------------
+namespace {
+struct BlobHeader {
+    uint64_t magic;
+    int64_t nn, ne, npairs, ncand, hist_n;
+    int32_t precision, cur;
+};
+const uint64_t kMagic = 0x31304b4350444e50ull;   // "PNDPCK01"
+}  // namespace
+
+int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
+{
+    if (!cc) return PDN_EINVAL;
+    pdn_ctx *c = const_cast<pdn_ctx *>(cc);
+    if (!c->ready || c->needs_init) return set_err(c, PDN_ESTATE, "checkpoint needs at least one completed step");
+    const size_t rs = rsize(c);
+    const int64_t ncand = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
+    const int64_t hn = c->gl.step;
+    const size_t need = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) + 4 * c->ne * rs +
+                        c->npairs * rs + ncand * (1 + 6 * sizeof(double)) + 3 * hn * sizeof(double);
+    if (n_out) *n_out = (int64_t)need;
+    if (cap < (int64_t)need || !buf) return set_err(c, PDN_ERANGE, "checkpoint needs %zu bytes", need);
+    (void)hipSetDevice(c->device);
+    int rc = sync_globals_from_device(c);
+    if (rc) return rc;
+    char *p = (char *)buf;
+    BlobHeader h{kMagic, c->nn, c->ne, c->npairs, ncand, hn, c->precision, 0};
+    std::memcpy(p, &h, sizeof h); p += sizeof h;
+    std::memcpy(p, &c->gl, sizeof(DevGlobals)); p += sizeof(DevGlobals);
+    auto d2h = [&](const void *src, size_t bytes) -> int {
+        if (bytes == 0) return PDN_OK;
+        HIPCHK(c, hipMemcpyAsync(p, src, bytes, hipMemcpyDeviceToHost, c->stream));
+        p += bytes;
+        return PDN_OK;
+    };
+    if ((rc = d2h(c->d[c->cur], 3 * c->nn * sizeof(double)))) return rc;
+    if ((rc = d2h(c->v[c->cur], 3 * c->nn * sizeof(double)))) return rc;
+    if ((rc = d2h(c->r, 4 * c->ne * rs))) return rc;
+    if ((rc = d2h(c->rd, c->npairs * rs))) return rc;
+    if ((rc = d2h(c->active_d, ncand))) return rc;
+    if ((rc = d2h(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
+    if ((rc = d2h(c->fcprev_d, 3 * ncand * sizeof(double)))) return rc;
+    if ((rc = d2h(c->hist_d, 3 * hn * sizeof(double)))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return PDN_OK;
+}
+
+int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
+{
+    if (!c || !buf) return PDN_EINVAL;
+    if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "set materials and striker before loading");
+    const char *p = (const char *)buf;
+    if (n < (int64_t)sizeof(BlobHeader)) return set_err(c, PDN_EINVAL, "checkpoint too short");
+    BlobHeader h;
+    std::memcpy(&h, p, sizeof h); p += sizeof h;
+    const int64_t ncand = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
+    if (h.magic != kMagic || h.nn != c->nn || h.ne != c->ne || h.npairs != c->npairs || h.ncand != ncand ||
+        h.precision != c->precision)
+        return set_err(c, PDN_EINVAL, "checkpoint does not match this context");
+    (void)hipSetDevice(c->device);
+    int rc;
+    if (!c->ready && (rc = prepare(c))) return rc;
+    if ((rc = ensure_history(c, h.hist_n + 1))) return rc;
+    std::memcpy(&c->gl, p, sizeof(DevGlobals)); p += sizeof(DevGlobals);
+    c->gl.hist_cap = c->hist_cap;
+    const size_t rs = rsize(c);
+    auto h2d = [&](void *dst, size_t bytes) -> int {
+        if (bytes == 0) return PDN_OK;
+        HIPCHK(c, hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, c->stream));
+        p += bytes;
+        return PDN_OK;
+    };
+    c->cur = 0;
+    if ((rc = h2d(c->d[0], 3 * c->nn * sizeof(double)))) return rc;
+    if ((rc = h2d(c->v[0], 3 * c->nn * sizeof(double)))) return rc;
+    if ((rc = h2d(c->r, 4 * c->ne * rs))) return rc;
+    if ((rc = h2d(c->rd, c->npairs * rs))) return rc;
+    if ((rc = h2d(c->active_d, ncand))) return rc;
+    if ((rc = h2d(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
+    if ((rc = h2d(c->fcprev_d, 3 * ncand * sizeof(double)))) return rc;
+    if ((rc = h2d(c->hist_d, 3 * h.hist_n * sizeof(double)))) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if ((rc = push_globals(c))) return rc;
+    c->needs_init = true;
+    c->loaded_state = true;
+    return PDN_OK;
+}
+
+int pdn_set_tile(pdn_ctx *c, int32_t tx, int32_t ty)
+{
+    if (!c) return PDN_EINVAL;
+    int t = -1;
+    if (tx == 0 && ty == 0) t = PDN_TILE_16x16;
+    for (int k = 0; k < PDN_TILE_COUNT; ++k)
+        if (pdn_tile_dims[k][0] == tx && pdn_tile_dims[k][1] == ty) t = k;
+    if (t < 0) return set_err(c, PDN_EINVAL, "unsupported tile %dx%d", tx, ty);
+    const int old = c->nblocks;
+    c->tile = t;
+    set_tiles(c);
+    if (c->nblocks > old) {
+        (void)hipFree(c->partials_d);
+        c->partials_d = nullptr;
+        int rc = dalloc(c, (void **)&c->partials_d, (size_t)PDN_NTERMS * c->nblocks * sizeof(double));
+        if (rc) return rc;
+    }
+    // the contact kernel reduces the partials of the previous element pass:
+    // recompute them in the new block layout, keeping the contact state
+    if (!c->needs_init) {
+        c->needs_init = true;
+        c->loaded_state = true;
+    }
+    return PDN_OK;
+}
+
+int pdn_kernel_times(const pdn_ctx *c, double *en, double *ct)
+{
+    if (!c) return PDN_EINVAL;
+    if (en) *en = c->t_en_ms;
+    if (ct) *ct = c->t_ct_ms;
+    return PDN_OK;
+}
+
+int pdn_set_timing(pdn_ctx *c, int32_t on)
+{
+    if (!c) return PDN_EINVAL;
+    c->timing = on != 0;
+    return PDN_OK;
+}
+
+const char *pdn_last_error(const pdn_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+void pdn_destroy(pdn_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

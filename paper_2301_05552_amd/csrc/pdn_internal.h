@@ -1,0 +1,109 @@
+// pdn_internal.h -- device-side data layout of libpdn (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PDN_MAX_PLIES 64
+#define PDN_MAX_LAYERS (3 * PDN_MAX_PLIES)
+#define PDN_K1_THREADS 256
+#define PDN_NTERMS 6          // per-block energy partials of the element/node kernel
+// partial slots: 0.5 m v^n.v~^{n+1}, 0.5 dt v^n.f^n, 0.5 dt v~^{n+1}.f^n,
+// sum m d_z^n, secant energy, surrogate exact-law count
+enum { T_KE = 0, T_WA = 1, T_WB = 2, T_MZ = 3, T_UEL = 4, T_AUX = 5 };
+
+// Per-ply constants in the arithmetic type R of the element kernel.
+template <typename R>
+struct PlyC {
+    R C11, C12, C13, C22, C23, C33, G23, G13, G12;   // undamaged material-frame stiffness
+    R iE1, iE2, iE3, mn12, mn13, mn23;               // compliance: 1/E_i and -nu_ij/E_i
+    R c, s;                                          // fibre angle about Z
+    R cmax;                                          // largest stiffness entry (hourglass, dt)
+    R E1, E2, G12v;
+    R XT, XC, YT, YC, SL;
+    R GXT, GXC, GYT, GYC, GSL;
+    R fXT, fGT, fXC, fGC;
+    R sa0, ca0, kST, etaT, kEtaL;                    // fracture-plane (alpha0) constants
+    R rho;
+    int law;
+    // screening constants (uncapped strengths): reciprocals and bounds
+    R kE1XT, kE1XC;                                  // E1/XT, E1/XC
+    R iYT, iYC, iSL, iST;                            // 1/YT, 1/YC, 1/SL, 1/ST
+    R etaL0;                                         // eta_L with uncapped strengths
+    R kT;                                            // ca0 (sa0 + |etaT| ca0): bound of tau_T^eff / -s22
+    R vol_nocap;                                     // element volume below which no strength is capped
+    // interface on top of this ply
+    R KI, Ksh, tauI, GIc, GIIc, eta_bk, GIo;
+};
+
+// Layer table: layer l joins node planes l and l+1.
+struct LayerInfo {
+    int type;      // 0 bulk, 1 cohesive
+    int ply;       // ply (bulk) or ply below (cohesive)
+    int index;     // bulk layer index or interface index
+    int pad;
+    double hz;     // bulk layer thickness (0 for cohesive)
+};
+
+// Scalars owned by the contact kernel (striker, books, counters).
+struct DevGlobals {
+    double c[3], V[3], c0[3];
+    double Fprev[3];                 // contact force on the plate found in the last step
+    double ms, R, g, dt, phi;
+    int64_t step;                    // completed steps
+    int64_t hist_cap;
+    int32_t first;                   // first contact pass after (re)initialisation
+    int32_t flag_unstable, flag_overflow, pad0;
+    // energy books at the last complete level
+    double e_level, e_kep, e_kes, e_wint, e_wgp, e_wgs, e_wc, e_ws, e_uel, ke0;
+    double half_int, mz0;            // opening half of the current interval; initial sum m d_z
+    double ws_acc, wgs_acc;          // striker works up to the current striker level
+    int64_t reset_passes, released, max_passes, active;
+    double fallback_gp;              // surrogate: GP updates that used the exact law
+    unsigned int ticket;             // contact-kernel workgroups finished (last one reduces)
+    unsigned int pad1;
+};
+
+#define PDN_CQ 18                    // per-workgroup results of the contact kernel
+
+// Everything the element/node kernel needs, passed by value.
+template <typename R>
+struct ElemArgs {
+    int nx, ny, K, NL;
+    int tiles_x, tiles_y;
+    int clamp_lateral;
+    int ci0, ci1, cj0, cj1;          // contact candidate window (node columns, half-open)
+    double dt, phi, grav;
+    R kappa;
+    const double *d_in, *v_in;       // state at level n (AoS xyz)
+    double *d_out, *v_out;           // predictor for level n+1
+    R *r;                            // 4 per bulk GP
+    R *rd;                           // 1 per cohesive node pair
+    const R *hx, *hy;                // element sizes (nx, ny)
+    const double *mx, *my, *mz;      // separable lumped-mass factors (nx+1, ny+1, K)
+    const double *imx, *imy, *imz;   // their reciprocals
+    const LayerInfo *layers;         // NL
+    const PlyC<R> *ply;              // n_plies
+    const uint8_t *bc_bottom;        // (nx+1)(ny+1) fixed-DOF bits of plane 0
+    double *fside;                   // 3 per candidate: internal force at level n
+    double *partials;                // PDN_NTERMS per block
+    // surrogate (optional)
+    const float *mlp;                // packed weights or null
+    float sur_dmg, sur_res;
+    unsigned long long *sur_counts;  // [exact, total]
+};
+
+struct ContactArgs {
+    DevGlobals *gl;
+    double *d, *v;                   // predictor buffer, corrected in place
+    const double *xs, *ys, *mx, *my; // grid lines and mass factors
+    double ztop, mztop;
+    int nx, ny, K, clamp_lateral;
+    int ci0, ci1, cj0, cj1;
+    uint8_t *active;                 // per candidate
+    double *vprev, *fcprev;          // per candidate, 3 each
+    const double *fside;             // per candidate internal force (from the element kernel)
+    const double *partials;          // element-kernel block partials
+    int nblocks;
+    double *hist;                    // 3 per step
+    double *blk;                     // PDN_CQ per contact workgroup
+};

@@ -1,0 +1,26 @@
+// pdn_launch.h -- host-side launchers of the libpdn kernels (internal).
+#pragma once
+#include "pdn_internal.h"
+
+#define PDN_MAX2(a, b) ((a) > (b) ? (a) : (b))
+// threads of an element-tile workgroup: one per element column and one per node column
+#define PDN_TILE_THREADS(TX, TY) ((PDN_MAX2((TX) * (TY), ((TX) + 1) * ((TY) + 1)) + 63) / 64 * 64)
+
+enum { PDN_TILE_16x16 = 0, PDN_TILE_32x8 = 1, PDN_TILE_8x8 = 2, PDN_TILE_15x15 = 3, PDN_TILE_COUNT = 4 };
+static const int pdn_tile_dims[PDN_TILE_COUNT][2] = {{16, 16}, {32, 8}, {8, 8}, {15, 15}};
+
+namespace pdn {
+template <typename R>
+hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, hipStream_t s);
+int contact_blocks(const ContactArgs &c);
+hipError_t launch_contact(const ContactArgs &c, hipStream_t s);
+hipError_t launch_contact_init(const ContactArgs &c, int reset_active, hipStream_t s);
+template <typename R>
+hipError_t launch_damage_bulk(const R *r, const LayerInfo *layers, const int *bulk_layer, const PlyC<R> *ply,
+                              const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind, double *out,
+                              hipStream_t s);
+template <typename R>
+hipError_t launch_damage_coh(const R *rd, const double *d, const LayerInfo *layers, const int *coh_layer,
+                             const PlyC<R> *ply, int nx, int ny, int64_t nce, double *out, hipStream_t s);
+hipError_t launch_project_max(const double *in, int64_t ncol, int nlayers, double *out, hipStream_t s);
+}  // namespace pdn

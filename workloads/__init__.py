@@ -69,6 +69,7 @@ LAW_CDM_SURROGATE = 2
 
 BC_CLAMPED_EDGES = 0
 BC_ASTM_WINDOW = 1
+BC_FREE = 2
 
 PREC_FP64 = 0
 PREC_MIXED = 1
