@@ -68,7 +68,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--config", default="config3", choices=["config2", "config3"])
     ap.add_argument("--precision", type=int, default=1)
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="15x15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300)
     args = ap.parse_args()

@@ -57,7 +57,7 @@ struct pdn_ctx {
     // device buffers
     double *d[2] = {nullptr, nullptr}, *v[2] = {nullptr, nullptr};
     void *r = nullptr, *rd = nullptr;
-    void *hx = nullptr, *hy = nullptr, *ply = nullptr;
+    void *hx = nullptr, *hy = nullptr, *ihx = nullptr, *ihy = nullptr, *ply = nullptr;
     double *xs_d = nullptr, *ys_d = nullptr, *mx_d = nullptr, *my_d = nullptr, *mz_d = nullptr;
     double *imx_d = nullptr, *imy_d = nullptr, *imz_d = nullptr, *blk_d = nullptr;
     LayerInfo *layers_d = nullptr;
@@ -309,6 +309,7 @@ ElemArgs<R> elem_args(pdn_ctx *c, int in, int out)
     a.d_in = c->d[in]; a.v_in = c->v[in]; a.d_out = c->d[out]; a.v_out = c->v[out];
     a.r = (R *)c->r; a.rd = (R *)c->rd;
     a.hx = (const R *)c->hx; a.hy = (const R *)c->hy;
+    a.ihx = (const R *)c->ihx; a.ihy = (const R *)c->ihy;
     a.mx = c->mx_d; a.my = c->my_d; a.mz = c->mz_d;
     a.imx = c->imx_d; a.imy = c->imy_d; a.imz = c->imz_d;
     a.layers = c->layers_d;
@@ -346,6 +347,14 @@ int launch_en(pdn_ctx *c, int in, int out)
     return PDN_OK;
 }
 
+bool tile_fits(pdn_ctx *c, int tile)
+{
+    int maxlds = 0;
+    if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) return false;
+    const int lds = pdn::elem_node_lds_bytes(c->precision == PDN_MIXED, tile);
+    return lds > 0 && lds <= maxlds;
+}
+
 void set_tiles(pdn_ctx *c)
 {
     const int TX = pdn_tile_dims[c->tile][0], TY = pdn_tile_dims[c->tile][1];
@@ -370,7 +379,7 @@ int init_level(pdn_ctx *c, bool reset_contact)
 
 void free_all(pdn_ctx *c)
 {
-    void *ps[] = {c->d[0], c->d[1], c->v[0], c->v[1], c->r, c->rd, c->hx, c->hy, c->ply, c->xs_d, c->ys_d,
+    void *ps[] = {c->d[0], c->d[1], c->v[0], c->v[1], c->r, c->rd, c->hx, c->hy, c->ihx, c->ihy, c->ply, c->xs_d, c->ys_d,
                   c->mx_d, c->my_d, c->mz_d, c->imx_d, c->imy_d, c->imz_d, c->blk_d,
                   c->layers_d, c->bulk_layer_d, c->coh_layer_d, c->bcb_d,
                   c->active_d, c->vprev_d, c->fcprev_d, c->fside_d, c->partials_d, c->gl_d, c->hist_d, c->dmg_d};
@@ -466,11 +475,11 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
     int nb = 0, ncl = 0;
     for (int p = 0; p < c->P; ++p) {
         for (int e = 0; e < c->epp; ++e) {
-            c->layers.push_back(LayerInfo{0, p, nb++, 0, hz});
+            c->layers.push_back(LayerInfo{0, p, nb++, 0, hz, 1.0 / hz});
             c->bulk_layer.push_back((int)c->layers.size() - 1);
         }
         if (p + 1 < c->P && c->cohesive && c->ang[p] != c->ang[p + 1]) {
-            c->layers.push_back(LayerInfo{1, p, ncl++, 0, 0.0});
+            c->layers.push_back(LayerInfo{1, p, ncl++, 0, 0.0, 0.0});
             c->coh_layer.push_back((int)c->layers.size() - 1);
         }
     }
@@ -511,6 +520,19 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
         if (he != hipSuccess) { delete c; return PDN_EDEVICE; }
         c->own_stream = true;
     }
+    {   // default element tile: the preferred shape whose workgroup fits the device's LDS
+        const int pref_mixed[] = {PDN_TILE_15x15, PDN_TILE_16x16, PDN_TILE_32x8, PDN_TILE_8x8};
+        const int pref_fp64[] = {PDN_TILE_16x16, PDN_TILE_15x15, PDN_TILE_32x8, PDN_TILE_8x8};
+        const int *pref = c->precision == PDN_MIXED ? pref_mixed : pref_fp64;
+        c->tile = -1;
+        for (int k = 0; k < PDN_TILE_COUNT && c->tile < 0; ++k)
+            if (tile_fits(c, pref[k])) c->tile = pref[k];
+        if (c->tile < 0) {
+            if (c->own_stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return PDN_EDEVICE;
+        }
+    }
     set_tiles(c);
     int rc = PDN_OK;
     const size_t rs = rsize(c);
@@ -522,6 +544,8 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
     if (!rc) rc = dalloc(c, &c->rd, c->npairs * rs);
     if (!rc) rc = dalloc(c, &c->hx, c->nx * rs);
     if (!rc) rc = dalloc(c, &c->hy, c->ny * rs);
+    if (!rc) rc = dalloc(c, &c->ihx, c->nx * rs);
+    if (!rc) rc = dalloc(c, &c->ihy, c->ny * rs);
     if (!rc) rc = dalloc(c, &c->ply, c->P * std::max(sizeof(PlyC<float>), sizeof(PlyC<double>)));
     if (!rc) rc = dalloc(c, (void **)&c->xs_d, (c->nx + 1) * sizeof(double));
     if (!rc) rc = dalloc(c, (void **)&c->ys_d, (c->ny + 1) * sizeof(double));
@@ -539,17 +563,23 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
     if (!rc) rc = dalloc(c, (void **)&c->partials_d, (size_t)PDN_NTERMS * std::max(1, c->nblocks) * sizeof(double));
     if (rc) { free_all(c); if (c->own_stream) (void)hipStreamDestroy(c->stream); delete c; return rc; }
     // tables
-    std::vector<double> hxv(c->nx), hyv(c->ny);
-    for (int i = 0; i < c->nx; ++i) hxv[i] = c->xs[i + 1] - c->xs[i];
-    for (int j = 0; j < c->ny; ++j) hyv[j] = c->ys[j + 1] - c->ys[j];
+    std::vector<double> hxv(c->nx), hyv(c->ny), ihxv(c->nx), ihyv(c->ny);
+    for (int i = 0; i < c->nx; ++i) { hxv[i] = c->xs[i + 1] - c->xs[i]; ihxv[i] = 1.0 / hxv[i]; }
+    for (int j = 0; j < c->ny; ++j) { hyv[j] = c->ys[j + 1] - c->ys[j]; ihyv[j] = 1.0 / hyv[j]; }
     if (c->precision == PDN_MIXED) {
         std::vector<float> a(hxv.begin(), hxv.end()), b(hyv.begin(), hyv.end());
+        std::vector<float> ia(ihxv.begin(), ihxv.end()), ib(ihyv.begin(), ihyv.end());
         rc = upload(c, (float *)c->hx, a);
         if (!rc) rc = upload(c, (float *)c->hy, b);
+        if (!rc) rc = upload(c, (float *)c->ihx, ia);
+        if (!rc) rc = upload(c, (float *)c->ihy, ib);
         if (!rc) rc = hipStreamSynchronize(c->stream) == hipSuccess ? PDN_OK : PDN_EDEVICE;
     } else {
         rc = upload(c, (double *)c->hx, hxv);
         if (!rc) rc = upload(c, (double *)c->hy, hyv);
+        if (!rc) rc = upload(c, (double *)c->ihx, ihxv);
+        if (!rc) rc = upload(c, (double *)c->ihy, ihyv);
+        if (!rc) rc = hipStreamSynchronize(c->stream) == hipSuccess ? PDN_OK : PDN_EDEVICE;
     }
     if (!rc) rc = upload(c, c->xs_d, c->xs);
     if (!rc) rc = upload(c, c->ys_d, c->ys);
@@ -1015,10 +1045,11 @@ int pdn_set_tile(pdn_ctx *c, int32_t tx, int32_t ty)
 {
     if (!c) return PDN_EINVAL;
     int t = -1;
-    if (tx == 0 && ty == 0) t = PDN_TILE_16x16;
+    if (tx == 0 && ty == 0) t = c->precision == PDN_MIXED ? PDN_TILE_15x15 : PDN_TILE_16x16;
     for (int k = 0; k < PDN_TILE_COUNT; ++k)
         if (pdn_tile_dims[k][0] == tx && pdn_tile_dims[k][1] == ty) t = k;
     if (t < 0) return set_err(c, PDN_EINVAL, "unsupported tile %dx%d", tx, ty);
+    if (!tile_fits(c, t)) return set_err(c, PDN_EINVAL, "tile %dx%d does not fit the device's LDS", tx, ty);
     const int old = c->nblocks;
     c->tile = t;
     set_tiles(c);

@@ -42,6 +42,7 @@ struct LayerInfo {
     int index;     // bulk layer index or interface index
     int pad;
     double hz;     // bulk layer thickness (0 for cohesive)
+    double ihz;    // 1 / hz (0 for cohesive)
 };
 
 // Scalars owned by the contact kernel (striker, books, counters).
@@ -79,6 +80,7 @@ struct ElemArgs {
     R *r;                            // 4 per bulk GP
     R *rd;                           // 1 per cohesive node pair
     const R *hx, *hy;                // element sizes (nx, ny)
+    const R *ihx, *ihy;              // their reciprocals
     const double *mx, *my, *mz;      // separable lumped-mass factors (nx+1, ny+1, K)
     const double *imx, *imy, *imz;   // their reciprocals
     const LayerInfo *layers;         // NL

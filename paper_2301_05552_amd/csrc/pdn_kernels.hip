@@ -219,13 +219,14 @@ __device__ __forceinline__ void inv8(const Modes<R> &c, R f[8])
     f[4] = q0 + r0; f[5] = q1 + r1; f[6] = q2 + r2; f[7] = q3 + r3;
 }
 
+// Returns the force coefficients on the corner basis (forces = inv8 of each).
 template <typename R>
 __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
-                              const PlyC<R> &P, R kappa, R r[4], bool &changed,
-                              R fx[8], R fy[8], R fz[8], R &uel)
+                              R ihx, R ihy, R ihz, const PlyC<R> &P, R kappa, R r[4], bool &changed,
+                              Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel)
 {
     Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
-    const R gx = R(0.25) / hx, gy = R(0.25) / hy, gz = R(0.25) / hz;
+    const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
     // displacement gradient G = F - I
     R G00 = sx.xi * gx, G01 = sx.eta * gy, G02 = sx.zeta * gz;
     R G10 = sy.xi * gx, G11 = sy.eta * gy, G12 = sy.zeta * gz;
@@ -269,18 +270,14 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
     R P22 = G20 * S02 + G21 * S12 + F22 * S22;
     const R ax = R(0.25) * hy * hz, ay = R(0.25) * hx * hz, az = R(0.25) * hx * hy;
     // hourglass: k = kappa Cmax V sum b^2 / 3, q = s/8, force coefficient k s / 64
-    const R khg = kappa * P.cmax * vol * (R(1) / (hx * hx) + R(1) / (hy * hy) + R(1) / (hz * hz)) / R(6);
+    const R khg = kappa * P.cmax * vol * (ihx * ihx + ihy * ihy + ihz * ihz) * R(1.0 / 6.0);
     const R kh = khg * R(1.0 / 64.0);
-    Modes<R> cx, cy, cz;
     cx.xi = P00 * ax; cx.eta = P01 * ay; cx.zeta = P02 * az;
     cy.xi = P10 * ax; cy.eta = P11 * ay; cy.zeta = P12 * az;
     cz.xi = P20 * ax; cz.eta = P21 * ay; cz.zeta = P22 * az;
     cx.ez = kh * sx.ez; cx.xz = kh * sx.xz; cx.xe = kh * sx.xe; cx.xez = kh * sx.xez;
     cy.ez = kh * sy.ez; cy.xz = kh * sy.xz; cy.xe = kh * sy.xe; cy.xez = kh * sy.xez;
     cz.ez = kh * sz.ez; cz.xz = kh * sz.xz; cz.xe = kh * sz.xe; cz.xez = kh * sz.xez;
-    inv8(cx, fx);
-    inv8(cy, fy);
-    inv8(cz, fz);
     R w = sg[0] * e[0] + sg[1] * e[1] + sg[2] * e[2] + sg[3] * e[3] + sg[4] * e[4] + sg[5] * e[5];
     R q2 = sx.ez * sx.ez + sx.xz * sx.xz + sx.xe * sx.xe + sx.xez * sx.xez
          + sy.ez * sy.ez + sy.xz * sy.xz + sy.xe * sy.xe + sy.xez * sy.xez
@@ -349,9 +346,15 @@ void k_elem_node(ElemArgs<R> A)
 {
     constexpr int NE = TX * TY, NCX = TX + 1, NCY = TY + 1, NC = NCX * NCY;
     constexpr int NT = PDN_TILE_THREADS(TX, TY);
-    __shared__ R U[2][3][NC];
-    __shared__ R Fs[2][4][3][NE];
+    constexpr bool F32 = sizeof(R) == 4;
+    __shared__ R Ubuf[F32 ? 2 : 1][3][F32 ? NC : 1];   // node planes k-1, k in FP32
+    __shared__ R Fs[2][4][3][NE];           // element corner forces: [bottom/top][corner][xyz]
+    __shared__ double D64[2][3][NC];        // FP64 displacement of planes k-1, k
+    __shared__ double V64[2][3][NC];        // FP64 velocity of planes k-1, k (own slot)
     __shared__ double red[PDN_NTERMS * (NT / 64)];
+    // element-type plane copy: the FP64 staging itself when R is double
+    R (*U)[3][NC] = F32 ? reinterpret_cast<R (*)[3][NC]>(&Ubuf[0][0][0])
+                        : reinterpret_cast<R (*)[3][NC]>(&D64[0][0][0]);
 
     const int t = threadIdx.x;
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -367,7 +370,6 @@ void k_elem_node(ElemArgs<R> A)
     const int ie = e0x + ea, je = e0y + eb;
     const bool evalid = erole && ie < nx && je < ny;
     const bool eown = evalid && (ea < TX - 1 || lastx) && (eb < TY - 1 || lasty);
-    const R ehx = evalid ? A.hx[ie] : R(1), ehy = evalid ? A.hy[je] : R(1);
     const int s0 = ea + NCX * eb;
 
     // node role: one node column per thread
@@ -379,40 +381,77 @@ void k_elem_node(ElemArgs<R> A)
     const int loy = ty == 0 ? 0 : e0y + 1, hiy = lasty ? ny + 1 : e0y + TY;
     const bool nown = nvalid && gi >= lox && gi < hix && gj >= loy && gj < hiy;
     const int64_t col = nvalid ? gi + (int64_t)(nx + 1) * gj : 0;
-    const double mxy = nvalid ? A.mx[gi] * A.my[gj] : 0.0;
-    const double imxy = nvalid ? A.imx[gi] * A.imy[gj] : 0.0;
-    const int fix_lat = (A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny)) ? 7 : 0;
-    const int fix_bot = nvalid ? (int)A.bc_bottom[col] : 0;
-    const bool cand = nvalid && gi >= A.ci0 && gi < A.ci1 && gj >= A.cj0 && gj < A.cj1;
 
-    double dp[3] = {0, 0, 0}, vp[3] = {0, 0, 0}, dc[3] = {0, 0, 0}, vc[3] = {0, 0, 0};
     double carry[3] = {0, 0, 0}, fin[3];
     double acc[PDN_NTERMS];
 #pragma unroll
     for (int k = 0; k < PDN_NTERMS; ++k) acc[k] = 0.0;
 
-    const double dt = A.dt, phi = A.phi, g = A.grav;
+    // node plane k is fetched from HBM one iteration ahead (kept in registers
+    // while the previous layer is computed), then staged in LDS
+    double pd[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
+    auto fetch_plane = [&](int k) {
+        if (nvalid) {
+            const int64_t nk = col + plane * k;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pd[c] = A.d_in[3 * nk + c];
+            if (nown) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pv[c] = A.v_in[3 * nk + c];
+            }
+        }
+    };
+    auto stage_plane = [&](int k) {
+        const int p = k & 1;
+        if (nvalid) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                D64[p][c][t] = pd[c];
+                if (F32) U[p][c][t] = (R)pd[c];
+            }
+            if (nown) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) V64[p][c][t] = pv[c];
+            }
+        } else if (nrole) {
+            U[p][0][t] = U[p][1][t] = U[p][2][t] = R(0);
+        }
+    };
+    // damage thresholds of the element in layer l, fetched one layer ahead
+    R rn[4] = {R(1), R(1), R(1), R(1)};
+    auto fetch_r = [&](int l) {
+        if (l < A.NL && evalid) {
+            const LayerInfo L = A.layers[l];
+            if (L.type == 0 && A.ply[L.ply].law != 0)
+                load_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * L.index), rn);
+        }
+    };
 
-    auto update_node = [&](int kp, const double d[3], const double v[3], const double f[3]) {
+    // lumped-mass integration of plane kp with total internal force f; next predictor
+    auto update_node = [&](int kp, const double f[3]) {
+        const int p = kp & 1;
         const int64_t n = col + plane * kp;
-        const int bits = fix_lat | (kp == 0 ? fix_bot : 0);
-        const double m = mxy * A.mz[kp];
-        acc[T_MZ] += m * d[2];                 // gravity work = -g (sum m d_z - its initial value)
-        const double im = imxy * A.imz[kp];
+        const int fix_lat = (A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny)) ? 7 : 0;
+        const int bits = fix_lat | (kp == 0 ? (int)A.bc_bottom[col] : 0);
+        const double m = A.mx[gi] * A.my[gj] * A.mz[kp];
+        const double im = A.imx[gi] * A.imy[gj] * A.imz[kp];
+        const double dt = A.dt, g = A.grav;
+        acc[T_MZ] += m * D64[p][2][t];         // gravity work = -g (sum m d_z - its initial value)
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
+            const double d = D64[p][c][t], v = V64[p][c][t];
             const bool fx = (bits >> c) & 1;
             const double fe = c == 2 ? -m * g : 0.0;
             const double a = fx ? 0.0 : (fe - f[c]) * im;
-            const double vn = fx ? 0.0 : v[c] + dt * a;
-            const double dn = fx ? d[c] : d[c] + dt * v[c] + phi * dt * dt * a;
-            acc[T_KE] += 0.5 * m * v[c] * vn;
-            acc[T_WA] += 0.5 * dt * v[c] * f[c];
+            const double vn = fx ? 0.0 : v + dt * a;
+            const double dn = fx ? d : d + dt * v + A.phi * dt * dt * a;
+            acc[T_KE] += 0.5 * m * v * vn;
+            acc[T_WA] += 0.5 * dt * v * f[c];
             acc[T_WB] += 0.5 * dt * vn * f[c];
             A.d_out[3 * n + c] = dn;
             A.v_out[3 * n + c] = vn;
         }
-        if (kp == A.K - 1 && cand) {
+        if (kp == A.K - 1 && gi >= A.ci0 && gi < A.ci1 && gj >= A.cj0 && gj < A.cj1) {
             const int64_t ci = (gi - A.ci0) + (int64_t)(A.ci1 - A.ci0) * (gj - A.cj0);
             A.fside[3 * ci + 0] = f[0];
             A.fside[3 * ci + 1] = f[1];
@@ -420,41 +459,20 @@ void k_elem_node(ElemArgs<R> A)
         }
     };
 
-    // prologue: plane 0
-    if (nvalid) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            dp[c] = A.d_in[3 * col + c];
-            U[0][c][t] = (R)dp[c];
-        }
-        if (nown) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) vp[c] = A.v_in[3 * col + c];
-        }
-    } else if (nrole) {
-        U[0][0][t] = U[0][1][t] = U[0][2][t] = R(0);
-    }
-
+    fetch_plane(0);
+    stage_plane(0);
+    fetch_plane(1);
+    fetch_r(0);
     for (int k = 1; k < A.K; ++k) {
         const LayerInfo L = A.layers[k - 1];
-        const int64_t nk = col + plane * k;
-        if (nvalid) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                dc[c] = A.d_in[3 * nk + c];
-                U[k & 1][c][t] = (R)dc[c];
-            }
-            if (nown) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) vc[c] = A.v_in[3 * nk + c];
-            }
-        } else if (nrole) {
-            U[k & 1][0][t] = U[k & 1][1][t] = U[k & 1][2][t] = R(0);
-        }
+        stage_plane(k);
+        R r[4] = {rn[0], rn[1], rn[2], rn[3]};
+        if (k + 1 < A.K) fetch_plane(k + 1);
+        fetch_r(k);
         if (L.type == 0) {
             __syncthreads();
             if (erole) {
-                R fx[8], fy[8], fz[8];
+                R* F0 = &Fs[0][0][0][t];
                 if (evalid) {
                     const int kb = (k - 1) & 1, kt = k & 1;
                     const int sl[4] = {s0, s0 + 1, s0 + 1 + NCX, s0 + NCX};
@@ -466,52 +484,58 @@ void k_elem_node(ElemArgs<R> A)
                     }
                     const PlyC<R> &P = A.ply[L.ply];
                     const int64_t e = ie + (int64_t)nx * (je + (int64_t)ny * L.index);
-                    R r[4] = {R(1), R(1), R(1), R(1)};
-                    if (P.law != 0) load_state(A.r, e, r);
                     bool changed = false;
                     R uel;
-                    hex_box_force(ux, uy, uz, ehx, ehy, (R)L.hz, P, A.kappa, r, changed, fx, fy, fz, uel);
+                    Modes<R> cm[3];
+                    hex_box_force(ux, uy, uz, A.hx[ie], A.hy[je], (R)L.hz, A.ihx[ie], A.ihy[je], (R)L.ihz, P,
+                                  A.kappa, r, changed, cm[0], cm[1], cm[2], uel);
                     if (eown) {
                         if (changed) store_state(A.r, e, r);
                         acc[T_UEL] += (double)uel;
                     }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        R f[8];
+                        inv8(cm[c], f);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            F0[(q * 3 + c) * NE] = f[q];                    // bottom corners
+                            F0[((4 + q) * 3 + c) * NE] = f[q + 4];          // top corners
+                        }
+                    }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) fx[q] = fy[q] = fz[q] = R(0);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    Fs[0][q][0][t] = fx[q]; Fs[0][q][1][t] = fy[q]; Fs[0][q][2][t] = fz[q];
-                    Fs[1][q][0][t] = fx[q + 4]; Fs[1][q][1][t] = fy[q + 4]; Fs[1][q][2][t] = fz[q + 4];
+                    for (int q = 0; q < 24; ++q) F0[q * NE] = R(0);
                 }
             }
             __syncthreads();
             if (nown) {
-                double fb[3] = {0, 0, 0}, ft[3] = {0, 0, 0};
                 // node (np, nq) is corner 0 of element (np, nq), 1 of (np-1, nq),
-                // 2 of (np-1, nq-1) and 3 of (np, nq-1)
+                // 2 of (np-1, nq-1) and 3 of (np, nq-1); the four corner forces of
+                // one layer are summed in the element type, in this order
+                R fb[3] = {R(0), R(0), R(0)}, ft[3] = {R(0), R(0), R(0)};
                 if (np < TX && nq < TY) {
                     const int e = np + TX * nq;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += (double)Fs[0][0][c][e]; ft[c] += (double)Fs[1][0][c][e]; }
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][0][c][e]; ft[c] += Fs[1][0][c][e]; }
                 }
                 if (np >= 1 && nq < TY) {
                     const int e = np - 1 + TX * nq;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += (double)Fs[0][1][c][e]; ft[c] += (double)Fs[1][1][c][e]; }
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][1][c][e]; ft[c] += Fs[1][1][c][e]; }
                 }
                 if (np >= 1 && nq >= 1) {
                     const int e = np - 1 + TX * (nq - 1);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += (double)Fs[0][2][c][e]; ft[c] += (double)Fs[1][2][c][e]; }
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][2][c][e]; ft[c] += Fs[1][2][c][e]; }
                 }
                 if (np < TX && nq >= 1) {
                     const int e = np + TX * (nq - 1);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += (double)Fs[0][3][c][e]; ft[c] += (double)Fs[1][3][c][e]; }
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][3][c][e]; ft[c] += Fs[1][3][c][e]; }
                 }
 #pragma unroll
-                for (int c = 0; c < 3; ++c) { fin[c] = carry[c] + fb[c]; carry[c] = ft[c]; }
+                for (int c = 0; c < 3; ++c) { fin[c] = carry[c] + (double)fb[c]; carry[c] = (double)ft[c]; }
             }
         } else if (nown) {
             // zero-thickness interface, nodal (Newton-Cotes) points: the points of
@@ -519,26 +543,27 @@ void k_elem_node(ElemArgs<R> A)
             // one state and the summed tributary area
             const PlyC<R> &P = A.ply[L.ply];
             const int64_t pi = col + plane * L.index;
+            const int pb = (k - 1) & 1, pt = k & 1;
             R rd = A.rd[pi];
             R tau[3];
             bool changed;
-            const R d1 = (R)(dc[0] - dp[0]), d2 = (R)(dc[1] - dp[1]), d3 = (R)(dc[2] - dp[2]);
+            const R d1 = (R)(D64[pt][0][t] - D64[pb][0][t]);
+            const R d2 = (R)(D64[pt][1][t] - D64[pb][1][t]);
+            const R d3 = (R)(D64[pt][2][t] - D64[pb][2][t]);
             czm_update(P, d1, d2, d3, rd, tau, changed);
             if (changed) A.rd[pi] = rd;
-            const double ap = mxy;     // (sum of adjacent widths / 2)(... / 2)
+            const double ap = A.mx[gi] * A.my[gj];   // (sum of adjacent widths / 2)(... / 2)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const double ft = ap * (double)tau[c];
-                fin[c] = carry[c] - ft;
-                carry[c] = ft;
+                const double ftc = ap * (double)tau[c];
+                fin[c] = carry[c] - ftc;
+                carry[c] = ftc;
             }
             acc[T_UEL] += 0.5 * ap * (double)(tau[0] * d1 + tau[1] * d2 + tau[2] * d3);
         }
-        if (nown) update_node(k - 1, dp, vp, fin);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { dp[c] = dc[c]; vp[c] = vc[c]; }
+        if (nown) update_node(k - 1, fin);
     }
-    if (nown) update_node(A.K - 1, dp, vp, carry);
+    if (nown) update_node(A.K - 1, carry);
     block_reduce_store<NT>(acc, A.partials + (int64_t)blockIdx.x * PDN_NTERMS, red);
 }
 
@@ -818,6 +843,28 @@ hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, hipStream_t s)
     default: return hipErrorInvalidValue;
     }
 }
+template <typename R, int TX, int TY>
+static int lds_of()
+{
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_elem_node<R, TX, TY>)) != hipSuccess) return -1;
+    return (int)at.sharedSizeBytes;
+}
+
+template <typename R>
+static int lds_r(int tile)
+{
+    switch (tile) {
+    case PDN_TILE_16x16: return lds_of<R, 16, 16>();
+    case PDN_TILE_32x8: return lds_of<R, 32, 8>();
+    case PDN_TILE_8x8: return lds_of<R, 8, 8>();
+    case PDN_TILE_15x15: return lds_of<R, 15, 15>();
+    default: return -1;
+    }
+}
+
+int elem_node_lds_bytes(int mixed, int tile) { return mixed ? lds_r<float>(tile) : lds_r<double>(tile); }
+
 template hipError_t launch_elem_node<float>(const ElemArgs<float> &, int, hipStream_t);
 template hipError_t launch_elem_node<double>(const ElemArgs<double> &, int, hipStream_t);
 

@@ -13,6 +13,7 @@ namespace pdn {
 template <typename R>
 hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, hipStream_t s);
 int contact_blocks(const ContactArgs &c);
+int elem_node_lds_bytes(int mixed, int tile);   // static LDS of one element/node workgroup (-1 on error)
 hipError_t launch_contact(const ContactArgs &c, hipStream_t s);
 hipError_t launch_contact_init(const ContactArgs &c, int reset_active, hipStream_t s);
 template <typename R>

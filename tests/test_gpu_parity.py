@@ -125,12 +125,17 @@ def test_tile_shape_invariance_bitwise(prec):
     cfg = copy.deepcopy(W.tiny(47, 23, 3, 1, angles=[0, 45, 90], cohesive=1, law=W.LAW_CDM, lx=47e-3,
                                ly=23e-3, ply_thickness=0.5e-3, v0=8.0, mass=0.1, R=4e-3, precision=prec))
     res = []
-    for tile in ((16, 16), (32, 8), (8, 8)):
-        g = pdn.Simulation(cfg, tile=tile)
+    for tile in ((15, 15), (16, 16), (32, 8), (8, 8)):
+        try:
+            g = pdn.Simulation(cfg, tile=tile)
+        except pdn.PdnError as e:                 # workgroup does not fit this device's LDS
+            assert e.code == pdn.PDN_EINVAL
+            continue
         g.step(120)
         res.append((g.array_get(pdn.ARR_DISP), g.array_get(pdn.ARR_VEL), g.contact_force()[1],
                     g.energies()["w_int"]))
         g.close()
+    assert len(res) >= 2
     for r in res[1:]:
         assert np.array_equal(r[0], res[0][0]) and np.array_equal(r[1], res[0][1])
         assert np.array_equal(r[2], res[0][2])
