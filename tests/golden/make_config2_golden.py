@@ -1,0 +1,87 @@
+"""Write config2_fp64_oracle.json: the FP64 oracle's run of the 8-ply
+[0/45/-45/90]s plate (300 x 200 x 8 hex8, intralaminar damage, ASTM window
+supports, 5.5 kg striker at 15 J) to 3 ms.
+
+The stored values (contact-force history, its peak, projected damage areas,
+energy books) are the expected values of the reduced-precision gate: FP32
+element arithmetic must reproduce the peak contact force within 0.5 % and the
+projected damage areas within 2 % of this FP64 run.
+
+Only the oracle and the input generators are called.  Usage (about two hours
+on 5 cores):
+
+    python tests/golden/make_config2_golden.py [--threads 5] [--t-end 3e-3]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+import workloads as W  # noqa: E402
+
+THRESHOLDS = (0.0, 0.5, 0.999)       # d > 0, and d >= 0.5 / 0.999 (damage-area readings)
+EVERY = 50
+
+
+def projected_areas(o, cfg):
+    m = cfg["mesh"]
+    cell = (m["lx"] / m["nx"]) * (m["ly"] / m["ny"])
+    out = {}
+    for name, kind in (("fibre", oracle.DMG_PROJ_FIBRE), ("matrix", oracle.DMG_PROJ_MATRIX)):
+        d = o.damage_field(kind)
+        out[name] = {}
+        for thr in THRESHOLDS:
+            n = int((d > 0).sum()) if thr == 0 else int((d >= thr).sum())
+            out[name][f"{thr:g}"] = {"columns": n, "area_m2": n * cell}
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--threads", type=int, default=5)
+    ap.add_argument("--t-end", type=float, default=3e-3)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                  "config2_fp64_oracle.json"))
+    args = ap.parse_args()
+    oracle.build(force=False)
+    cfg = W.config2(W.PREC_FP64)
+    o = oracle.Oracle(cfg, threads=args.threads)
+    steps = int(math.ceil(args.t_end / o.dt))
+    t0 = time.time()
+    done = 0
+    while done < steps:
+        n = min(1000, steps - done)
+        o.step(n)
+        done += n
+        t, f, _ = o.history()
+        print(f"[golden] {done}/{steps} steps, F={f[-1]:.1f} N, {time.time() - t0:.0f} s", flush=True)
+    t, f, x = o.history()
+    i = int(np.argmax(f))
+    res = {
+        "source": "FP64 oracle (oracle/pdn_oracle.c) on workloads.config2, written by make_config2_golden.py",
+        "basis": "laminate, supports and striker of the drop-weight coupon (Sec. 4), Table 1 material; "
+                 "contact force and projected damage are the outputs of Tabs. 2 and 4 and Fig. 9",
+        "dt": o.dt, "steps": steps, "t_end": float(t[-1]),
+        "peak_force_N": float(f[i]), "t_peak_s": float(t[i]),
+        "history_every": EVERY,
+        "history": {"t": t[EVERY - 1::EVERY].tolist(), "force": f[EVERY - 1::EVERY].tolist(),
+                    "imp_disp": x[EVERY - 1::EVERY].tolist()},
+        "projected_damage": projected_areas(o, cfg),
+        "energies": o.energies(),
+        "oracle_seconds": time.time() - t0,
+    }
+    with open(args.out, "w") as fh:
+        json.dump(res, fh, indent=1)
+    print(f"[golden] wrote {args.out}: peak {f[i]:.2f} N at {t[i] * 1e3:.3f} ms", flush=True)
+
+
+if __name__ == "__main__":
+    main()
