@@ -163,6 +163,31 @@ int pdn_set_tile(pdn_ctx *ctx, int32_t tile_x, int32_t tile_y);
  * kernel over the last pdn_step call, from HIP events (0 if not timed). */
 int pdn_kernel_times(const pdn_ctx *ctx, double *elem_node_ms, double *contact_ms);
 int pdn_set_timing(pdn_ctx *ctx, int32_t on);
+/* Autotuner: time one element/node pass per supported tile shape that fits
+ * the device, keep the fastest (remembered per plate shape for the process)
+ * and report it.  The timed passes recompute the current predictor, so the
+ * simulation state is unchanged.  ESTATE before materials and striker. */
+int pdn_autotune(pdn_ctx *ctx, int32_t *tile_x, int32_t *tile_y);
+
+/* Batched stepping of independent impact cases (many plates of uneven size
+ * advanced together; each case is the method of Algorithm 1 on its own plate).
+ * pdn_batch_create takes n contexts that are fully set up (mesh, materials,
+ * striker), on one device and in one precision; they stay owned by the caller
+ * and must outlive the batch.  It picks one element tile for all cases with
+ * the autotuner (remembered per batch composition) and captures a graph of
+ * steps.  pdn_batch_step advances every case by n steps: one launch of the
+ * contact kernel and one of the element/node kernel per step serve all cases;
+ * it runs on the first case's stream and returns when done.  Each case keeps
+ * its own time step, history, energies and outputs, read with the per-context
+ * calls; a case may also be stepped alone between batched calls.  Errors name
+ * the case (pdn_batch_last_error); EINVAL for mixed devices or precisions or a
+ * repeated context, and on failure of pdn_batch_create the first case's
+ * pdn_last_error gives the reason. */
+int pdn_batch_create(pdn_ctx *const *cases, int32_t n, pdn_batch **out);
+int pdn_batch_step(pdn_batch *b, int64_t n);
+int pdn_batch_info(const pdn_batch *b, int32_t *tile_x, int32_t *tile_y, int64_t *n_bulk, int32_t *blocks);
+const char *pdn_batch_last_error(const pdn_batch *b);
+void pdn_batch_destroy(pdn_batch *b);
 const char *pdn_last_error(const pdn_ctx *ctx);
 void pdn_destroy(pdn_ctx *ctx);
 

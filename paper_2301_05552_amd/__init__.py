@@ -98,6 +98,12 @@ def lib():
             "pdn_set_timing": [vp, C.c_int32],
             "pdn_last_error": [vp],
             "pdn_destroy": [vp],
+            "pdn_autotune": [vp, P(C.c_int32), P(C.c_int32)],
+            "pdn_batch_create": [P(vp), C.c_int32, P(vp)],
+            "pdn_batch_step": [vp, i64],
+            "pdn_batch_info": [vp, P(C.c_int32), P(C.c_int32), P(i64), P(C.c_int32)],
+            "pdn_batch_last_error": [vp],
+            "pdn_batch_destroy": [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -105,6 +111,8 @@ def lib():
             f.restype = C.c_int
         L.pdn_last_error.restype = C.c_char_p
         L.pdn_destroy.restype = None
+        L.pdn_batch_last_error.restype = C.c_char_p
+        L.pdn_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -239,3 +247,46 @@ class Simulation:
         a, b = C.c_double(), C.c_double()
         self._chk(lib().pdn_kernel_times(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def autotune(self):
+        tx, ty = C.c_int32(), C.c_int32()
+        self._chk(lib().pdn_autotune(self.h, C.byref(tx), C.byref(ty)))
+        return tx.value, ty.value
+
+
+class Batch:
+    """Independent cases advanced together (pdn_batch_*): one launch of each
+    kernel per step serves every case.  The Simulations stay owned by the
+    caller and must outlive the batch."""
+
+    def __init__(self, sims):
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.h for s in self.sims])
+        h = C.c_void_p()
+        rc = lib().pdn_batch_create(arr, len(self.sims), C.byref(h))
+        if rc != 0:
+            raise PdnError(rc, lib().pdn_last_error(self.sims[0].h).decode())
+        self.h = h
+
+    def _chk(self, rc):
+        if rc != 0:
+            raise PdnError(rc, lib().pdn_batch_last_error(self.h).decode())
+
+    def step(self, n: int = 1):
+        self._chk(lib().pdn_batch_step(self.h, n))
+
+    def info(self) -> dict:
+        tx, ty, nb, bl = C.c_int32(), C.c_int32(), C.c_int64(), C.c_int32()
+        self._chk(lib().pdn_batch_info(self.h, C.byref(tx), C.byref(ty), C.byref(nb), C.byref(bl)))
+        return {"tile": (tx.value, ty.value), "n_bulk": nb.value, "blocks": bl.value}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pdn_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

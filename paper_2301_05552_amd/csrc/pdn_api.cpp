@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -293,6 +294,7 @@ int ensure_history(pdn_ctx *c, int64_t need)
     c->hist_cap = cap;
     c->gl.hist_cap = cap;
     HIPCHK(c, hipMemcpyAsync(&c->gl_d->hist_cap, &cap, sizeof cap, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));      // the source is a local
     return PDN_OK;
 }
 
@@ -1096,3 +1098,382 @@ void pdn_destroy(pdn_ctx *c)
 }
 
 }  // extern "C"
+
+// ---- autotuner and batched stepping --------------------------------------
+struct pdn_batch {
+    std::string err;
+    std::vector<pdn_ctx *> cs;
+    int device = 0, precision = 0, tile = -1;
+    hipStream_t stream = nullptr;        // stream of the first case; every step runs here
+    hipStream_t cap = nullptr;           // private stream used only to capture the step graph
+    void *eargs_d = nullptr;             // 2 x n element-kernel arguments (step parity 0, 1)
+    ContactArgs *cargs_d = nullptr;      // 2 x n contact-kernel arguments
+    int *estart_d = nullptr, *cstart_d = nullptr;
+    std::vector<int> estart, cstart;
+    std::vector<unsigned char> eargs_h;
+    std::vector<ContactArgs> cargs_h;
+    int eblocks = 0, cblocks = 0;
+    hipGraphExec_t exec = nullptr;       // PDN_BATCH_GRAPH_STEPS steps, built for (tile, eblocks, cblocks)
+    int graph_tile = -1, graph_eblocks = 0, graph_cblocks = 0;
+};
+
+#define PDN_BATCH_GRAPH_STEPS 8          // even: a replay returns every case to the same buffer parity
+
+namespace {
+
+int berr(pdn_batch *b, int code, const char *fmt, ...)
+{
+    if (b) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        b->err = buf;
+    }
+    return code;
+}
+
+#define BHIPCHK(b, call)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return berr(b, e_ == hipErrorOutOfMemory ? PDN_ENOMEM : PDN_EDEVICE, "%s: %s",     \
+                        #call, hipGetErrorString(e_));                                          \
+    } while (0)
+
+const int kTileOrder[PDN_TILE_COUNT] = {PDN_TILE_15x15, PDN_TILE_16x16, PDN_TILE_32x8, PDN_TILE_8x8};
+
+// tile measured fastest, per plate shape (single plates) or per batch composition
+std::map<std::string, int> &tune_cache()
+{
+    static std::map<std::string, int> m;
+    return m;
+}
+
+std::string shape_key(const pdn_ctx *c)
+{
+    char k[96];
+    snprintf(k, sizeof k, "%d:%d:%d:%d:%d;", c->device, c->precision, c->nx, c->ny, c->K);
+    return k;
+}
+
+// Put a context in tile layout t and re-run its element pass in that layout
+// (the pass recomputes the predictor from the last completed level, so it
+// changes no state: running it again gives the same outputs).
+int use_tile(pdn_ctx *c, int t)
+{
+    int rc = pdn_set_tile(c, pdn_tile_dims[t][0], pdn_tile_dims[t][1]);
+    if (!rc) rc = pdn_step(c, 0);
+    return rc;
+}
+
+// mean time of `reps` element passes of one context in its current layout
+int time_single(pdn_ctx *c, int reps, float *ms)
+{
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    int rc = launch_en(c, c->cur, 1 - c->cur);            // warm
+    if (!rc) HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps && !rc; ++r) rc = launch_en(c, c->cur, 1 - c->cur);
+    if (!rc) HIPCHK(c, hipEventRecord(e1, c->stream));
+    if (!rc) HIPCHK(c, hipEventSynchronize(e1));
+    if (!rc) HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc) *ms /= reps;
+    return rc;
+}
+
+template <typename R>
+void fill_eargs(pdn_batch *b)
+{
+    const size_t n = b->cs.size();
+    b->eargs_h.resize(2 * n * sizeof(ElemArgs<R>));
+    ElemArgs<R> *ea = reinterpret_cast<ElemArgs<R> *>(b->eargs_h.data());
+    for (int p = 0; p < 2; ++p)
+        for (size_t i = 0; i < n; ++i) {
+            pdn_ctx *c = b->cs[i];
+            const int cur = c->cur ^ p, pred = 1 - cur;     // state of case i at a step of parity p
+            ea[p * n + i] = elem_args<R>(c, pred, cur);
+        }
+}
+
+// argument tables and block offsets of the current layout, uploaded to the device
+int upload_tables(pdn_batch *b)
+{
+    const size_t n = b->cs.size();
+    b->estart.assign(n + 1, 0);
+    b->cstart.assign(n + 1, 0);
+    b->cargs_h.resize(2 * n);
+    for (size_t i = 0; i < n; ++i) {
+        pdn_ctx *c = b->cs[i];
+        b->estart[i + 1] = b->estart[i] + c->nblocks;
+        for (int p = 0; p < 2; ++p) b->cargs_h[p * n + i] = contact_args(c, 1 - (c->cur ^ p));
+        b->cstart[i + 1] = b->cstart[i] + pdn::contact_blocks(b->cargs_h[i]);
+    }
+    b->eblocks = b->estart[n];
+    b->cblocks = b->cstart[n];
+    if (b->precision == PDN_MIXED) fill_eargs<float>(b);
+    else fill_eargs<double>(b);
+    if (!b->eargs_d) {
+        BHIPCHK(b, hipMalloc(&b->eargs_d, b->eargs_h.size()));
+        BHIPCHK(b, hipMalloc((void **)&b->cargs_d, 2 * n * sizeof(ContactArgs)));
+        BHIPCHK(b, hipMalloc((void **)&b->estart_d, (n + 1) * sizeof(int)));
+        BHIPCHK(b, hipMalloc((void **)&b->cstart_d, (n + 1) * sizeof(int)));
+    }
+    BHIPCHK(b, hipMemcpyAsync(b->eargs_d, b->eargs_h.data(), b->eargs_h.size(), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->cargs_d, b->cargs_h.data(), 2 * n * sizeof(ContactArgs), hipMemcpyHostToDevice,
+                              b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->estart_d, b->estart.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->cstart_d, b->cstart.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipStreamSynchronize(b->stream));          // host tables are reused
+    return PDN_OK;
+}
+
+hipError_t launch_batch_elem(pdn_batch *b, int parity, hipStream_t s)
+{
+    const int n = (int)b->cs.size();
+    if (b->precision == PDN_MIXED)
+        return pdn::launch_elem_node_batch<float>(reinterpret_cast<ElemArgs<float> *>(b->eargs_d) + parity * n,
+                                                  b->estart_d, n, b->eblocks, b->tile, s);
+    return pdn::launch_elem_node_batch<double>(reinterpret_cast<ElemArgs<double> *>(b->eargs_d) + parity * n,
+                                               b->estart_d, n, b->eblocks, b->tile, s);
+}
+
+// one step of every case: contact pass, then element/node pass
+hipError_t launch_batch_step(pdn_batch *b, int parity, hipStream_t s)
+{
+    const int n = (int)b->cs.size();
+    hipError_t e = pdn::launch_contact_batch(b->cargs_d + parity * n, b->cstart_d, n, b->cblocks, s);
+    if (e == hipSuccess) e = launch_batch_elem(b, parity, s);
+    return e;
+}
+
+// Mean time of `reps` batched element passes.  The passes use the parity-1
+// tables, which read the last completed level and write the next predictor
+// (what the pass after a step already wrote), so no state changes.
+int time_batch(pdn_batch *b, int reps, float *ms)
+{
+    hipEvent_t e0, e1;
+    BHIPCHK(b, hipEventCreate(&e0));
+    BHIPCHK(b, hipEventCreate(&e1));
+    hipError_t e = launch_batch_elem(b, 1, b->stream);      // warm
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch_elem(b, 1, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return berr(b, PDN_EDEVICE, "batch timing: %s", hipGetErrorString(e));
+    *ms /= reps;
+    return PDN_OK;
+}
+
+int batch_case_err(pdn_batch *b, size_t i, int rc)
+{
+    return berr(b, rc, "case %zu: %s", i, b->cs[i]->err.c_str());
+}
+
+// all cases in tile layout t, ready to step, tables uploaded
+int batch_use_tile(pdn_batch *b, int t)
+{
+    for (size_t i = 0; i < b->cs.size(); ++i) {
+        int rc = use_tile(b->cs[i], t);
+        if (rc) return batch_case_err(b, i, rc);
+    }
+    b->tile = t;
+    return upload_tables(b);
+}
+
+int build_graph(pdn_batch *b)
+{
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    hipGraph_t g = nullptr;
+    BHIPCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int s = 0; s < PDN_BATCH_GRAPH_STEPS && e == hipSuccess; ++s) e = launch_batch_step(b, s & 1, b->cap);
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return berr(b, PDN_EDEVICE, "step graph capture: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiateWithFlags(&b->exec, g, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return berr(b, PDN_EDEVICE, "step graph instantiation: %s", hipGetErrorString(e));
+    b->graph_tile = b->tile;
+    b->graph_eblocks = b->eblocks;
+    b->graph_cblocks = b->cblocks;
+    return PDN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdn_autotune(pdn_ctx *c, int32_t *tile_x, int32_t *tile_y)
+{
+    if (!c) return PDN_EINVAL;
+    if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
+    if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "materials and striker must be set first");
+    (void)hipSetDevice(c->device);
+    const std::string key = "1|" + shape_key(c);
+    auto it = tune_cache().find(key);
+    int best = -1, rc;
+    if (it != tune_cache().end()) {
+        best = it->second;
+    } else {
+        float best_ms = 0;
+        for (int t : kTileOrder) {
+            if (!tile_fits(c, t)) continue;
+            float ms = 0;
+            if ((rc = use_tile(c, t)) || (rc = time_single(c, 3, &ms))) return rc;
+            if (best < 0 || ms < best_ms) { best = t; best_ms = ms; }
+        }
+        if (best < 0) return set_err(c, PDN_EINVAL, "no element tile fits this device");
+        tune_cache()[key] = best;
+    }
+    if ((rc = use_tile(c, best))) return rc;
+    if (tile_x) *tile_x = pdn_tile_dims[best][0];
+    if (tile_y) *tile_y = pdn_tile_dims[best][1];
+    return PDN_OK;
+}
+
+int pdn_batch_create(pdn_ctx *const *cases, int32_t n, pdn_batch **out)
+{
+    if (!out) return PDN_EINVAL;
+    *out = nullptr;
+    if (!cases || n < 1) return PDN_EINVAL;
+    for (int32_t i = 0; i < n; ++i) {
+        pdn_ctx *c = cases[i];
+        if (!c) return PDN_EINVAL;
+        for (int32_t j = 0; j < i; ++j)
+            if (cases[j] == c) return set_err(c, PDN_EINVAL, "a context appears twice in the batch");
+        if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
+        if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "materials and striker must be set first");
+        if (c->device != cases[0]->device || c->precision != cases[0]->precision)
+            return set_err(c, PDN_EINVAL, "batched cases must share device and precision");
+    }
+    pdn_batch *b = new pdn_batch;
+    b->cs.assign(cases, cases + n);
+    b->device = cases[0]->device;
+    b->precision = cases[0]->precision;
+    b->stream = cases[0]->stream;
+    (void)hipSetDevice(b->device);
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
+        delete b;
+        return PDN_EDEVICE;
+    }
+    for (pdn_ctx *c : b->cs) (void)hipStreamSynchronize(c->stream);
+    // autotuner: time one batched element pass per tile shape that fits
+    std::string key = "B|";
+    for (pdn_ctx *c : b->cs) key += shape_key(c);
+    int rc = PDN_OK, best = -1;
+    auto it = tune_cache().find(key);
+    if (it != tune_cache().end()) {
+        best = it->second;
+    } else {
+        float best_ms = 0;
+        for (int t : kTileOrder) {
+            bool fits = true;
+            for (pdn_ctx *c : b->cs) fits = fits && tile_fits(c, t);
+            if (!fits) continue;
+            float ms = 0;
+            if ((rc = batch_use_tile(b, t)) || (rc = time_batch(b, 3, &ms))) break;
+            if (best < 0 || ms < best_ms) { best = t; best_ms = ms; }
+        }
+        if (!rc && best < 0) rc = berr(b, PDN_EINVAL, "no element tile fits this device");
+        if (!rc) tune_cache()[key] = best;
+    }
+    if (!rc) rc = batch_use_tile(b, best);
+    if (!rc) rc = build_graph(b);
+    if (rc) {
+        set_err(cases[0], rc, "batch: %s", b->err.c_str());      // the batch is gone; keep the reason
+        pdn_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return PDN_OK;
+}
+
+int pdn_batch_step(pdn_batch *b, int64_t n)
+{
+    if (!b || n < 0) return PDN_EINVAL;
+    (void)hipSetDevice(b->device);
+    int rc;
+    for (size_t i = 0; i < b->cs.size(); ++i) {
+        pdn_ctx *c = b->cs[i];
+        if (c->broken) return berr(b, PDN_EUNSTABLE, "case %zu is unstable", i);
+        if (c->tile != b->tile) {
+            if ((rc = use_tile(c, b->tile))) return batch_case_err(b, i, rc);
+        } else if ((rc = pdn_step(c, 0))) {          // pending (re)initialisation, if any
+            return batch_case_err(b, i, rc);
+        }
+        if ((rc = ensure_history(c, c->gl.step + n))) return batch_case_err(b, i, rc);
+        (void)hipStreamSynchronize(c->stream);
+    }
+    if ((rc = upload_tables(b))) return rc;
+    if (b->graph_tile != b->tile || b->graph_eblocks != b->eblocks || b->graph_cblocks != b->cblocks)
+        if ((rc = build_graph(b))) return rc;
+    int64_t s = 0;
+    for (; s + PDN_BATCH_GRAPH_STEPS <= n; s += PDN_BATCH_GRAPH_STEPS)
+        BHIPCHK(b, hipGraphLaunch(b->exec, b->stream));
+    for (; s < n; ++s) {
+        hipError_t e = launch_batch_step(b, (int)(s & 1), b->stream);
+        if (e != hipSuccess) return berr(b, PDN_EDEVICE, "batched step launch: %s", hipGetErrorString(e));
+    }
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    rc = PDN_OK;
+    for (size_t i = 0; i < b->cs.size(); ++i) {
+        pdn_ctx *c = b->cs[i];
+        if (n & 1) c->cur ^= 1;
+        int r2 = sync_globals_from_device(c);
+        if (r2) return batch_case_err(b, i, r2);
+        if (c->gl.flag_unstable) {
+            c->broken = true;
+            set_err(c, PDN_EUNSTABLE, "non-finite displacement at step %lld", (long long)c->gl.step);
+            if (!rc) rc = berr(b, PDN_EUNSTABLE, "case %zu: non-finite state", i);
+        } else if (c->gl.flag_overflow && !rc) {
+            set_err(c, PDN_ERANGE, "contact reached the edge of the contact search window");
+            rc = berr(b, PDN_ERANGE, "case %zu: contact reached the edge of the search window", i);
+        }
+    }
+    return rc;
+}
+
+int pdn_batch_info(const pdn_batch *b, int32_t *tile_x, int32_t *tile_y, int64_t *n_bulk, int32_t *blocks)
+{
+    if (!b) return PDN_EINVAL;
+    int64_t ne = 0;
+    for (const pdn_ctx *c : b->cs) ne += c->ne;
+    if (tile_x) *tile_x = b->tile >= 0 ? pdn_tile_dims[b->tile][0] : 0;
+    if (tile_y) *tile_y = b->tile >= 0 ? pdn_tile_dims[b->tile][1] : 0;
+    if (n_bulk) *n_bulk = ne;
+    if (blocks) *blocks = b->eblocks;
+    return PDN_OK;
+}
+
+const char *pdn_batch_last_error(const pdn_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+void pdn_batch_destroy(pdn_batch *b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->device);
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->eargs_d) (void)hipFree(b->eargs_d);
+    if (b->cargs_d) (void)hipFree(b->cargs_d);
+    if (b->estart_d) (void)hipFree(b->estart_d);
+    if (b->cstart_d) (void)hipFree(b->cstart_d);
+    delete b;
+}
+
+}  // extern "C"
+

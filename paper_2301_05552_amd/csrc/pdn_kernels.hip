@@ -340,9 +340,9 @@ __device__ void block_reduce_store(double acc[PDN_NTERMS], double *out, double *
     }
 }
 
+// one workgroup's tile of one plate; block partials go to A.partials[tile]
 template <typename R, int TX, int TY>
-__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
-void k_elem_node(ElemArgs<R> A)
+__device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int tile)
 {
     constexpr int NE = TX * TY, NCX = TX + 1, NCY = TY + 1, NC = NCX * NCY;
     constexpr int NT = PDN_TILE_THREADS(TX, TY);
@@ -357,7 +357,6 @@ void k_elem_node(ElemArgs<R> A)
                         : reinterpret_cast<R (*)[3][NC]>(&D64[0][0][0]);
 
     const int t = threadIdx.x;
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
     const int e0x = tx * (TX - 1), e0y = ty * (TY - 1);
     const bool lastx = tx == A.tiles_x - 1, lasty = ty == A.tiles_y - 1;
@@ -564,7 +563,38 @@ void k_elem_node(ElemArgs<R> A)
         if (nown) update_node(k - 1, fin);
     }
     if (nown) update_node(A.K - 1, carry);
-    block_reduce_store<NT>(acc, A.partials + (int64_t)blockIdx.x * PDN_NTERMS, red);
+    block_reduce_store<NT>(acc, A.partials + (int64_t)tile * PDN_NTERMS, red);
+}
+
+template <typename R, int TX, int TY>
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
+void k_elem_node(ElemArgs<R> A)
+{
+    elem_node_tile<R, TX, TY>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// case of global block b in a batch: the last c with start[c] <= b
+__device__ __forceinline__ int batch_case(const int *start, int ncase, int b)
+{
+    int lo = 0, hi = ncase - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// many plates in one launch: tiles of case c are blocks start[c] .. start[c+1)-1
+// (after the XCD remap, so that one case's neighbouring tiles share an L2)
+template <typename R, int TX, int TY>
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
+void k_elem_node_batch(const ElemArgs<R> *__restrict__ args, const int *__restrict__ start, int ncase)
+{
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int c = batch_case(start, ncase, b);
+    const ElemArgs<R> A = args[c];
+    elem_node_tile<R, TX, TY>(A, b - start[c]);
 }
 
 // ---------------------------------------------------------------------------
@@ -587,7 +617,8 @@ __device__ double blk_sum(double v, double *sh)
     return s;
 }
 
-__global__ __launch_bounds__(PDN_K1_THREADS) void k_contact(ContactArgs C)
+// workgroup blk of the nblk workgroups that serve one plate
+__device__ __forceinline__ void contact_block(const ContactArgs &C, const int blk, const int nblk)
 {
     constexpr int NT = PDN_K1_THREADS;
     __shared__ double sh[NT / 64];
@@ -608,11 +639,11 @@ __global__ __launch_bounds__(PDN_K1_THREADS) void k_contact(ContactArgs C)
 
     const int cw = C.ci1 - C.ci0, ch = C.cj1 - C.cj0, nc = cw * ch;
     const int64_t plane = (int64_t)(C.nx + 1) * (C.ny + 1);
-    const int j = blockIdx.x * NT + t;
+    const int j = blk * NT + t;
     double q[PDN_CQ];
     for (int k = 0; k < PDN_CQ; ++k) q[k] = 0.0;
     // slots 0..7: element-kernel partials of the previous level (strided rows)
-    for (int b = j; b < C.nblocks; b += gridDim.x * NT)
+    for (int b = j; b < C.nblocks; b += nblk * NT)
         for (int k = 0; k < PDN_NTERMS; ++k) q[k] += C.partials[(int64_t)b * PDN_NTERMS + k];
     if (j < nc) {
         const int i = C.ci0 + j % cw, jj = C.cj0 + j / cw;
@@ -675,19 +706,19 @@ __global__ __launch_bounds__(PDN_K1_THREADS) void k_contact(ContactArgs C)
         if (t == 0) row[k] = s;
     }
     __syncthreads();
-    if (t < PDN_CQ) C.blk[(int64_t)blockIdx.x * PDN_CQ + t] = row[t];
+    if (t < PDN_CQ) C.blk[(int64_t)blk * PDN_CQ + t] = row[t];
     __threadfence();
     __syncthreads();
     if (t == 0) {
         const unsigned tk = atomicAdd(&G->ticket, 1u);
-        am_last = tk == gridDim.x - 1;
+        am_last = tk == (unsigned)nblk - 1;
     }
     __syncthreads();
     if (!am_last) return;
     __threadfence();
     if (t < PDN_CQ) {
         double s = 0;
-        for (int b = 0; b < (int)gridDim.x; ++b) s += __builtin_nontemporal_load(&C.blk[(int64_t)b * PDN_CQ + t]);
+        for (int b = 0; b < nblk; ++b) s += __builtin_nontemporal_load(&C.blk[(int64_t)b * PDN_CQ + t]);
         row[t] = s;
     }
     __syncthreads();
@@ -737,6 +768,19 @@ __global__ __launch_bounds__(PDN_K1_THREADS) void k_contact(ContactArgs C)
         G->first = 0;
         G->ticket = 0;
     }
+}
+
+__global__ __launch_bounds__(PDN_K1_THREADS) void k_contact(ContactArgs C)
+{
+    contact_block(C, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(PDN_K1_THREADS)
+void k_contact_batch(const ContactArgs *__restrict__ args, const int *__restrict__ start, int ncase)
+{
+    const int c = batch_case(start, ncase, blockIdx.x);
+    const ContactArgs C = args[c];
+    contact_block(C, blockIdx.x - start[c], start[c + 1] - start[c]);
 }
 
 // candidate bookkeeping at (re)initialisation
@@ -867,6 +911,38 @@ int elem_node_lds_bytes(int mixed, int tile) { return mixed ? lds_r<float>(tile)
 
 template hipError_t launch_elem_node<float>(const ElemArgs<float> &, int, hipStream_t);
 template hipError_t launch_elem_node<double>(const ElemArgs<double> &, int, hipStream_t);
+
+template <typename R, int TX, int TY>
+static hipError_t launch_enb(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_elem_node_batch<R, TX, TY>), dim3(nblocks), dim3(PDN_TILE_THREADS(TX, TY)), 0, s, args,
+                       start, ncase);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_elem_node_batch(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
+                                  hipStream_t s)
+{
+    if (ncase < 1 || nblocks < 1) return hipErrorInvalidValue;
+    switch (tile) {
+    case PDN_TILE_16x16: return launch_enb<R, 16, 16>(args, start, ncase, nblocks, s);
+    case PDN_TILE_32x8: return launch_enb<R, 32, 8>(args, start, ncase, nblocks, s);
+    case PDN_TILE_8x8: return launch_enb<R, 8, 8>(args, start, ncase, nblocks, s);
+    case PDN_TILE_15x15: return launch_enb<R, 15, 15>(args, start, ncase, nblocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_elem_node_batch<float>(const ElemArgs<float> *, const int *, int, int, int, hipStream_t);
+template hipError_t launch_elem_node_batch<double>(const ElemArgs<double> *, const int *, int, int, int,
+                                                   hipStream_t);
+
+hipError_t launch_contact_batch(const ContactArgs *args, const int *start, int ncase, int nblocks, hipStream_t s)
+{
+    if (ncase < 1 || nblocks < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_contact_batch, dim3(nblocks), dim3(PDN_K1_THREADS), 0, s, args, start, ncase);
+    return hipGetLastError();
+}
 
 int contact_blocks(const ContactArgs &c)
 {

@@ -12,6 +12,11 @@ static const int pdn_tile_dims[PDN_TILE_COUNT][2] = {{16, 16}, {32, 8}, {8, 8}, 
 namespace pdn {
 template <typename R>
 hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, hipStream_t s);
+// batched launches: case c owns blocks start[c] .. start[c+1]-1 (args and start in device memory)
+template <typename R>
+hipError_t launch_elem_node_batch(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
+                                  hipStream_t s);
+hipError_t launch_contact_batch(const ContactArgs *args, const int *start, int ncase, int nblocks, hipStream_t s);
 int contact_blocks(const ContactArgs &c);
 int elem_node_lds_bytes(int mixed, int tile);   // static LDS of one element/node workgroup (-1 on error)
 hipError_t launch_contact(const ContactArgs &c, hipStream_t s);
