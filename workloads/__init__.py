@@ -270,3 +270,52 @@ def synthetic_state(n_nodes: int, n_gp: int, n_coh_pairs: int, seed: int,
     r = 1.0 + g.uniform(0.0, max(r_max - 1.0, 0.0), 4 * n_gp)
     rd = g.uniform(0.0, rd_max, n_coh_pairs)
     return dict(disp=d, vel=v, r=r, rd=rd)
+
+
+# ---------------------------------------------------------------------------
+# strain paths for the constitutive surrogate's training set
+# ---------------------------------------------------------------------------
+
+SUR_SEED = 0x5EED5EED
+SUR_INCREMENTS = 32
+SUR_MAX_ONSET = 3.0
+
+
+def sur_path(p: int, n_inc: int = SUR_INCREMENTS, seed: int = SUR_SEED) -> np.ndarray:
+    """Strain path p in onset-scaled strain space, shape (n_inc, 6).
+
+    SplitMix64(seed + p) draws, in this order: a direction u (six uniforms on
+    [-1, 1), normalised); then for even p (monotone) an amplitude A ~ U[0, 3)
+    and the path is A (i / n_inc) u, i = 1..n_inc; for odd p (cyclic) a count
+    of reversals nr = 2 + floor(3 U) (2..4) and nr + 1 turning amplitudes a_j =
+    (-1)^(j+1) 3 U, j = 1..nr+1, visited from 0 in order along u with
+    n_inc // (nr + 1) increments per leg (the remainder added to the last).
+    Every operation is one correctly rounded double operation, so other
+    implementations of the recipe reproduce it bit for bit."""
+    g = SplitMix64(seed + p)
+    u = [2.0 * g.uniform() - 1.0 for _ in range(6)]
+    nrm = math.sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2] + u[3] * u[3] + u[4] * u[4] + u[5] * u[5])
+    u = [1.0, 0.0, 0.0, 0.0, 0.0, 0.0] if nrm == 0.0 else [c / nrm for c in u]
+    amp = []
+    if p % 2 == 0:
+        A = SUR_MAX_ONSET * g.uniform()
+        for i in range(1, n_inc + 1):
+            amp.append(A * (i / n_inc))
+    else:
+        nr = 2 + int(3.0 * g.uniform())
+        legs = nr + 1
+        a = [0.0] + [(1.0 if j % 2 == 1 else -1.0) * (SUR_MAX_ONSET * g.uniform()) for j in range(1, legs + 1)]
+        per = n_inc // legs
+        for j in range(1, legs + 1):
+            nj = per + (n_inc - per * legs if j == legs else 0)
+            for i in range(1, nj + 1):
+                amp.append(a[j - 1] + (a[j] - a[j - 1]) * (i / nj))
+    return np.array([[s * c for c in u] for s in amp], dtype=np.float64)
+
+
+def sur_scales(mat: dict) -> tuple:
+    """(E_k, X_k) of the surrogate's normalisation: strain eps_k * E_k / X_k,
+    stress sigma_k / X_k, components 11, 22, 33, 23, 13, 12."""
+    E = (mat["E1"], mat["E2"], mat["E2"], mat["G23"], mat["G12"], mat["G12"])
+    X = (mat["XT"], mat["YT"], mat["YT"], mat["SL"], mat["SL"], mat["SL"])
+    return E, X
