@@ -191,6 +191,69 @@ void pdn_batch_destroy(pdn_batch *b);
 const char *pdn_last_error(const pdn_ctx *ctx);
 void pdn_destroy(pdn_ctx *ctx);
 
+/* ---- constitutive surrogate ------------------------------------------------
+ * A network 10 -> 64 -> 64 -> 64 -> 10 (SiLU) replaces the intralaminar update
+ * of Section 2.3.1 (Algorithm 4) on chosen plies, evaluated with bf16 matrix
+ * operands and fp32 accumulation; the exact law stays the fallback.
+ * Inputs: strain_k * E_k / X_k (material frame, Voigt 11, 22, 33, 23, 13, 12,
+ * engineering shear) with (E_k, X_k) = (E1, XT), (E2, YT), (E2, YT), (G23, SL),
+ * (G12, SL), (G12, SL), then s_N = 1 - 1/r_N for the thresholds r1+, r1-, r2+,
+ * r2-.  Outputs: stress_k / X_k, then the new s_N through a sigmoid.
+ * Parameters: PDN_SUR_NPARAM floats, W1[10][64], b1[64], W2[64][64], b2[64],
+ * W3[64][64], b3[64], W4[64][10], b4[10] (W stored [in][out]).
+ * The context-free calls below return negative codes with the reason in
+ * pdn_global_last_error() (per host thread). */
+#define PDN_SUR_NPARAM 9674
+
+typedef struct {
+    int32_t device;
+    void *stream;           /* hipStream_t, NULL = null stream */
+    int64_t n_paths;        /* strain paths in the data set (e.g. 10,000,000) */
+    int32_t increments;     /* increments per path, 1..64 (e.g. 32) */
+    uint64_t seed;          /* path recipe seed (e.g. 0x5EED5EED) */
+    double val_fraction;    /* last fraction of the paths held out for validation */
+    int64_t steps;          /* Adam steps */
+    int32_t batch;          /* samples per step, a multiple of 128 */
+    double lr, lr_final;    /* cosine schedule from lr to lr_final (0: lr / 100) */
+    uint64_t init_seed;     /* Glorot-uniform initial weights */
+} pdn_sur_train;
+
+typedef struct {
+    double loss_val_initial;   /* validation mean square error per output, before training */
+    double loss_val;           /* ... after training */
+    double loss_train;         /* training-set error after training (first 4M samples) */
+    double data_seconds, train_seconds;
+    int64_t samples_train, samples_val;
+} pdn_sur_report;
+
+/* Generate the data set on the device from the exact law (FP64) along the
+ * seeded strain paths (monotone for even path index, 2-4 reversals for odd,
+ * up to 3x onset), at crack-band length `crack_band`, and train the network
+ * on it with the library's own matrix-core forward and backward kernels and
+ * Adam.  Writes PDN_SUR_NPARAM weights. */
+int pdn_surrogate_train(const pdn_sur_train *opt, const pdn_material *m, double crack_band, float *weights,
+                        pdn_sur_report *rep);
+/* Use a trained network on ply `ply` (-1: every ply with a damage law) of the
+ * context.  A point keeps the exact law when a damage variable of its incoming
+ * thresholds exceeds dmg_thresh (e.g. 0.05), or when the network's stress
+ * differs from the nominal stress of its own new thresholds by more than
+ * res_thresh (e.g. 1e-3) relative to |C0 strain|.  pdn_info reports the
+ * fraction of updates that used the exact law.  ESTATE for a ply without a
+ * damage law.  Legal mid-run. */
+int pdn_surrogate_set(pdn_ctx *ctx, int32_t ply, const float *weights, int64_t n, double dmg_thresh,
+                      double res_thresh);
+/* Forward pass on n points: x is n x 10 inputs, y receives n x 10 outputs. */
+int pdn_surrogate_eval(int32_t device, void *stream, const float *weights, const float *x, int64_t n, float *y);
+/* Mean square error over n x 10 outputs against targets t, and its gradient
+ * with respect to the PDN_SUR_NPARAM parameters (the training kernel's). */
+int pdn_surrogate_grad(int32_t device, void *stream, const float *weights, const float *x, const float *t,
+                       int64_t n, float *grad, double *loss);
+/* Records of paths p0 .. p0+n_paths-1 of the data set (20 floats each:
+ * 10 inputs, 10 exact outputs; increments of a path consecutive). */
+int pdn_surrogate_data(int32_t device, void *stream, const pdn_material *m, double crack_band, uint64_t seed,
+                       int64_t p0, int64_t n_paths, int32_t increments, float *records);
+const char *pdn_global_last_error(void);
+
 #ifdef __cplusplus
 }
 #endif

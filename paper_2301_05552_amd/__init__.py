@@ -104,6 +104,14 @@ def lib():
             "pdn_batch_info": [vp, P(C.c_int32), P(C.c_int32), P(i64), P(C.c_int32)],
             "pdn_batch_last_error": [vp],
             "pdn_batch_destroy": [vp],
+            "pdn_surrogate_train": [P(SurTrain), P(Material), C.c_double, P(C.c_float), P(SurReport)],
+            "pdn_surrogate_set": [vp, C.c_int32, P(C.c_float), i64, C.c_double, C.c_double],
+            "pdn_surrogate_eval": [C.c_int32, vp, P(C.c_float), P(C.c_float), i64, P(C.c_float)],
+            "pdn_surrogate_grad": [C.c_int32, vp, P(C.c_float), P(C.c_float), P(C.c_float), i64, P(C.c_float),
+                                   P(C.c_double)],
+            "pdn_surrogate_data": [C.c_int32, vp, P(Material), C.c_double, C.c_uint64, i64, i64, C.c_int32,
+                                   P(C.c_float)],
+            "pdn_global_last_error": [],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -113,12 +121,82 @@ def lib():
         L.pdn_destroy.restype = None
         L.pdn_batch_last_error.restype = C.c_char_p
         L.pdn_batch_destroy.restype = None
+        L.pdn_global_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
 
 def _dp(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+SUR_NPARAM = 9674
+SUR_SEED = 0x5EED5EED
+
+
+class SurTrain(C.Structure):
+    _fields_ = [("device", C.c_int32), ("stream", C.c_void_p), ("n_paths", C.c_int64), ("increments", C.c_int32),
+                ("seed", C.c_uint64), ("val_fraction", C.c_double), ("steps", C.c_int64), ("batch", C.c_int32),
+                ("lr", C.c_double), ("lr_final", C.c_double), ("init_seed", C.c_uint64)]
+
+
+class SurReport(C.Structure):
+    _fields_ = [("loss_val_initial", C.c_double), ("loss_val", C.c_double), ("loss_train", C.c_double),
+                ("data_seconds", C.c_double), ("train_seconds", C.c_double), ("samples_train", C.c_int64),
+                ("samples_val", C.c_int64)]
+
+
+def _gchk(rc):
+    if rc != 0:
+        raise PdnError(rc, lib().pdn_global_last_error().decode())
+
+
+def _material(m: dict) -> Material:
+    return Material(**{f: (int(m[f]) if f == "law" else float(m[f])) for f, _ in Material._fields_})
+
+
+def surrogate_train(mat: dict, crack_band: float, *, n_paths=10_000_000, increments=32, seed=SUR_SEED,
+                    val_fraction=0.1, steps=4000, batch=65536, lr=2e-3, lr_final=2e-5, init_seed=1,
+                    device=0, stream=None):
+    """Generate the data set from the exact law on the device and train the
+    surrogate there (pdn_surrogate_train).  Returns (weights, report)."""
+    o = SurTrain(device=device, stream=stream, n_paths=n_paths, increments=increments, seed=seed,
+                 val_fraction=val_fraction, steps=steps, batch=batch, lr=lr, lr_final=lr_final,
+                 init_seed=init_seed)
+    w = np.zeros(SUR_NPARAM, dtype=np.float32)
+    rep = SurReport()
+    _gchk(lib().pdn_surrogate_train(C.byref(o), C.byref(_material(mat)), crack_band, _fp(w), C.byref(rep)))
+    return w, {f: getattr(rep, f) for f, _ in SurReport._fields_}
+
+
+def surrogate_eval(w, x, device=0, stream=None):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 10)
+    y = np.zeros_like(x)
+    _gchk(lib().pdn_surrogate_eval(device, stream, _fp(w), _fp(x), x.shape[0], _fp(y)))
+    return y
+
+
+def surrogate_grad(w, x, t, device=0, stream=None):
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 10)
+    t = np.ascontiguousarray(t, dtype=np.float32).reshape(-1, 10)
+    g = np.zeros(SUR_NPARAM, dtype=np.float32)
+    loss = C.c_double()
+    _gchk(lib().pdn_surrogate_grad(device, stream, _fp(w), _fp(x), _fp(t), x.shape[0], _fp(g), C.byref(loss)))
+    return g, loss.value
+
+
+def surrogate_data(mat: dict, crack_band: float, p0: int, n_paths: int, increments=32, seed=SUR_SEED,
+                   device=0, stream=None):
+    out = np.zeros((n_paths * increments, 20), dtype=np.float32)
+    _gchk(lib().pdn_surrogate_data(device, stream, C.byref(_material(mat)), crack_band, seed, p0, n_paths,
+                                   increments, _fp(out)))
+    return out
 
 
 class Simulation:
@@ -247,6 +325,10 @@ class Simulation:
         a, b = C.c_double(), C.c_double()
         self._chk(lib().pdn_kernel_times(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def surrogate_set(self, ply: int, w, dmg_thresh: float = 0.05, res_thresh: float = 1e-3):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._chk(lib().pdn_surrogate_set(self.h, ply, _fp(w), w.size, dmg_thresh, res_thresh))
 
     def autotune(self):
         tx, ty = C.c_int32(), C.c_int32()

@@ -6,6 +6,7 @@
 #include "pdn.h"
 #include "pdn_internal.h"
 #include "pdn_launch.h"
+#include "pdn_mlp.h"
 
 #include <hip/hip_runtime.h>
 
@@ -74,6 +75,12 @@ struct pdn_ctx {
     double *dmg_d = nullptr;
     size_t dmg_n = 0;
     std::vector<uint8_t> bcb;
+    // constitutive surrogate: packed networks, network of each ply (-1 none)
+    uint4 *sur_d = nullptr;
+    int n_nets = 0;
+    bool use_sur = false;             // some ply evaluates a network (kernel variant)
+    std::vector<int> ply_net;
+    double sur_dmg = 0.05, sur_res = 1e-3;
     // timing
     bool timing = false;
     double t_en_ms = 0, t_ct_ms = 0;
@@ -148,7 +155,7 @@ double stiffness_max(const pdn_material &m, double C[3][3])
 }
 
 template <typename R>
-PlyC<R> make_ply(const pdn_material &m, double ang_deg)
+PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1)
 {
     PlyC<R> P{};
     double C[3][3];
@@ -173,7 +180,9 @@ PlyC<R> make_ply(const pdn_material &m, double ang_deg)
     P.etaT = (R)(-1.0 / std::tan(2 * a0));
     P.kEtaL = (R)(-std::cos(2 * a0) / (std::cos(a0) * std::cos(a0)));
     P.rho = (R)m.rho;
-    P.law = m.law == PDN_LAW_ELASTIC ? 0 : 1;
+    // a surrogate ply without a network keeps the exact law
+    P.law = m.law == PDN_LAW_ELASTIC ? 0 : (m.law == PDN_LAW_CDM_SURROGATE && net >= 0 ? 2 : 1);
+    P.sur = P.law == 2 ? net : 0;
     if (P.law) {
         const double kst = std::cos(a0) * (std::sin(a0) + std::cos(a0) / std::tan(2 * a0));
         const double etat = -1.0 / std::tan(2 * a0);
@@ -263,14 +272,17 @@ int prepare(pdn_ctx *c)
     if ((rc = upload(c, c->imx_d, c->imx))) return rc;
     if ((rc = upload(c, c->imy_d, c->imy))) return rc;
     if ((rc = upload(c, c->imz_d, c->imz))) return rc;
+    c->use_sur = false;
+    for (int p = 0; p < c->P; ++p)
+        if (c->mat[p].law == PDN_LAW_CDM_SURROGATE && c->ply_net[p] >= 0) c->use_sur = true;
     if (c->precision == PDN_MIXED) {
         std::vector<PlyC<float>> pc;
-        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<float>(c->mat[p], c->ang[p]));
+        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<float>(c->mat[p], c->ang[p], c->ply_net[p]));
         HIPCHK(c, hipMemcpyAsync(c->ply, pc.data(), pc.size() * sizeof(pc[0]), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     } else {
         std::vector<PlyC<double>> pc;
-        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<double>(c->mat[p], c->ang[p]));
+        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<double>(c->mat[p], c->ang[p], c->ply_net[p]));
         HIPCHK(c, hipMemcpyAsync(c->ply, pc.data(), pc.size() * sizeof(pc[0]), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -319,6 +331,9 @@ ElemArgs<R> elem_args(pdn_ctx *c, int in, int out)
     a.bc_bottom = c->bcb_d;
     a.fside = c->fside_d;
     a.partials = c->partials_d;
+    a.mlp = c->sur_d;
+    a.sur_dmg = (float)c->sur_dmg;
+    a.sur_res = (float)c->sur_res;
     return a;
 }
 
@@ -343,8 +358,10 @@ ContactArgs contact_args(pdn_ctx *c, int buf)
 int launch_en(pdn_ctx *c, int in, int out)
 {
     hipError_t e;
-    if (c->precision == PDN_MIXED) e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out), c->tile, c->stream);
-    else e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out), c->tile, c->stream);
+    if (c->precision == PDN_MIXED)
+        e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out), c->tile, c->use_sur, c->stream);
+    else
+        e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out), c->tile, c->use_sur, c->stream);
     if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "element/node kernel launch: %s", hipGetErrorString(e));
     return PDN_OK;
 }
@@ -353,7 +370,7 @@ bool tile_fits(pdn_ctx *c, int tile)
 {
     int maxlds = 0;
     if (hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess) return false;
-    const int lds = pdn::elem_node_lds_bytes(c->precision == PDN_MIXED, tile);
+    const int lds = pdn::elem_node_lds_bytes(c->precision == PDN_MIXED, tile, c->use_sur);
     return lds > 0 && lds <= maxlds;
 }
 
@@ -384,7 +401,8 @@ void free_all(pdn_ctx *c)
     void *ps[] = {c->d[0], c->d[1], c->v[0], c->v[1], c->r, c->rd, c->hx, c->hy, c->ihx, c->ihy, c->ply, c->xs_d, c->ys_d,
                   c->mx_d, c->my_d, c->mz_d, c->imx_d, c->imy_d, c->imz_d, c->blk_d,
                   c->layers_d, c->bulk_layer_d, c->coh_layer_d, c->bcb_d,
-                  c->active_d, c->vprev_d, c->fcprev_d, c->fside_d, c->partials_d, c->gl_d, c->hist_d, c->dmg_d};
+                  c->active_d, c->vprev_d, c->fcprev_d, c->fside_d, c->partials_d, c->gl_d, c->hist_d, c->dmg_d,
+                  c->sur_d};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -463,6 +481,7 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
     c->ang.assign(D.ply_angle_deg, D.ply_angle_deg + D.n_plies);
     c->mat.assign(c->P, pdn_material{});
     c->mat_set.assign(c->P, 0);
+    c->ply_net.assign(c->P, -1);
     // grid lines
     c->xs.resize(c->nx + 1);
     c->ys.resize(c->ny + 1);
@@ -643,7 +662,10 @@ int pdn_material_set(pdn_ctx *c, int32_t ply, const pdn_material *m)
     for (int p = 0; p < c->P; ++p)
         if (ply < 0 || p == ply) { c->mat[p] = *m; c->mat_set[p] = 1; }
     c->ready = false;
-    if (c->gl.step > 0) c->needs_init = true;
+    if (c->gl.step > 0) {           // mid-run: re-run the element pass, keep the contact state
+        c->needs_init = true;
+        c->loaded_state = true;
+    }
     return PDN_OK;
 }
 
@@ -851,7 +873,7 @@ int pdn_info_get(const pdn_ctx *c, pdn_info *o)
     o->n_candidates = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
     o->steps = c->gl.step; o->reset_passes = c->gl.reset_passes; o->released = c->gl.released;
     o->active = c->gl.active; o->max_passes = c->gl.max_passes;
-    o->fallback_fraction = (c->gl.step > 0 && c->ne > 0) ? c->gl.fallback_gp / ((double)c->gl.step * c->ne) : 0.0;
+    o->fallback_fraction = c->gl.sur_gp > 0 ? c->gl.fallback_gp / c->gl.sur_gp : 0.0;
     o->precision = c->precision;
     o->tile_x = pdn_tile_dims[c->tile][0];
     o->tile_y = pdn_tile_dims[c->tile][1];
@@ -1113,8 +1135,10 @@ struct pdn_batch {
     std::vector<unsigned char> eargs_h;
     std::vector<ContactArgs> cargs_h;
     int eblocks = 0, cblocks = 0;
-    hipGraphExec_t exec = nullptr;       // PDN_BATCH_GRAPH_STEPS steps, built for (tile, eblocks, cblocks)
+    bool sur = false;                    // some case evaluates a surrogate network
+    hipGraphExec_t exec = nullptr;       // PDN_BATCH_GRAPH_STEPS steps, built for (tile, sur, eblocks, cblocks)
     int graph_tile = -1, graph_eblocks = 0, graph_cblocks = 0;
+    bool graph_sur = false;
 };
 
 #define PDN_BATCH_GRAPH_STEPS 8          // even: a replay returns every case to the same buffer parity
@@ -1154,7 +1178,7 @@ std::map<std::string, int> &tune_cache()
 std::string shape_key(const pdn_ctx *c)
 {
     char k[96];
-    snprintf(k, sizeof k, "%d:%d:%d:%d:%d;", c->device, c->precision, c->nx, c->ny, c->K);
+    snprintf(k, sizeof k, "%d:%d:%d:%d:%d:%d;", c->device, c->precision, (int)c->use_sur, c->nx, c->ny, c->K);
     return k;
 }
 
@@ -1215,6 +1239,8 @@ int upload_tables(pdn_batch *b)
     }
     b->eblocks = b->estart[n];
     b->cblocks = b->cstart[n];
+    b->sur = false;
+    for (pdn_ctx *c : b->cs) b->sur = b->sur || c->use_sur;
     if (b->precision == PDN_MIXED) fill_eargs<float>(b);
     else fill_eargs<double>(b);
     if (!b->eargs_d) {
@@ -1237,9 +1263,9 @@ hipError_t launch_batch_elem(pdn_batch *b, int parity, hipStream_t s)
     const int n = (int)b->cs.size();
     if (b->precision == PDN_MIXED)
         return pdn::launch_elem_node_batch<float>(reinterpret_cast<ElemArgs<float> *>(b->eargs_d) + parity * n,
-                                                  b->estart_d, n, b->eblocks, b->tile, s);
+                                                  b->estart_d, n, b->eblocks, b->tile, b->sur, s);
     return pdn::launch_elem_node_batch<double>(reinterpret_cast<ElemArgs<double> *>(b->eargs_d) + parity * n,
-                                               b->estart_d, n, b->eblocks, b->tile, s);
+                                               b->estart_d, n, b->eblocks, b->tile, b->sur, s);
 }
 
 // one step of every case: contact pass, then element/node pass
@@ -1308,6 +1334,7 @@ int build_graph(pdn_batch *b)
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return berr(b, PDN_EDEVICE, "step graph instantiation: %s", hipGetErrorString(e));
     b->graph_tile = b->tile;
+    b->graph_sur = b->sur;
     b->graph_eblocks = b->eblocks;
     b->graph_cblocks = b->cblocks;
     return PDN_OK;
@@ -1419,7 +1446,8 @@ int pdn_batch_step(pdn_batch *b, int64_t n)
         (void)hipStreamSynchronize(c->stream);
     }
     if ((rc = upload_tables(b))) return rc;
-    if (b->graph_tile != b->tile || b->graph_eblocks != b->eblocks || b->graph_cblocks != b->cblocks)
+    if (b->graph_tile != b->tile || b->graph_sur != b->sur || b->graph_eblocks != b->eblocks ||
+        b->graph_cblocks != b->cblocks)
         if ((rc = build_graph(b))) return rc;
     int64_t s = 0;
     for (; s + PDN_BATCH_GRAPH_STEPS <= n; s += PDN_BATCH_GRAPH_STEPS)
@@ -1473,6 +1501,309 @@ void pdn_batch_destroy(pdn_batch *b)
     if (b->estart_d) (void)hipFree(b->estart_d);
     if (b->cstart_d) (void)hipFree(b->cstart_d);
     delete b;
+}
+
+}  // extern "C"
+
+// ---- constitutive surrogate ----------------------------------------------
+namespace {
+
+thread_local std::string g_err;
+
+int gerr(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define GHIPCHK(call)                                                                           \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return gerr(e_ == hipErrorOutOfMemory ? PDN_ENOMEM : PDN_EDEVICE, "%s: %s", #call,  \
+                        hipGetErrorString(e_));                                                 \
+    } while (0)
+
+// device buffers released on scope exit
+struct DevMem {
+    std::vector<void *> ps;
+    ~DevMem()
+    {
+        for (void *p : ps) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t get(T **p, size_t bytes)
+    {
+        *p = nullptr;
+        hipError_t e = hipMalloc((void **)p, bytes ? bytes : 1);
+        if (e == hipSuccess) ps.push_back((void *)*p);
+        return e;
+    }
+};
+
+// Glorot-uniform weights from SplitMix64(seed), zero biases
+void sur_init(uint64_t seed, std::vector<float> &w)
+{
+    w.assign(SUR_NPARAM, 0.f);
+    uint64_t st = seed;
+    auto uni = [&]() {
+        st += 0x9E3779B97F4A7C15ull;
+        uint64_t z = st;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    };
+    const int offs[4] = {SUR_W1, SUR_W2, SUR_W3, SUR_W4};
+    const int fin[4] = {SUR_NIN, SUR_NH, SUR_NH, SUR_NH}, fout[4] = {SUR_NH, SUR_NH, SUR_NH, SUR_NOUT};
+    for (int l = 0; l < 4; ++l) {
+        const double a = std::sqrt(6.0 / (fin[l] + fout[l]));
+        for (int i = 0; i < fin[l] * fout[l]; ++i) w[offs[l] + i] = (float)(a * (2.0 * uni() - 1.0));
+    }
+}
+
+PlyC<double> sur_ply(const pdn_material &m)
+{
+    pdn_material e = m;
+    e.law = PDN_LAW_CDM;
+    return make_ply<double>(e, 0.0);
+}
+
+bool sur_material_ok(const pdn_material *m)
+{
+    return m && m->E1 > 0 && m->E2 > 0 && m->G12 > 0 && m->G23 > 0 && m->XT > 0 && m->XC > 0 && m->YT > 0 &&
+           m->YC > 0 && m->SL > 0 && m->GXT > 0 && m->GXC > 0 && m->GYT > 0 && m->GYC > 0 && m->GSL > 0;
+}
+
+int sur_loss_host(const void *pk, const float *data, int64_t i0, int64_t n, double *part, hipStream_t s, double *out)
+{
+    if (n <= 0) { *out = 0.0; return PDN_OK; }
+    GHIPCHK(pdn::launch_sur_loss(pk, data, i0, n, part, s));
+    std::vector<double> h(pdn::sur_loss_blocks(n));
+    GHIPCHK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+    double t = 0;
+    for (double v : h) t += v;
+    *out = t / ((double)n * SUR_NOUT);
+    return PDN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pdn_global_last_error(void) { return g_err.c_str(); }
+
+int pdn_surrogate_data(int32_t device, void *stream, const pdn_material *m, double crack_band, uint64_t seed,
+                       int64_t p0, int64_t n_paths, int32_t increments, float *records)
+{
+    if (!sur_material_ok(m) || !(crack_band > 0) || p0 < 0 || n_paths < 1 || increments < 1 || increments > 64 ||
+        !records)
+        return gerr(PDN_EINVAL, "surrogate data: invalid argument");
+    GHIPCHK(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)stream;
+    DevMem mem;
+    float *out;
+    const size_t bytes = (size_t)n_paths * increments * 20 * sizeof(float);
+    GHIPCHK(mem.get(&out, bytes));
+    const double vol = crack_band * crack_band * crack_band;
+    GHIPCHK(pdn::launch_sur_data(sur_ply(*m), vol, seed, p0, n_paths, increments, out, s));
+    GHIPCHK(hipMemcpyAsync(records, out, bytes, hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+    return PDN_OK;
+}
+
+int pdn_surrogate_eval(int32_t device, void *stream, const float *weights, const float *x, int64_t n, float *y)
+{
+    if (!weights || !x || !y || n < 0) return gerr(PDN_EINVAL, "surrogate eval: invalid argument");
+    if (n == 0) return PDN_OK;
+    GHIPCHK(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)stream;
+    DevMem mem;
+    float *w, *xd, *yd;
+    void *pk;
+    GHIPCHK(mem.get(&w, SUR_NPARAM * sizeof(float)));
+    GHIPCHK(mem.get(&pk, SUR_PACK_BYTES));
+    GHIPCHK(mem.get(&xd, n * SUR_NIN * sizeof(float)));
+    GHIPCHK(mem.get(&yd, n * SUR_NOUT * sizeof(float)));
+    GHIPCHK(hipMemcpyAsync(w, weights, SUR_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    GHIPCHK(hipMemcpyAsync(xd, x, n * SUR_NIN * sizeof(float), hipMemcpyHostToDevice, s));
+    GHIPCHK(pdn::launch_sur_pack(w, pk, s));
+    GHIPCHK(pdn::launch_sur_eval(pk, xd, n, yd, s));
+    GHIPCHK(hipMemcpyAsync(y, yd, n * SUR_NOUT * sizeof(float), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+    return PDN_OK;
+}
+
+int pdn_surrogate_grad(int32_t device, void *stream, const float *weights, const float *x, const float *t,
+                       int64_t n, float *grad, double *loss)
+{
+    if (!weights || !x || !t || !grad || n < 1) return gerr(PDN_EINVAL, "surrogate grad: invalid argument");
+    GHIPCHK(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> rec((size_t)n * 20);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 10; ++k) {
+            rec[i * 20 + k] = x[i * 10 + k];
+            rec[i * 20 + 10 + k] = t[i * 10 + k];
+        }
+    const int nwg = pdn::sur_grad_blocks(n, 1);
+    DevMem mem;
+    float *w, *data, *part;
+    void *pk;
+    GHIPCHK(mem.get(&w, SUR_NPARAM * sizeof(float)));
+    GHIPCHK(mem.get(&pk, SUR_PACK_BYTES));
+    GHIPCHK(mem.get(&data, rec.size() * sizeof(float)));
+    GHIPCHK(mem.get(&part, (size_t)nwg * (SUR_NPARAM + 1) * sizeof(float)));
+    GHIPCHK(hipMemcpyAsync(w, weights, SUR_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    GHIPCHK(hipMemcpyAsync(data, rec.data(), rec.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    GHIPCHK(pdn::launch_sur_pack(w, pk, s));
+    GHIPCHK(pdn::launch_sur_grad(pk, data, n, 0, n, 1, 0, 0, (float)(1.0 / ((double)n * SUR_NOUT)), part, s));
+    std::vector<float> h((size_t)nwg * (SUR_NPARAM + 1));
+    GHIPCHK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+    double l = 0;
+    for (int p = 0; p <= SUR_NPARAM; ++p) {
+        double g = 0;
+        for (int b = 0; b < nwg; ++b) g += h[(size_t)b * (SUR_NPARAM + 1) + p];
+        if (p < SUR_NPARAM) grad[p] = (float)g;
+        else l = g;
+    }
+    if (loss) *loss = l / ((double)n * SUR_NOUT);
+    return PDN_OK;
+}
+
+int pdn_surrogate_train(const pdn_sur_train *o, const pdn_material *m, double crack_band, float *weights,
+                        pdn_sur_report *rep)
+{
+    if (!o || !sur_material_ok(m) || !(crack_band > 0) || !weights || o->n_paths < 2 || o->increments < 1 ||
+        o->increments > 64 || o->steps < 0 || o->batch < 128 || o->batch % 128 || !(o->lr > 0) ||
+        !(o->val_fraction > 0 && o->val_fraction < 1))
+        return gerr(PDN_EINVAL, "surrogate training: invalid argument");
+    GHIPCHK(hipSetDevice(o->device));
+    hipStream_t s = (hipStream_t)o->stream;
+    const int64_t n_val_paths = std::max<int64_t>(1, (int64_t)(o->n_paths * o->val_fraction));
+    const int64_t n_train_paths = o->n_paths - n_val_paths;
+    if (n_train_paths < 1) return gerr(PDN_EINVAL, "surrogate training: no training paths");
+    const int64_t n_all = o->n_paths * o->increments, n_train = n_train_paths * o->increments;
+    const int nblk = std::max(1, o->batch / (128 * 256));
+    const int nwg = pdn::sur_grad_blocks(o->batch, nblk);
+    DevMem mem;
+    float *data, *w, *mm, *vv, *part, *lossd;
+    double *lpart;
+    void *pk;
+    GHIPCHK(mem.get(&data, (size_t)n_all * 20 * sizeof(float)));
+    GHIPCHK(mem.get(&w, SUR_NPARAM * sizeof(float)));
+    GHIPCHK(mem.get(&mm, SUR_NPARAM * sizeof(float)));
+    GHIPCHK(mem.get(&vv, SUR_NPARAM * sizeof(float)));
+    GHIPCHK(mem.get(&pk, SUR_PACK_BYTES));
+    GHIPCHK(mem.get(&part, (size_t)nwg * (SUR_NPARAM + 1) * sizeof(float)));
+    GHIPCHK(mem.get(&lossd, std::max<int64_t>(1, o->steps) * sizeof(float)));
+    GHIPCHK(mem.get(&lpart, (size_t)pdn::sur_loss_blocks(std::max(n_all - n_train, n_train)) * sizeof(double)));
+    hipEvent_t e0, e1, e2;
+    GHIPCHK(hipEventCreate(&e0));
+    GHIPCHK(hipEventCreate(&e1));
+    GHIPCHK(hipEventCreate(&e2));
+    GHIPCHK(hipEventRecord(e0, s));
+    GHIPCHK(pdn::launch_sur_data(sur_ply(*m), crack_band * crack_band * crack_band, o->seed, 0, o->n_paths,
+                                 o->increments, data, s));
+    GHIPCHK(hipEventRecord(e1, s));
+    std::vector<float> w0;
+    sur_init(o->init_seed, w0);
+    GHIPCHK(hipMemcpyAsync(w, w0.data(), SUR_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    GHIPCHK(hipMemsetAsync(mm, 0, SUR_NPARAM * sizeof(float), s));
+    GHIPCHK(hipMemsetAsync(vv, 0, SUR_NPARAM * sizeof(float), s));
+    GHIPCHK(pdn::launch_sur_pack(w, pk, s));
+    double val0 = 0;
+    int rc = sur_loss_host(pk, data, n_train, n_all - n_train, lpart, s, &val0);
+    if (rc) return rc;
+    const float b1 = 0.9f, b2 = 0.999f;
+    double p1 = 1, p2 = 1;
+    const double lr_end = o->lr_final > 0 ? o->lr_final : 0.01 * o->lr;
+    GHIPCHK(hipEventRecord(e1, s));
+    for (int64_t t = 0; t < o->steps; ++t) {
+        p1 *= b1;
+        p2 *= b2;
+        const double lr = lr_end + 0.5 * (o->lr - lr_end) * (1.0 + std::cos(M_PI * (double)t / (double)o->steps));
+        GHIPCHK(pdn::launch_sur_grad(pk, data, n_train, t * (int64_t)o->batch, o->batch, nblk, 1,
+                                     o->seed ^ 0x5A17C0DEull, (float)(1.0 / ((double)o->batch * SUR_NOUT)), part, s));
+        GHIPCHK(pdn::launch_sur_adam(part, nwg, w, mm, vv, (float)lr, b1, b2, 1e-8f, (float)(1 - p1), (float)(1 - p2),
+                                     lossd + t, s));
+        GHIPCHK(pdn::launch_sur_pack(w, pk, s));
+    }
+    GHIPCHK(hipEventRecord(e2, s));
+    double val = 0;
+    if ((rc = sur_loss_host(pk, data, n_train, n_all - n_train, lpart, s, &val))) return rc;
+    double tr = 0;
+    if ((rc = sur_loss_host(pk, data, 0, std::min<int64_t>(n_train, 1 << 22), lpart, s, &tr))) return rc;
+    GHIPCHK(hipMemcpyAsync(weights, w, SUR_NPARAM * sizeof(float), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+    float tdata = 0, ttrain = 0;
+    GHIPCHK(hipEventElapsedTime(&tdata, e0, e1));
+    GHIPCHK(hipEventElapsedTime(&ttrain, e1, e2));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
+    if (rep) {
+        rep->loss_val_initial = val0;
+        rep->loss_val = val;
+        rep->loss_train = tr;
+        rep->data_seconds = 1e-3 * tdata;
+        rep->train_seconds = 1e-3 * ttrain;
+        rep->samples_train = n_train;
+        rep->samples_val = n_all - n_train;
+    }
+    return PDN_OK;
+}
+
+int pdn_surrogate_set(pdn_ctx *c, int32_t ply, const float *weights, int64_t n, double dmg_thresh,
+                      double res_thresh)
+{
+    if (!c) return PDN_EINVAL;
+    if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
+    if (!weights || n != SUR_NPARAM) return set_err(c, PDN_EINVAL, "surrogate needs %d parameters", SUR_NPARAM);
+    if (ply < -1 || ply >= c->P) return set_err(c, PDN_EINVAL, "ply index %d out of range", ply);
+    if (!(dmg_thresh >= 0) || !(res_thresh >= 0)) return set_err(c, PDN_EINVAL, "thresholds must be >= 0");
+    for (int p = 0; p < c->P; ++p)
+        if ((ply < 0 || p == ply) && (!c->mat_set[p] || c->mat[p].law == PDN_LAW_ELASTIC))
+            return set_err(c, PDN_ESTATE, "ply %d has no damage law to replace", p);
+    (void)hipSetDevice(c->device);
+    // grow the network table by one
+    uint4 *nd = nullptr;
+    int rc = dalloc(c, (void **)&nd, (size_t)(c->n_nets + 1) * SUR_PACK_BYTES);
+    if (rc) return rc;
+    if (c->sur_d) {
+        HIPCHK(c, hipMemcpyAsync(nd, c->sur_d, (size_t)c->n_nets * SUR_PACK_BYTES, hipMemcpyDeviceToDevice, c->stream));
+    }
+    float *w = nullptr;
+    if ((rc = dalloc(c, (void **)&w, SUR_NPARAM * sizeof(float)))) return rc;
+    HIPCHK(c, hipMemcpyAsync(w, weights, SUR_NPARAM * sizeof(float), hipMemcpyHostToDevice, c->stream));
+    hipError_t e = pdn::launch_sur_pack(w, reinterpret_cast<char *>(nd) + (size_t)c->n_nets * SUR_PACK_BYTES,
+                                        c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(w);
+    if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "surrogate packing: %s", hipGetErrorString(e));
+    if (c->sur_d) (void)hipFree(c->sur_d);
+    c->sur_d = nd;
+    for (int p = 0; p < c->P; ++p)
+        if (ply < 0 || p == ply) {
+            c->ply_net[p] = c->n_nets;
+            c->mat[p].law = PDN_LAW_CDM_SURROGATE;
+        }
+    c->n_nets += 1;
+    c->sur_dmg = dmg_thresh;
+    c->sur_res = res_thresh;
+    c->ready = false;
+    if (c->gl.step > 0) {
+        c->needs_init = true;
+        c->loaded_state = true;
+    }
+    return PDN_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,581 @@
+// pdn_elem.h -- the fused element / node kernel (device code, internal),
+// instantiated without the surrogate in pdn_kernels.hip and with it in
+// pdn_elem_sur.hip.
+#pragma once
+#include "pdn_internal.h"
+#include "pdn_launch.h"
+#include "pdn_law.h"
+#include "pdn_mlp.h"
+
+namespace pdn {
+
+// ---------------------------------------------------------------------------
+// intralaminar update by the surrogate network with the exact law as fallback
+//
+// A point keeps the exact law when any damage variable of its incoming
+// thresholds exceeds dmg_thr, or when the network's stress disagrees with
+// the nominal stress of the network's own new thresholds by more than
+// res_thr (relative to |C0 e|, at least 1e-3 Y_T).  Every lane of the wave
+// must call it together (the network runs on the matrix cores); exact = 1
+// when the exact law produced the result.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6], bool &changed,
+                           const uint4 *__restrict__ pk, float dmg_thr, float res_thr, int &exact)
+{
+    const R lc = cbrt(vol);
+    const R YT = cap_strength(P.YT, P.E2, P.GYT, lc);
+    const R YC = cap_strength(P.YC, P.E2, P.GYC, lc);
+    const R SL = cap_strength(P.SL, P.G12v, P.GSL, lc);
+    const R X[6] = {P.XT, P.YT, P.YT, P.SL, P.SL, P.SL};
+    const R kx[6] = {P.kE1XT, P.E2 * P.iYT, P.E2 * P.iYT, P.G23 * P.iSL, P.G12 * P.iSL, P.G12 * P.iSL};
+    float x[SUR_NIN], y[SUR_NOUT];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = (float)(e[k] * kx[k]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) x[6 + k] = (float)(R(1) - R(1) / r[k]);
+    bool fb = (r[0] > R(1) || r[1] > R(1) || r[2] > R(1) || r[3] > R(1)) &&
+              cdm_max_damage(P, lc, YT, YC, SL, r) > (R)dmg_thr;
+    if (__ballot(!fb) != 0) sur_forward_wave(pk, x, y);         // uniform across the wave
+    R rs[4], ss[6];
+    if (!fb) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ss[k] = (R)y[k] * X[k];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const R so = rmin(rmax((R)x[6 + k], (R)y[6 + k]), R(1) - R(1e-6));
+            rs[k] = rmax(r[k], R(1) / (R(1) - so));               // thresholds never decrease
+        }
+        rs[0] = rmax(rs[0], rs[1]);
+        rs[2] = rmax(rs[2], rs[3]);
+        // nominal stress of the predicted thresholds, and the effective stress
+        const R s0 = P.C11 * e[0] + P.C12 * e[1] + P.C13 * e[2];
+        const R s1 = P.C12 * e[0] + P.C22 * e[1] + P.C23 * e[2];
+        const R s2 = P.C13 * e[0] + P.C23 * e[1] + P.C33 * e[2];
+        const R s3 = P.G23 * e[3], s4 = P.G13 * e[4], s5 = P.G12 * e[5];
+        R sc[6];
+        if (rs[0] <= R(1) && rs[1] <= R(1) && rs[2] <= R(1) && rs[3] <= R(1)) {
+            sc[0] = s0; sc[1] = s1; sc[2] = s2; sc[3] = s3; sc[4] = s4; sc[5] = s5;
+        } else {
+            cdm_nominal(P, lc, YT, YC, SL, rs[0], rs[1], rs[2], rs[3], s0, s1, e, sc);
+        }
+        R num = R(0);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) num += (ss[k] - sc[k]) * (ss[k] - sc[k]);
+        const R den = rmax(s0 * s0 + s1 * s1 + s2 * s2 + s3 * s3 + s4 * s4 + s5 * s5, R(1e-6) * P.YT * P.YT);
+        fb = num > (R)res_thr * (R)res_thr * den;
+    }
+    exact = fb ? 1 : 0;
+    if (fb) {
+        cdm_update(P, vol, e, r, sg, changed);
+        return;
+    }
+    changed = (rs[0] != r[0]) | (rs[1] != r[1]) | (rs[2] != r[2]) | (rs[3] != r[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = rs[k];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sg[k] = ss[k];
+}
+
+// ---------------------------------------------------------------------------
+// 1-point hex8 on a box element (Section 2, total Lagrangian, Eq. 3 form)
+//
+// For an axis-aligned box the mean gradient is b_a = (xi_a/4hx, eta_a/4hy,
+// zeta_a/4hz) and the Flanagan-Belytschko vectors are gamma = h/8, so the
+// 8 nodal values of each displacement component are projected on the
+// orthogonal corner basis {xi, eta, zeta, eta.zeta, xi.zeta, xi.eta,
+// xi.eta.zeta} (a Walsh-Hadamard transform, 24 adds) and the nodal forces are
+// the inverse transform of the stress and hourglass coefficients.
+// Node order: bottom face (-,-), (+,-), (+,+), (-,+), then the top face.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct Modes { R xi, eta, zeta, ez, xz, xe, xez; };
+
+template <typename R>
+__device__ __forceinline__ Modes<R> fwd8(const R u[8])
+{
+    R p0 = u[0] + u[4], p1 = u[1] + u[5], p2 = u[2] + u[6], p3 = u[3] + u[7];
+    R m0 = u[4] - u[0], m1 = u[5] - u[1], m2 = u[6] - u[2], m3 = u[7] - u[3];
+    R pa = p0 + p2, pb = p1 + p3, pc = p2 - p0, pd = p1 - p3;
+    R ma = m0 + m2, mb = m1 + m3, mc = m2 - m0, md = m1 - m3;
+    Modes<R> s;
+    s.xi = pc + pd; s.eta = pc - pd; s.xe = pa - pb;
+    s.zeta = ma + mb; s.xz = mc + md; s.ez = mc - md; s.xez = ma - mb;
+    return s;
+}
+
+template <typename R>
+__device__ __forceinline__ void inv8(const Modes<R> &c, R f[8])
+{
+    R q0 = -c.xi - c.eta + c.xe, q1 = c.xi - c.eta - c.xe;
+    R q2 = c.xi + c.eta + c.xe, q3 = -c.xi + c.eta - c.xe;
+    R r0 = c.zeta - c.xz - c.ez + c.xez, r1 = c.zeta + c.xz - c.ez - c.xez;
+    R r2 = c.zeta + c.xz + c.ez + c.xez, r3 = c.zeta - c.xz + c.ez - c.xez;
+    f[0] = q0 - r0; f[1] = q1 - r1; f[2] = q2 - r2; f[3] = q3 - r3;
+    f[4] = q0 + r0; f[5] = q1 + r1; f[6] = q2 + r2; f[7] = q3 + r3;
+}
+
+// Returns the force coefficients on the corner basis (forces = inv8 of each).
+template <typename R, bool SUR>
+__device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
+                              R ihx, R ihy, R ihz, const PlyC<R> &P, R kappa, R r[4], bool &changed,
+                              Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel,
+                              const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact)
+{
+    Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
+    const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
+    // displacement gradient G = F - I
+    R G00 = sx.xi * gx, G01 = sx.eta * gy, G02 = sx.zeta * gz;
+    R G10 = sy.xi * gx, G11 = sy.eta * gy, G12 = sy.zeta * gz;
+    R G20 = sz.xi * gx, G21 = sz.eta * gy, G22 = sz.zeta * gz;
+    // Green strain E = (G + G^T + G^T G)/2, formed without the 1 + small - 1 cancellation
+    R E00 = G00 + R(0.5) * (G00 * G00 + G10 * G10 + G20 * G20);
+    R E11 = G11 + R(0.5) * (G01 * G01 + G11 * G11 + G21 * G21);
+    R E22 = G22 + R(0.5) * (G02 * G02 + G12 * G12 + G22 * G22);
+    R E01 = R(0.5) * (G01 + G10 + G00 * G01 + G10 * G11 + G20 * G21);
+    R E02 = R(0.5) * (G02 + G20 + G00 * G02 + G10 * G12 + G20 * G22);
+    R E12 = R(0.5) * (G12 + G21 + G01 * G02 + G11 * G12 + G21 * G22);
+    // to the ply frame (fibre at angle theta about Z)
+    const R c = P.c, s = P.s, cc = c * c, ss = s * s, cs = c * s;
+    R e[6];
+    e[0] = cc * E00 + R(2) * cs * E01 + ss * E11;
+    e[1] = ss * E00 - R(2) * cs * E01 + cc * E11;
+    e[2] = E22;
+    e[3] = R(2) * (-s * E02 + c * E12);
+    e[4] = R(2) * (c * E02 + s * E12);
+    e[5] = R(2) * (-cs * E00 + (cc - ss) * E01 + cs * E11);
+    R sg[6];
+    const R vol = hx * hy * hz;
+    exact = 0;
+    if constexpr (SUR) {
+        if (P.law == 2)
+            sur_update(P, vol, e, r, sg, changed, sur_pk + (int64_t)P.sur * (SUR_PACK_BYTES / 16), sur_dmg, sur_res,
+                       exact);
+        else
+            cdm_update(P, vol, e, r, sg, changed);
+    } else {
+        cdm_update(P, vol, e, r, sg, changed);                   // a surrogate ply keeps the exact law
+    }
+    // back to the global frame
+    R S00 = cc * sg[0] - R(2) * cs * sg[5] + ss * sg[1];
+    R S11 = ss * sg[0] + R(2) * cs * sg[5] + cc * sg[1];
+    R S22 = sg[2];
+    R S01 = cs * sg[0] + (cc - ss) * sg[5] - cs * sg[1];
+    R S02 = c * sg[4] - s * sg[3];
+    R S12 = s * sg[4] + c * sg[3];
+    // nominal stress P = F S (index form (F S)_{iJ})
+    R F00 = R(1) + G00, F11 = R(1) + G11, F22 = R(1) + G22;
+    R P00 = F00 * S00 + G01 * S01 + G02 * S02;
+    R P01 = F00 * S01 + G01 * S11 + G02 * S12;
+    R P02 = F00 * S02 + G01 * S12 + G02 * S22;
+    R P10 = G10 * S00 + F11 * S01 + G12 * S02;
+    R P11 = G10 * S01 + F11 * S11 + G12 * S12;
+    R P12 = G10 * S02 + F11 * S12 + G12 * S22;
+    R P20 = G20 * S00 + G21 * S01 + F22 * S02;
+    R P21 = G20 * S01 + G21 * S11 + F22 * S12;
+    R P22 = G20 * S02 + G21 * S12 + F22 * S22;
+    const R ax = R(0.25) * hy * hz, ay = R(0.25) * hx * hz, az = R(0.25) * hx * hy;
+    // hourglass: k = kappa Cmax V sum b^2 / 3, q = s/8, force coefficient k s / 64
+    const R khg = kappa * P.cmax * vol * (ihx * ihx + ihy * ihy + ihz * ihz) * R(1.0 / 6.0);
+    const R kh = khg * R(1.0 / 64.0);
+    cx.xi = P00 * ax; cx.eta = P01 * ay; cx.zeta = P02 * az;
+    cy.xi = P10 * ax; cy.eta = P11 * ay; cy.zeta = P12 * az;
+    cz.xi = P20 * ax; cz.eta = P21 * ay; cz.zeta = P22 * az;
+    cx.ez = kh * sx.ez; cx.xz = kh * sx.xz; cx.xe = kh * sx.xe; cx.xez = kh * sx.xez;
+    cy.ez = kh * sy.ez; cy.xz = kh * sy.xz; cy.xe = kh * sy.xe; cy.xez = kh * sy.xez;
+    cz.ez = kh * sz.ez; cz.xz = kh * sz.xz; cz.xe = kh * sz.xe; cz.xez = kh * sz.xez;
+    R w = sg[0] * e[0] + sg[1] * e[1] + sg[2] * e[2] + sg[3] * e[3] + sg[4] * e[4] + sg[5] * e[5];
+    R q2 = sx.ez * sx.ez + sx.xz * sx.xz + sx.xe * sx.xe + sx.xez * sx.xez
+         + sy.ez * sy.ez + sy.xz * sy.xz + sy.xe * sy.xe + sy.xez * sy.xez
+         + sz.ez * sz.ez + sz.xz * sz.xz + sz.xe * sz.xe + sz.xez * sz.xez;
+    uel = R(0.5) * vol * w + R(0.5) * khg * q2 * R(1.0 / 64.0);
+}
+
+// ---------------------------------------------------------------------------
+// fused element / node kernel
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int xcd_tile(int b, int nb)
+{
+    // consecutive tiles on one XCD: blocks are dealt round-robin to 8 XCDs
+    const int per = nb / 8, rem = nb % 8, x = b % 8, loc = b / 8;
+    return x < rem ? x * (per + 1) + loc : rem * (per + 1) + (x - rem) * per + loc;
+}
+
+template <typename R>
+__device__ __forceinline__ void load_state(const R *r, int64_t e, R out[4])
+{
+    const R *p = r + 4 * e;
+    out[0] = p[0]; out[1] = p[1]; out[2] = p[2]; out[3] = p[3];
+}
+template <>
+__device__ __forceinline__ void load_state<float>(const float *r, int64_t e, float out[4])
+{
+    float4 v = reinterpret_cast<const float4 *>(r)[e];
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+}
+template <typename R>
+__device__ __forceinline__ void store_state(R *r, int64_t e, const R in[4])
+{
+    R *p = r + 4 * e;
+    p[0] = in[0]; p[1] = in[1]; p[2] = in[2]; p[3] = in[3];
+}
+template <>
+__device__ __forceinline__ void store_state<float>(float *r, int64_t e, const float in[4])
+{
+    reinterpret_cast<float4 *>(r)[e] = make_float4(in[0], in[1], in[2], in[3]);
+}
+
+template <int NT>
+__device__ void block_reduce_store(double acc[PDN_NTERMS], double *out, double *sh)
+{
+    // deterministic: fixed shuffle tree inside each wave, waves summed in order
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int NW = NT / 64;
+#pragma unroll
+    for (int k = 0; k < PDN_NTERMS; ++k) {
+        double v = acc[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) sh[k * NW + wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < PDN_NTERMS) {
+        double v = 0;
+        for (int w = 0; w < NW; ++w) v += sh[threadIdx.x * NW + w];
+        out[threadIdx.x] = v;
+    }
+}
+
+// one workgroup's tile of one plate; block partials go to A.partials[tile].
+// SUR: plies with law 2 use the surrogate network (a separate instantiation,
+// so that the plain path keeps its register budget)
+template <typename R, int TX, int TY, bool SUR>
+__device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int tile)
+{
+    constexpr int NE = TX * TY, NCX = TX + 1, NCY = TY + 1, NC = NCX * NCY;
+    constexpr int NT = PDN_TILE_THREADS(TX, TY);
+    constexpr bool F32 = sizeof(R) == 4;
+    __shared__ R Ubuf[F32 ? 2 : 1][3][F32 ? NC : 1];   // node planes k-1, k in FP32
+    __shared__ R Fs[2][4][3][NE];           // element corner forces: [bottom/top][corner][xyz]
+    __shared__ double D64[2][3][NC];        // FP64 displacement of planes k-1, k
+    __shared__ double V64[2][3][NC];        // FP64 velocity of planes k-1, k (own slot)
+    __shared__ double red[PDN_NTERMS * (NT / 64)];
+    // element-type plane copy: the FP64 staging itself when R is double
+    R (*U)[3][NC] = F32 ? reinterpret_cast<R (*)[3][NC]>(&Ubuf[0][0][0])
+                        : reinterpret_cast<R (*)[3][NC]>(&D64[0][0][0]);
+
+    const int t = threadIdx.x;
+    const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
+    const int e0x = tx * (TX - 1), e0y = ty * (TY - 1);
+    const bool lastx = tx == A.tiles_x - 1, lasty = ty == A.tiles_y - 1;
+    const int nx = A.nx, ny = A.ny;
+    const int64_t plane = (int64_t)(nx + 1) * (ny + 1);
+
+    // element role: one element column per thread; ewave: the thread's wave has some
+    const bool erole = t < NE;
+    const bool ewave = (t & ~63) < NE;
+    const int ea = t % TX, eb = t / TX;
+    const int ie = e0x + ea, je = e0y + eb;
+    const bool evalid = erole && ie < nx && je < ny;
+    const bool eown = evalid && (ea < TX - 1 || lastx) && (eb < TY - 1 || lasty);
+    const int s0 = ea + NCX * eb;
+
+    // node role: one node column per thread
+    const bool nrole = t < NC;
+    const int np = t % NCX, nq = t / NCX;
+    const int gi = e0x + np, gj = e0y + nq;
+    const bool nvalid = nrole && gi <= nx && gj <= ny;
+    const int lox = tx == 0 ? 0 : e0x + 1, hix = lastx ? nx + 1 : e0x + TX;
+    const int loy = ty == 0 ? 0 : e0y + 1, hiy = lasty ? ny + 1 : e0y + TY;
+    const bool nown = nvalid && gi >= lox && gi < hix && gj >= loy && gj < hiy;
+    const int64_t col = nvalid ? gi + (int64_t)(nx + 1) * gj : 0;
+
+    double carry[3] = {0, 0, 0}, fin[3];
+    double acc[PDN_NTERMS];
+#pragma unroll
+    for (int k = 0; k < PDN_NTERMS; ++k) acc[k] = 0.0;
+
+    // node plane k is fetched from HBM one iteration ahead (kept in registers
+    // while the previous layer is computed), then staged in LDS
+    double pd[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
+    auto fetch_plane = [&](int k) {
+        if (nvalid) {
+            const int64_t nk = col + plane * k;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pd[c] = A.d_in[3 * nk + c];
+            if (nown) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) pv[c] = A.v_in[3 * nk + c];
+            }
+        }
+    };
+    auto stage_plane = [&](int k) {
+        const int p = k & 1;
+        if (nvalid) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                D64[p][c][t] = pd[c];
+                if (F32) U[p][c][t] = (R)pd[c];
+            }
+            if (nown) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) V64[p][c][t] = pv[c];
+            }
+        } else if (nrole) {
+            U[p][0][t] = U[p][1][t] = U[p][2][t] = R(0);
+        }
+    };
+    // damage thresholds of the element in layer l, fetched one layer ahead
+    R rn[4] = {R(1), R(1), R(1), R(1)};
+    auto fetch_r = [&](int l) {
+        if (l < A.NL && evalid) {
+            const LayerInfo L = A.layers[l];
+            if (L.type == 0 && A.ply[L.ply].law != 0)
+                load_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * L.index), rn);
+        }
+    };
+
+    // lumped-mass integration of plane kp with total internal force f; next predictor
+    auto update_node = [&](int kp, const double f[3]) {
+        const int p = kp & 1;
+        const int64_t n = col + plane * kp;
+        const int fix_lat = (A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny)) ? 7 : 0;
+        const int bits = fix_lat | (kp == 0 ? (int)A.bc_bottom[col] : 0);
+        const double m = A.mx[gi] * A.my[gj] * A.mz[kp];
+        const double im = A.imx[gi] * A.imy[gj] * A.imz[kp];
+        const double dt = A.dt, g = A.grav;
+        acc[T_MZ] += m * D64[p][2][t];         // gravity work = -g (sum m d_z - its initial value)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double d = D64[p][c][t], v = V64[p][c][t];
+            const bool fx = (bits >> c) & 1;
+            const double fe = c == 2 ? -m * g : 0.0;
+            const double a = fx ? 0.0 : (fe - f[c]) * im;
+            const double vn = fx ? 0.0 : v + dt * a;
+            const double dn = fx ? d : d + dt * v + A.phi * dt * dt * a;
+            acc[T_KE] += 0.5 * m * v * vn;
+            acc[T_WA] += 0.5 * dt * v * f[c];
+            acc[T_WB] += 0.5 * dt * vn * f[c];
+            A.d_out[3 * n + c] = dn;
+            A.v_out[3 * n + c] = vn;
+        }
+        if (kp == A.K - 1 && gi >= A.ci0 && gi < A.ci1 && gj >= A.cj0 && gj < A.cj1) {
+            const int64_t ci = (gi - A.ci0) + (int64_t)(A.ci1 - A.ci0) * (gj - A.cj0);
+            A.fside[3 * ci + 0] = f[0];
+            A.fside[3 * ci + 1] = f[1];
+            A.fside[3 * ci + 2] = f[2];
+        }
+    };
+
+    fetch_plane(0);
+    stage_plane(0);
+    fetch_plane(1);
+    fetch_r(0);
+    for (int k = 1; k < A.K; ++k) {
+        const LayerInfo L = A.layers[k - 1];
+        stage_plane(k);
+        R r[4] = {rn[0], rn[1], rn[2], rn[3]};
+        if (k + 1 < A.K) fetch_plane(k + 1);
+        fetch_r(k);
+        if (L.type == 0) {
+            __syncthreads();
+            if (ewave) {
+                // every lane of a wave with element columns evaluates one (lanes
+                // without a valid element take a stand-in and discard it), so
+                // that wave-wide operations of the law see the whole wave
+                const int kb = (k - 1) & 1, kt = k & 1;
+                const int sb = erole ? s0 : 0;
+                const int iv = rmin(ie, nx - 1), jv = rmin(je, ny - 1);
+                const int sl[4] = {sb, sb + 1, sb + 1 + NCX, sb + NCX};
+                R ux[8], uy[8], uz[8];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    ux[q] = U[kb][0][sl[q]]; uy[q] = U[kb][1][sl[q]]; uz[q] = U[kb][2][sl[q]];
+                    ux[q + 4] = U[kt][0][sl[q]]; uy[q + 4] = U[kt][1][sl[q]]; uz[q + 4] = U[kt][2][sl[q]];
+                }
+                const PlyC<R> &P = A.ply[L.ply];
+                bool changed = false;
+                R uel;
+                int exact;
+                Modes<R> cm[3];
+                hex_box_force<R, SUR>(ux, uy, uz, A.hx[iv], A.hy[jv], (R)L.hz, A.ihx[iv], A.ihy[jv], (R)L.ihz, P,
+                              A.kappa, r, changed, cm[0], cm[1], cm[2], uel, A.mlp, A.sur_dmg, A.sur_res, exact);
+                if (eown) {
+                    if (changed) store_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * L.index), r);
+                    acc[T_UEL] += (double)uel;
+                    if (P.law == 2) {
+                        acc[T_AUX] += (double)exact;
+                        acc[T_SURN] += 1.0;
+                    }
+                }
+                if (erole) {
+                    R *F0 = &Fs[0][0][0][t];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        R f[8];
+                        inv8(cm[c], f);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            F0[(q * 3 + c) * NE] = evalid ? f[q] : R(0);                  // bottom corners
+                            F0[((4 + q) * 3 + c) * NE] = evalid ? f[q + 4] : R(0);        // top corners
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (nown) {
+                // node (np, nq) is corner 0 of element (np, nq), 1 of (np-1, nq),
+                // 2 of (np-1, nq-1) and 3 of (np, nq-1); the four corner forces of
+                // one layer are summed in the element type, in this order
+                R fb[3] = {R(0), R(0), R(0)}, ft[3] = {R(0), R(0), R(0)};
+                if (np < TX && nq < TY) {
+                    const int e = np + TX * nq;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][0][c][e]; ft[c] += Fs[1][0][c][e]; }
+                }
+                if (np >= 1 && nq < TY) {
+                    const int e = np - 1 + TX * nq;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][1][c][e]; ft[c] += Fs[1][1][c][e]; }
+                }
+                if (np >= 1 && nq >= 1) {
+                    const int e = np - 1 + TX * (nq - 1);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][2][c][e]; ft[c] += Fs[1][2][c][e]; }
+                }
+                if (np < TX && nq >= 1) {
+                    const int e = np + TX * (nq - 1);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][3][c][e]; ft[c] += Fs[1][3][c][e]; }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { fin[c] = carry[c] + (double)fb[c]; carry[c] = (double)ft[c]; }
+            }
+        } else if (nown) {
+            // zero-thickness interface, nodal (Newton-Cotes) points: the points of
+            // the four elements sharing a node pair coincide, so the pair carries
+            // one state and the summed tributary area
+            const PlyC<R> &P = A.ply[L.ply];
+            const int64_t pi = col + plane * L.index;
+            const int pb = (k - 1) & 1, pt = k & 1;
+            R rd = A.rd[pi];
+            R tau[3];
+            bool changed;
+            const R d1 = (R)(D64[pt][0][t] - D64[pb][0][t]);
+            const R d2 = (R)(D64[pt][1][t] - D64[pb][1][t]);
+            const R d3 = (R)(D64[pt][2][t] - D64[pb][2][t]);
+            czm_update(P, d1, d2, d3, rd, tau, changed);
+            if (changed) A.rd[pi] = rd;
+            const double ap = A.mx[gi] * A.my[gj];   // (sum of adjacent widths / 2)(... / 2)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double ftc = ap * (double)tau[c];
+                fin[c] = carry[c] - ftc;
+                carry[c] = ftc;
+            }
+            acc[T_UEL] += 0.5 * ap * (double)(tau[0] * d1 + tau[1] * d2 + tau[2] * d3);
+        }
+        if (nown) update_node(k - 1, fin);
+    }
+    if (nown) update_node(A.K - 1, carry);
+    block_reduce_store<NT>(acc, A.partials + (int64_t)tile * PDN_NTERMS, red);
+}
+
+template <typename R, int TX, int TY, bool SUR>
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
+void k_elem_node(ElemArgs<R> A)
+{
+    elem_node_tile<R, TX, TY, SUR>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// case of global block b in a batch: the last c with start[c] <= b
+__device__ __forceinline__ int batch_case(const int *start, int ncase, int b)
+{
+    int lo = 0, hi = ncase - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// many plates in one launch: tiles of case c are blocks start[c] .. start[c+1)-1
+// (after the XCD remap, so that one case's neighbouring tiles share an L2)
+template <typename R, int TX, int TY, bool SUR>
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
+void k_elem_node_batch(const ElemArgs<R> *__restrict__ args, const int *__restrict__ start, int ncase)
+{
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int c = batch_case(start, ncase, b);
+    const ElemArgs<R> A = args[c];
+    elem_node_tile<R, TX, TY, SUR>(A, b - start[c]);
+}
+
+// ---------------------------------------------------------------------------
+// launchers of one variant
+// ---------------------------------------------------------------------------
+template <typename R, int TX, int TY, bool SUR>
+static hipError_t launch_en(const ElemArgs<R> &a, hipStream_t s)
+{
+    const int nb = a.tiles_x * a.tiles_y;
+    hipLaunchKernelGGL((k_elem_node<R, TX, TY, SUR>), dim3(nb), dim3(PDN_TILE_THREADS(TX, TY)), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename R, bool SUR>
+static hipError_t launch_elem_node_v(const ElemArgs<R> &a, int tile, hipStream_t s)
+{
+    switch (tile) {
+    case PDN_TILE_16x16: return launch_en<R, 16, 16, SUR>(a, s);
+    case PDN_TILE_32x8: return launch_en<R, 32, 8, SUR>(a, s);
+    case PDN_TILE_8x8: return launch_en<R, 8, 8, SUR>(a, s);
+    case PDN_TILE_15x15: return launch_en<R, 15, 15, SUR>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R, int TX, int TY, bool SUR>
+static int lds_of()
+{
+    hipFuncAttributes at;
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_elem_node<R, TX, TY, SUR>)) != hipSuccess)
+        return -1;
+    return (int)at.sharedSizeBytes;
+}
+
+template <typename R, bool SUR>
+static int lds_v(int tile)
+{
+    switch (tile) {
+    case PDN_TILE_16x16: return lds_of<R, 16, 16, SUR>();
+    case PDN_TILE_32x8: return lds_of<R, 32, 8, SUR>();
+    case PDN_TILE_8x8: return lds_of<R, 8, 8, SUR>();
+    case PDN_TILE_15x15: return lds_of<R, 15, 15, SUR>();
+    default: return -1;
+    }
+}
+
+template <typename R, int TX, int TY, bool SUR>
+static hipError_t launch_enb(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_elem_node_batch<R, TX, TY, SUR>), dim3(nblocks), dim3(PDN_TILE_THREADS(TX, TY)), 0, s,
+                       args, start, ncase);
+    return hipGetLastError();
+}
+
+template <typename R, bool SUR>
+static hipError_t launch_elem_node_batch_v(const ElemArgs<R> *args, const int *start, int ncase, int nblocks,
+                                           int tile, hipStream_t s)
+{
+    if (ncase < 1 || nblocks < 1) return hipErrorInvalidValue;
+    switch (tile) {
+    case PDN_TILE_16x16: return launch_enb<R, 16, 16, SUR>(args, start, ncase, nblocks, s);
+    case PDN_TILE_32x8: return launch_enb<R, 32, 8, SUR>(args, start, ncase, nblocks, s);
+    case PDN_TILE_8x8: return launch_enb<R, 8, 8, SUR>(args, start, ncase, nblocks, s);
+    case PDN_TILE_15x15: return launch_enb<R, 15, 15, SUR>(args, start, ncase, nblocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace pdn

@@ -6,10 +6,11 @@
 #define PDN_MAX_PLIES 64
 #define PDN_MAX_LAYERS (3 * PDN_MAX_PLIES)
 #define PDN_K1_THREADS 256
-#define PDN_NTERMS 6          // per-block energy partials of the element/node kernel
+#define PDN_NTERMS 7          // per-block partials of the element/node kernel (at most 8)
 // partial slots: 0.5 m v^n.v~^{n+1}, 0.5 dt v^n.f^n, 0.5 dt v~^{n+1}.f^n,
-// sum m d_z^n, secant energy, surrogate exact-law count
-enum { T_KE = 0, T_WA = 1, T_WB = 2, T_MZ = 3, T_UEL = 4, T_AUX = 5 };
+// sum m d_z^n, secant energy, surrogate points updated by the exact law,
+// surrogate points updated in total
+enum { T_KE = 0, T_WA = 1, T_WB = 2, T_MZ = 3, T_UEL = 4, T_AUX = 5, T_SURN = 6 };
 
 // Per-ply constants in the arithmetic type R of the element kernel.
 template <typename R>
@@ -24,7 +25,8 @@ struct PlyC {
     R fXT, fGT, fXC, fGC;
     R sa0, ca0, kST, etaT, kEtaL;                    // fracture-plane (alpha0) constants
     R rho;
-    int law;
+    int law;                                         // 0 elastic, 1 damage, 2 damage by the surrogate
+    int sur;                                         // network of a surrogate ply
     // screening constants (uncapped strengths): reciprocals and bounds
     R kE1XT, kE1XC;                                  // E1/XT, E1/XC
     R iYT, iYC, iSL, iST;                            // 1/YT, 1/YC, 1/SL, 1/ST
@@ -60,6 +62,7 @@ struct DevGlobals {
     double ws_acc, wgs_acc;          // striker works up to the current striker level
     int64_t reset_passes, released, max_passes, active;
     double fallback_gp;              // surrogate: GP updates that used the exact law
+    double sur_gp;                   // surrogate: GP updates of surrogate plies
     unsigned int ticket;             // contact-kernel workgroups finished (last one reduces)
     unsigned int pad1;
 };
@@ -88,10 +91,9 @@ struct ElemArgs {
     const uint8_t *bc_bottom;        // (nx+1)(ny+1) fixed-DOF bits of plane 0
     double *fside;                   // 3 per candidate: internal force at level n
     double *partials;                // PDN_NTERMS per block
-    // surrogate (optional)
-    const float *mlp;                // packed weights or null
+    // constitutive surrogate: packed networks (PlyC::sur selects one), fallback thresholds
+    const uint4 *mlp;
     float sur_dmg, sur_res;
-    unsigned long long *sur_counts;  // [exact, total]
 };
 
 struct ContactArgs {

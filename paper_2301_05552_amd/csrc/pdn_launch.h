@@ -10,15 +10,22 @@ enum { PDN_TILE_16x16 = 0, PDN_TILE_32x8 = 1, PDN_TILE_8x8 = 2, PDN_TILE_15x15 =
 static const int pdn_tile_dims[PDN_TILE_COUNT][2] = {{16, 16}, {32, 8}, {8, 8}, {15, 15}};
 
 namespace pdn {
+// sur: the instantiation that evaluates the surrogate network on plies of law 2
 template <typename R>
-hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, hipStream_t s);
+hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, hipStream_t s);
+template <typename R>
+hipError_t launch_elem_node_sur(const ElemArgs<R> &a, int tile, hipStream_t s);
 // batched launches: case c owns blocks start[c] .. start[c+1]-1 (args and start in device memory)
 template <typename R>
 hipError_t launch_elem_node_batch(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
-                                  hipStream_t s);
+                                  bool sur, hipStream_t s);
+template <typename R>
+hipError_t launch_elem_node_batch_sur(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
+                                      hipStream_t s);
 hipError_t launch_contact_batch(const ContactArgs *args, const int *start, int ncase, int nblocks, hipStream_t s);
 int contact_blocks(const ContactArgs &c);
-int elem_node_lds_bytes(int mixed, int tile);   // static LDS of one element/node workgroup (-1 on error)
+int elem_node_lds_bytes(int mixed, int tile, bool sur);   // static LDS of one workgroup (-1 on error)
+int elem_node_lds_bytes_sur(int mixed, int tile);
 hipError_t launch_contact(const ContactArgs &c, hipStream_t s);
 hipError_t launch_contact_init(const ContactArgs &c, int reset_active, hipStream_t s);
 template <typename R>
@@ -29,4 +36,17 @@ template <typename R>
 hipError_t launch_damage_coh(const R *rd, const double *d, const LayerInfo *layers, const int *coh_layer,
                              const PlyC<R> *ply, int nx, int ny, int64_t nce, double *out, hipStream_t s);
 hipError_t launch_project_max(const double *in, int64_t ncol, int nlayers, double *out, hipStream_t s);
+
+// constitutive surrogate (pdn_sur.hip); pk is a packed network (SUR_PACK_BYTES)
+hipError_t launch_sur_pack(const float *w, void *pk, hipStream_t s);
+hipError_t launch_sur_data(const PlyC<double> &P, double vol, uint64_t seed, int64_t p0, int64_t np, int n_inc,
+                           float *out, hipStream_t s);
+int sur_grad_blocks(int64_t batch, int nblk);
+hipError_t launch_sur_grad(const void *pk, const float *data, int64_t n_data, int64_t base, int64_t batch, int nblk,
+                           int randomize, uint64_t seed, float scale, float *partials, hipStream_t s);
+hipError_t launch_sur_adam(const float *partials, int nparts, float *w, float *m, float *v, float lr, float b1,
+                           float b2, float eps, float bc1, float bc2, float *loss_out, hipStream_t s);
+hipError_t launch_sur_eval(const void *pk, const float *x, int64_t n, float *y, hipStream_t s);
+int sur_loss_blocks(int64_t n);
+hipError_t launch_sur_loss(const void *pk, const float *data, int64_t i0, int64_t n, double *partials, hipStream_t s);
 }  // namespace pdn
