@@ -137,6 +137,90 @@ def batched_leg(steps: int, warmup: int, stream) -> dict:
             "create_and_autotune_s": setup}
 
 
+def _crack_band(cfg) -> float:
+    m = cfg["mesh"]
+    return (m["lx"] / m["nx"] * m["ly"] / m["ny"] * m["ply_thickness"] / m["elems_per_ply"]) ** (1.0 / 3.0)
+
+
+def _train_networks(cfg, steps: int) -> tuple:
+    """One network per distinct ply material, trained on the device from the
+    exact law at the plate's crack band (10M paths x 32 increments)."""
+    import paper_2301_05552_amd as pdn
+    lc = _crack_band(cfg)
+    nets, reps = {}, {}
+    for m in cfg["materials"]:
+        key = (m["YT"], m["SL"])
+        if key not in nets:
+            nets[key], reps[key] = pdn.surrogate_train(m, lc, steps=steps)
+    return [nets[(m["YT"], m["SL"])] for m in cfg["materials"]], list(reps.values())
+
+
+def _run(cfg, stream, tile, nets, res, pre, warmup, steps):
+    """Pre-roll, warm-up and timed steps of one configuration; returns
+    (ms per step, info, peak force over the whole run)."""
+    import torch
+    import paper_2301_05552_amd as pdn
+    sim = pdn.Simulation(cfg, stream=stream, tile=tile)
+    if nets is not None:
+        for p, w in enumerate(nets):
+            sim.surrogate_set(p, w, 0.05, res)
+    sim.step(pre + warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    info = sim.info()
+    f = sim.contact_force()[1]
+    sim.close()
+    return 1e3 * el / steps, info, float(f.max()) if len(f) else 0.0
+
+
+def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_steps) -> dict:
+    """The metric's second half: the same plate with the intralaminar update
+    by the trained network (exact law as fallback), at the stated residual bar
+    1e-3 and at a looser 3e-2; speed against the plain path on this GPU, and
+    the peak-force error against the FP64 oracle on the 300 x 200 x 8 plate
+    run to 3 ms (when its stored oracle run is present)."""
+    import workloads as W
+    cfg = W.config3(1)
+    t0 = time.perf_counter()
+    nets, reps = _train_networks(cfg, train_steps)
+    out = {"training": {"networks": len(reps), "wall_s": time.perf_counter() - t0,
+                        "train_steps": train_steps, "batch": 65536,
+                        "samples_train": reps[0]["samples_train"], "samples_val": reps[0]["samples_val"],
+                        "val_mse_before": [r["loss_val_initial"] for r in reps],
+                        "val_mse_after": [r["loss_val"] for r in reps],
+                        "data_s": sum(r["data_seconds"] for r in reps),
+                        "train_s": sum(r["train_seconds"] for r in reps)}}
+    _, _, f_plain = _run(cfg, stream, tile, None, 0, pre, warmup, steps)
+    for res in (1e-3, 3e-2):
+        ms, info, fpk = _run(cfg, stream, tile, nets, res, pre, warmup, steps)
+        out[f"res_{res:g}"] = {"value": info["n_bulk"] / (ms * 1e-3), "unit": "GP-updates/s", "ms_per_step": ms,
+                               "speedup_vs_plain": plain_ms / ms, "fallback_fraction": info["fallback_fraction"],
+                               "peak_force_N": fpk, "plain_peak_force_N": f_plain}
+    gold = os.path.join(ROOT, "tests", "golden", "config2_fp64_oracle.json")
+    if gate_steps and os.path.exists(gold):
+        with open(gold) as fh:
+            g = json.load(fh)
+        c2 = W.config2(1)
+        nets2, _ = _train_networks(c2, train_steps)
+        n = min(gate_steps, g["steps"])
+        gate = {"workload": "300x200x8 [0/45/-45/90]s plate, 15 J, to %.2f ms" % (n * g["dt"] * 1e3),
+                "oracle_peak_force_N": g["peak_force_N"] if n == g["steps"] else None}
+        for name, nn, res in (("plain_mixed", None, 0), ("surrogate_res_0.001", nets2, 1e-3),
+                              ("surrogate_res_0.03", nets2, 3e-2)):
+            ms, info, fpk = _run(c2, stream, (15, 15), nn, res, 0, 0, n)
+            e = {"peak_force_N": fpk, "ms_per_step": ms}
+            if gate["oracle_peak_force_N"]:
+                e["peak_force_rel_err"] = abs(fpk - g["peak_force_N"]) / g["peak_force_N"]
+            if nn is not None:
+                e["fallback_fraction"] = info["fallback_fraction"]
+            gate[name] = e
+        out["accuracy_gate"] = gate
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +232,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-case batched leg")
     ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
+    ap.add_argument("--sur-train-steps", type=int, default=16000)
+    ap.add_argument("--gate-steps", type=int, default=61000,
+                    help="steps of the 300x200x8 accuracy gate (0 = skip)")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--max-preroll", type=int, default=2000,
                     help="untimed steps allowed to bring the striker into contact before the warm-up")
@@ -230,6 +318,11 @@ def main():
                      "algorithmic_bytes_per_launch": bytes_launch},
     }
     sim.close()
+    if not args.no_surrogate:
+        log("surrogate leg: training networks, surrogate runs")
+        res["surrogate"] = surrogate_leg(stream.cuda_stream, (tx, ty), pre, args.warmup, args.steps,
+                                         res["ms_per_step"], args.sur_train_steps, args.gate_steps)
+        log("surrogate leg done")
     if not args.no_batched:
         log("batched leg: 64 cases")
         res["batched"] = batched_leg(args.batched_steps, 10, stream.cuda_stream)
