@@ -202,6 +202,37 @@ __device__ __forceinline__ int xcd_tile(int b, int nb)
     return x < rem ? x * (per + 1) + loc : rem * (per + 1) + (x - rem) * per + loc;
 }
 
+// Read-only tables (plies, layers, per-plane factors) are read through the
+// constant address space: the kernel never writes them, and loads from a
+// uniform address then use the scalar cache, whose waits do not drain the
+// vector loads in flight (the next node plane).
+// a whole read-only record through the constant address space (word by word)
+template <typename T>
+__device__ __forceinline__ T cload(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "record of whole words");
+    T v;
+    const __attribute__((address_space(4))) int *src = (const __attribute__((address_space(4))) int *)p;
+    int *dst = reinterpret_cast<int *>(&v);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = src[i];
+    return v;
+}
+
+// Values that are the same in every lane, made visibly so: addresses built
+// from them stay scalar (constants then come through the scalar cache, whose
+// waits do not drain the vector loads in flight).
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ float uni(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, x)));
+}
+__device__ __forceinline__ double uni(double x)
+{
+    const int2 v = __builtin_bit_cast(int2, x);
+    return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y)));
+}
+
 template <typename R>
 __device__ __forceinline__ void load_state(const R *r, int64_t e, R out[4])
 {
@@ -290,15 +321,23 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     const bool nown = nvalid && gi >= lox && gi < hix && gj >= loy && gj < hiy;
     const int64_t col = nvalid ? gi + (int64_t)(nx + 1) * gj : 0;
 
+    // per-thread constants of the march, loaded once (inside the loop their
+    // loads could not move past the state stores and would stall every layer)
+    const int iv = rmin(ie, nx - 1), jv = rmin(je, ny - 1);
+    const R ehx = A.hx[iv], ehy = A.hy[jv], eihx = A.ihx[iv], eihy = A.ihy[jv];
+    const double mxy = nvalid ? A.mx[gi] * A.my[gj] : 0.0;
+    const double imxy = nvalid ? A.imx[gi] * A.imy[gj] : 0.0;
+
     double carry[3] = {0, 0, 0}, fin[3];
     double acc[PDN_NTERMS];
 #pragma unroll
     for (int k = 0; k < PDN_NTERMS; ++k) acc[k] = 0.0;
 
-    // node plane k is fetched from HBM one iteration ahead (kept in registers
-    // while the previous layer is computed), then staged in LDS
-    double pd[3] = {0, 0, 0}, pv[3] = {0, 0, 0};
-    auto fetch_plane = [&](int k) {
+    // node plane k is fetched from HBM two iterations ahead into one of two
+    // register sets (the loop is unrolled by two so that a set is never
+    // touched while its loads are in flight), then staged in LDS
+    double pdA[3] = {0, 0, 0}, pvA[3] = {0, 0, 0}, pdB[3] = {0, 0, 0}, pvB[3] = {0, 0, 0};
+    auto fetch_plane = [&](int k, double (&pd)[3], double (&pv)[3]) {
         if (nvalid) {
             const int64_t nk = col + plane * k;
 #pragma unroll
@@ -309,7 +348,7 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             }
         }
     };
-    auto stage_plane = [&](int k) {
+    auto stage_plane = [&](int k, const double (&pd)[3], const double (&pv)[3]) {
         const int p = k & 1;
         if (nvalid) {
 #pragma unroll
@@ -328,10 +367,11 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     // damage thresholds of the element in layer l, fetched one layer ahead
     R rn[4] = {R(1), R(1), R(1), R(1)};
     auto fetch_r = [&](int l) {
-        if (l < A.NL && evalid) {
-            const LayerInfo L = A.layers[l];
-            if (L.type == 0 && A.ply[L.ply].law != 0)
-                load_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * L.index), rn);
+        if (l < A.NL) {
+            const LayerInfo Lr = cload(A.layers + l);
+            const int lt = uni(Lr.type), lp = uni(Lr.ply), li = uni(Lr.index);
+            if (lt == 0 && cload(&A.ply[lp].law) != 0 && evalid)
+                load_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * li), rn);
         }
     };
 
@@ -341,8 +381,8 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         const int64_t n = col + plane * kp;
         const int fix_lat = (A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny)) ? 7 : 0;
         const int bits = fix_lat | (kp == 0 ? (int)A.bc_bottom[col] : 0);
-        const double m = A.mx[gi] * A.my[gj] * A.mz[kp];
-        const double im = A.imx[gi] * A.imy[gj] * A.imz[kp];
+        const double m = mxy * cload(A.mz + kp);
+        const double im = imxy * cload(A.imz + kp);
         const double dt = A.dt, g = A.grav;
         acc[T_MZ] += m * D64[p][2][t];         // gravity work = -g (sum m d_z - its initial value)
 #pragma unroll
@@ -367,17 +407,16 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         }
     };
 
-    fetch_plane(0);
-    stage_plane(0);
-    fetch_plane(1);
-    fetch_r(0);
-    for (int k = 1; k < A.K; ++k) {
-        const LayerInfo L = A.layers[k - 1];
-        stage_plane(k);
+    // layer k-1 (between node planes k-1 and k), then the update of plane k-1
+    auto layer_step = [&](int k, double (&pd)[3], double (&pv)[3]) {
+        const LayerInfo Lk = cload(A.layers + (k - 1));
+        const int ltype = uni(Lk.type), lply = uni(Lk.ply), lidx = uni(Lk.index);
+        const R lhz = (R)uni(Lk.hz), lihz = (R)uni(Lk.ihz);
+        stage_plane(k, pd, pv);
         R r[4] = {rn[0], rn[1], rn[2], rn[3]};
-        if (k + 1 < A.K) fetch_plane(k + 1);
+        if (k + 2 < A.K) fetch_plane(k + 2, pd, pv);
         fetch_r(k);
-        if (L.type == 0) {
+        if (ltype == 0) {
             __syncthreads();
             if (ewave) {
                 // every lane of a wave with element columns evaluates one (lanes
@@ -385,7 +424,6 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                 // that wave-wide operations of the law see the whole wave
                 const int kb = (k - 1) & 1, kt = k & 1;
                 const int sb = erole ? s0 : 0;
-                const int iv = rmin(ie, nx - 1), jv = rmin(je, ny - 1);
                 const int sl[4] = {sb, sb + 1, sb + 1 + NCX, sb + NCX};
                 R ux[8], uy[8], uz[8];
 #pragma unroll
@@ -393,15 +431,15 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                     ux[q] = U[kb][0][sl[q]]; uy[q] = U[kb][1][sl[q]]; uz[q] = U[kb][2][sl[q]];
                     ux[q + 4] = U[kt][0][sl[q]]; uy[q + 4] = U[kt][1][sl[q]]; uz[q + 4] = U[kt][2][sl[q]];
                 }
-                const PlyC<R> &P = A.ply[L.ply];
+                const PlyC<R> P = cload(A.ply + lply);
                 bool changed = false;
                 R uel;
                 int exact;
                 Modes<R> cm[3];
-                hex_box_force<R, SUR>(ux, uy, uz, A.hx[iv], A.hy[jv], (R)L.hz, A.ihx[iv], A.ihy[jv], (R)L.ihz, P,
+                hex_box_force<R, SUR>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P,
                               A.kappa, r, changed, cm[0], cm[1], cm[2], uel, A.mlp, A.sur_dmg, A.sur_res, exact);
                 if (eown) {
-                    if (changed) store_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * L.index), r);
+                    if (changed) store_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * lidx), r);
                     acc[T_UEL] += (double)uel;
                     if (P.law == 2) {
                         acc[T_AUX] += (double)exact;
@@ -455,8 +493,8 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             // zero-thickness interface, nodal (Newton-Cotes) points: the points of
             // the four elements sharing a node pair coincide, so the pair carries
             // one state and the summed tributary area
-            const PlyC<R> &P = A.ply[L.ply];
-            const int64_t pi = col + plane * L.index;
+            const PlyC<R> P = cload(A.ply + lply);
+            const int64_t pi = col + plane * lidx;
             const int pb = (k - 1) & 1, pt = k & 1;
             R rd = A.rd[pi];
             R tau[3];
@@ -466,7 +504,7 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             const R d3 = (R)(D64[pt][2][t] - D64[pb][2][t]);
             czm_update(P, d1, d2, d3, rd, tau, changed);
             if (changed) A.rd[pi] = rd;
-            const double ap = A.mx[gi] * A.my[gj];   // (sum of adjacent widths / 2)(... / 2)
+            const double ap = mxy;                   // (sum of adjacent widths / 2)(... / 2)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const double ftc = ap * (double)tau[c];
@@ -476,6 +514,16 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             acc[T_UEL] += 0.5 * ap * (double)(tau[0] * d1 + tau[1] * d2 + tau[2] * d3);
         }
         if (nown) update_node(k - 1, fin);
+    };
+
+    fetch_plane(0, pdA, pvA);
+    stage_plane(0, pdA, pvA);
+    fetch_plane(1, pdB, pvB);
+    if (A.K > 2) fetch_plane(2, pdA, pvA);
+    fetch_r(0);
+    for (int k = 1; k < A.K; k += 2) {
+        layer_step(k, pdB, pvB);
+        if (k + 1 < A.K) layer_step(k + 1, pdA, pvA);
     }
     if (nown) update_node(A.K - 1, carry);
     block_reduce_store<NT>(acc, A.partials + (int64_t)tile * PDN_NTERMS, red);
