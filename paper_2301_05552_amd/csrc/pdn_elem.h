@@ -337,16 +337,16 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     // register sets (the loop is unrolled by two so that a set is never
     // touched while its loads are in flight), then staged in LDS
     double pdA[3] = {0, 0, 0}, pvA[3] = {0, 0, 0}, pdB[3] = {0, 0, 0}, pvB[3] = {0, 0, 0};
+    // Every lane issues the same loads in every layer (clamped addresses for
+    // lanes without a node, a repeat of the top plane past it): the waits for
+    // a load then count only loads issued after it, and the plane in flight
+    // is never drained early.
     auto fetch_plane = [&](int k, double (&pd)[3], double (&pv)[3]) {
-        if (nvalid) {
-            const int64_t nk = col + plane * k;
+        const int64_t nk = (nvalid ? col : 0) + plane * (int64_t)rmin(k, A.K - 1);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) pd[c] = A.d_in[3 * nk + c];
-            if (nown) {
+        for (int c = 0; c < 3; ++c) pd[c] = A.d_in[3 * nk + c];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) pv[c] = A.v_in[3 * nk + c];
-            }
-        }
+        for (int c = 0; c < 3; ++c) pv[c] = A.v_in[3 * nk + c];
     };
     auto stage_plane = [&](int k, const double (&pd)[3], const double (&pv)[3]) {
         const int p = k & 1;
@@ -365,14 +365,20 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         }
     };
     // damage thresholds of the element in layer l, fetched one layer ahead
+    // and the interface damage threshold of the node pair, for a cohesive layer.
     R rn[4] = {R(1), R(1), R(1), R(1)};
+    // Both are loaded for every layer (the other one from a fixed address):
+    // the same two loads per lane and layer keep the wait counts static.
+    // Values of lanes without an element or node pair, or of an elastic ply,
+    // are not used.
+    R rdn = R(0);
     auto fetch_r = [&](int l) {
-        if (l < A.NL) {
-            const LayerInfo Lr = cload(A.layers + l);
-            const int lt = uni(Lr.type), lp = uni(Lr.ply), li = uni(Lr.index);
-            if (lt == 0 && cload(&A.ply[lp].law) != 0 && evalid)
-                load_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * li), rn);
-        }
+        const LayerInfo Lr = cload(A.layers + rmin(l, A.NL - 1));
+        const int lt = uni(Lr.type), li = uni(Lr.index);
+        const int64_t eidx = lt == 0 ? iv + (int64_t)nx * (jv + (int64_t)ny * li) : 0;
+        const int64_t pidx = lt == 0 ? 0 : (nvalid ? col : 0) + plane * li;
+        load_state(A.r, eidx, rn);
+        rdn = A.rd[pidx];
     };
 
     // lumped-mass integration of plane kp with total internal force f; next predictor
@@ -414,8 +420,11 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         const R lhz = (R)uni(Lk.hz), lihz = (R)uni(Lk.ihz);
         stage_plane(k, pd, pv);
         R r[4] = {rn[0], rn[1], rn[2], rn[3]};
-        if (k + 2 < A.K) fetch_plane(k + 2, pd, pv);
+        const R rdl = rdn;
+        // thresholds first: the wait for them next layer then leaves the plane
+        // loads (issued after them) in flight
         fetch_r(k);
+        fetch_plane(k + 2, pd, pv);
         if (ltype == 0) {
             __syncthreads();
             if (ewave) {
@@ -496,7 +505,7 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             const PlyC<R> P = cload(A.ply + lply);
             const int64_t pi = col + plane * lidx;
             const int pb = (k - 1) & 1, pt = k & 1;
-            R rd = A.rd[pi];
+            R rd = rdl;                              // fetched one layer ahead
             R tau[3];
             bool changed;
             const R d1 = (R)(D64[pt][0][t] - D64[pb][0][t]);
@@ -519,12 +528,14 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     fetch_plane(0, pdA, pvA);
     stage_plane(0, pdA, pvA);
     fetch_plane(1, pdB, pvB);
-    if (A.K > 2) fetch_plane(2, pdA, pvA);
+    fetch_plane(2, pdA, pvA);
     fetch_r(0);
-    for (int k = 1; k < A.K; k += 2) {
+    int k = 1;
+    for (; k + 1 < A.K; k += 2) {
         layer_step(k, pdB, pvB);
-        if (k + 1 < A.K) layer_step(k + 1, pdA, pvA);
+        layer_step(k + 1, pdA, pvA);
     }
+    if (k < A.K) layer_step(k, pdB, pvB);
     if (nown) update_node(A.K - 1, carry);
     block_reduce_store<NT>(acc, A.partials + (int64_t)tile * PDN_NTERMS, red);
 }
