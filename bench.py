@@ -86,8 +86,15 @@ def copy_calibration(nbytes: int):
     for _ in range(3):
         y.copy_(x)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8}),
-          flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    print(json.dumps({"copy_bytes_read_per_launch": n * 8, "copy_bytes_written_per_launch": n * 8,
+                      "copy_ms": ms, "copy_GBs": 2 * n * 8 / (ms * 1e-3) / 1e9}), flush=True)
 
 
 def cpu_baseline(steps: int, threads: int) -> dict:

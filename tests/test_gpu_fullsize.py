@@ -1,0 +1,129 @@
+"""Parity at full size: the [0/45/-45/90]s plate at 1200 x 800 x 16 with 6
+cohesive interfaces (22.1M nodes, 15.4M bulk Gauss points, 5.8M node pairs),
+in the benchmark's launch configuration (15 x 15 tiles), one step from a
+seeded damaged state.
+
+The oracle cannot step the whole plate in seconds, so it evaluates sampled
+columns one by one: each sample is a 4 x 4-column patch of the same laminate
+and element size carrying the same state.  The patch's inner 3 x 3 node
+columns, 2 x 2 element columns and 3 x 3 node-pair columns see exactly the
+neighbourhood they have in the full plate through the step, so their results
+must agree.  Properties that hold at
+any size (thresholds never decrease, finite state) are checked on every value.
+"""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2301_05552_amd as pdn
+import workloads as W
+from pdn_testutil import coh_pairs_from_oracle, interface_bottom_planes
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(name):
+    print(f"[gpu case] {name}", flush=True)
+    sys.stdout.flush()
+
+
+def _patch_cfg(cfg):
+    c = copy.deepcopy(cfg)
+    m = c["mesh"]
+    hx, hy = m["lx"] / m["nx"], m["ly"] / m["ny"]
+    m.update(nx=4, ny=4, lx=4 * hx, ly=4 * hy, bc=W.BC_FREE, precision=W.PREC_FP64)
+    return c
+
+
+def _samples(nx, ny, rs, n_random=12):
+    # Columns whose patch has no supported node: inside the support window
+    # and clear of the 5 mm (40-column) clamp discs at its corners.  Tile
+    # borders (every 14 element columns) and their neighbours, plus random.
+    pts = []
+    for t in (11, 40, 71):
+        for di in (-1, 0, 1):
+            pts.append((14 * t + di, 14 * (t % 40 + 11) + di))
+    pts += [(int(rs.integers(150, nx - 150)), int(rs.integers(150, ny - 150))) for _ in range(n_random)]
+    return pts
+
+
+@pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
+def test_full_size_one_step_sampled_columns(prec):
+    _note(f"full size 1200x800x16+6 one step prec={prec}")
+    cfg = W.config3(prec)
+    m = cfg["mesh"]
+    nx, ny = m["nx"], m["ny"]
+    g = pdn.Simulation(cfg, tile=(15, 15))
+    info = g.info()
+    nn, ne, npairs = info["n_nodes"], info["n_bulk"], info["n_pairs"]
+    st = W.synthetic_state(nn, ne, npairs, seed=31, disp_amp=1e-6, vel_amp=1e-2, r_max=1.5, rd_max=0.3)
+    g.array_set(pdn.ARR_DISP, st["disp"])
+    g.array_set(pdn.ARR_VEL, st["vel"])
+    g.array_set(pdn.ARR_GP_R, st["r"])
+    g.array_set(pdn.ARR_COH_R, st["rd"])
+    g.step(1)
+    d1 = g.array_get(pdn.ARR_DISP)
+    v1 = g.array_get(pdn.ARR_VEL)
+    r1 = g.array_get(pdn.ARR_GP_R)
+    rd1 = g.array_get(pdn.ARR_COH_R)
+    dt = g.info()["dt"]
+    g.close()
+    # properties of every value
+    assert np.all(np.isfinite(d1)) and np.all(np.isfinite(v1))
+    assert np.all(r1 >= st["r"] * (1 - 1e-7)) and np.all(rd1 >= st["rd"] * (1 - 1e-7))
+    assert (r1 > st["r"] * (1 + 1e-6)).sum() > 1000        # the step damaged points
+    # sampled columns against the oracle
+    K = nn // ((nx + 1) * (ny + 1))
+    NLb = ne // (nx * ny)
+    NC = npairs // ((nx + 1) * (ny + 1))
+    pc = _patch_cfg(cfg)
+    planes = interface_bottom_planes(pc["mesh"])
+    assert len(planes) == NC
+    # FP64: the patch's time step differs from the plate's in the last bits
+    # (its masses are summed over fewer elements), ~3e-13 relative, and the
+    # increments scale with dt^2
+    tol_d, tol_r = (1e-11, 1e-10) if prec == W.PREC_FP64 else (2e-4, 1e-5)
+    worst = {"d": 0.0, "v": 0.0, "r": 0.0, "rd": 0.0}
+    D0, V0 = st["disp"].reshape(-1, 3), st["vel"].reshape(-1, 3)
+    P = 5                                                       # patch node columns per direction
+    inner_n = [a + P * b for b in (1, 2, 3) for a in (1, 2, 3)]
+    inner_e = [a + 4 * b for b in (1, 2) for a in (1, 2)]
+    for (I, J) in _samples(nx, ny, np.random.default_rng(5)):
+        nid = np.array([(I - 2 + i) + (nx + 1) * ((J - 2 + j) + (ny + 1) * k)
+                        for k in range(K) for j in range(P) for i in range(P)])
+        eid = np.array([(I - 2 + i) + nx * ((J - 2 + j) + ny * l) for l in range(NLb) for j in range(4)
+                        for i in range(4)])
+        pid = np.array([(I - 2 + i) + (nx + 1) * ((J - 2 + j) + (ny + 1) * c) for c in range(NC) for j in range(P)
+                        for i in range(P)])
+        o = oracle.Oracle(pc)
+        assert abs(o.dt - dt) <= 1e-12 * dt
+        worst["dt"] = max(worst.get("dt", 0.0), abs(o.dt - dt) / dt)
+        o.set(oracle.DISP, D0[nid].reshape(-1))
+        o.set(oracle.VEL, V0[nid].reshape(-1))
+        o.set(oracle.GP_R, st["r"].reshape(-1, 4)[eid].reshape(-1))
+        byn = np.zeros(len(nid))
+        for c, kb in enumerate(planes):
+            byn[kb * P * P:(kb + 1) * P * P] = st["rd"][pid[c * P * P:(c + 1) * P * P]]
+        o.set(oracle.COH_R_BY_BOTTOM_NODE, byn)
+        o.step(1)
+        sel_n = np.array([k * P * P + q for k in range(K) for q in inner_n])
+        sel_e = np.array([l * 16 + q for l in range(NLb) for q in inner_e])
+        sel_p = np.array([c * P * P + q for c in range(NC) for q in inner_n])
+        od = o.get(oracle.DISP).reshape(-1, 3)[sel_n]
+        ov = o.get(oracle.VEL).reshape(-1, 3)[sel_n]
+        gd = d1.reshape(-1, 3)[nid[sel_n]]
+        gv = v1.reshape(-1, 3)[nid[sel_n]]
+        d0 = D0[nid[sel_n]]
+        inc_o, inc_g = od - d0, gd - d0
+        worst["d"] = max(worst["d"], np.abs(inc_g - inc_o).max() / np.abs(inc_o).max())
+        worst["v"] = max(worst["v"], np.abs(gv - ov).max() / np.abs(ov).max())
+        ro = o.get(oracle.GP_R).reshape(-1, 4)[sel_e]
+        worst["r"] = max(worst["r"], np.abs(r1.reshape(-1, 4)[eid[sel_e]] - ro).max() / np.abs(ro).max())
+        ord_ = coh_pairs_from_oracle(o, pc["mesh"])[sel_p]
+        worst["rd"] = max(worst["rd"], np.abs(rd1[pid[sel_p]] - ord_).max() / max(np.abs(ord_).max(), 1.0))
+    print(f"[full size] worst relative differences {worst}", flush=True)
+    assert worst["d"] <= tol_d and worst["v"] <= 10 * tol_d, worst
+    assert worst["r"] <= tol_r and worst["rd"] <= tol_r, worst
