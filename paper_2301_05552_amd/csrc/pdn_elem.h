@@ -341,12 +341,16 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     // lanes without a node, a repeat of the top plane past it): the waits for
     // a load then count only loads issued after it, and the plane in flight
     // is never drained early.
+    // Velocities are used for owned nodes only: other lanes read the nearest
+    // owned node's, a line the wave reads anyway.
+    const int64_t vcol = rmin(rmax(gi, lox), hix - 1) + (int64_t)(nx + 1) * rmin(rmax(gj, loy), hiy - 1);
     auto fetch_plane = [&](int k, double (&pd)[3], double (&pv)[3]) {
-        const int64_t nk = (nvalid ? col : 0) + plane * (int64_t)rmin(k, A.K - 1);
+        const int64_t kk = plane * (int64_t)rmin(k, A.K - 1);
+        const int64_t nk = (nvalid ? col : 0) + kk, nv = vcol + kk;
 #pragma unroll
         for (int c = 0; c < 3; ++c) pd[c] = A.d_in[3 * nk + c];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) pv[c] = A.v_in[3 * nk + c];
+        for (int c = 0; c < 3; ++c) pv[c] = A.v_in[3 * nv + c];
     };
     auto stage_plane = [&](int k, const double (&pd)[3], const double (&pv)[3]) {
         const int p = k & 1;
