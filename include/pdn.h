@@ -159,9 +159,10 @@ int pdn_state_save(const pdn_ctx *ctx, void *buf, int64_t cap, int64_t *n_out);
 int pdn_state_load(pdn_ctx *ctx, const void *buf, int64_t n);
 /* Element-tile shape of the element/node kernel (autotuner hook): 0 = default. */
 int pdn_set_tile(pdn_ctx *ctx, int32_t tile_x, int32_t tile_y);
-/* Mean device time per step of the element/node kernel and of the contact
- * kernel over the last pdn_step call, from HIP events (0 if not timed). */
-int pdn_kernel_times(const pdn_ctx *ctx, double *elem_node_ms, double *contact_ms);
+/* Mean device time per step of the element/node kernel (with the contact
+ * step on the top plane) and of the one-workgroup books kernel that closes
+ * the step, over the last pdn_step call, from HIP events (0 if not timed). */
+int pdn_kernel_times(const pdn_ctx *ctx, double *elem_node_ms, double *books_ms);
 int pdn_set_timing(pdn_ctx *ctx, int32_t on);
 /* Autotuner: time one element/node pass per supported tile shape that fits
  * the device, keep the fastest (remembered per plate shape for the process)
@@ -176,7 +177,7 @@ int pdn_autotune(pdn_ctx *ctx, int32_t *tile_x, int32_t *tile_y);
  * and must outlive the batch.  It picks one element tile for all cases with
  * the autotuner (remembered per batch composition) and captures a graph of
  * steps.  pdn_batch_step advances every case by n steps: one launch of the
- * contact kernel and one of the element/node kernel per step serve all cases;
+ * element/node kernel and one of the books kernel per step serve all cases;
  * it runs on the first case's stream and returns when done.  Each case keeps
  * its own time step, history, energies and outputs, read with the per-context
  * calls; a case may also be stepped alone between batched calls.  Errors name

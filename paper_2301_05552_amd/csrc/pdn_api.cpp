@@ -61,13 +61,15 @@ struct pdn_ctx {
     void *r = nullptr, *rd = nullptr;
     void *hx = nullptr, *hy = nullptr, *ihx = nullptr, *ihy = nullptr, *ply = nullptr;
     double *xs_d = nullptr, *ys_d = nullptr, *mx_d = nullptr, *my_d = nullptr, *mz_d = nullptr;
-    double *imx_d = nullptr, *imy_d = nullptr, *imz_d = nullptr, *blk_d = nullptr;
+    double *imx_d = nullptr, *imy_d = nullptr, *imz_d = nullptr, *cand_d = nullptr;
+    bool cand_dirty = false;          // corrected candidates not yet in the state buffers
     LayerInfo *layers_d = nullptr;
     int *bulk_layer_d = nullptr, *coh_layer_d = nullptr;
     uint8_t *bcb_d = nullptr;
     uint8_t *active_d = nullptr;
     double *vprev_d = nullptr, *fcprev_d = nullptr, *fside_d = nullptr;
-    double *partials_d = nullptr;
+    double *partials_d = nullptr;     // two sets (written / read by consecutive passes), then the stage rows
+    int prow = 0;                     // rows of one set
     int nblocks = 0;
     DevGlobals *gl_d = nullptr;
     double *hist_d = nullptr;
@@ -83,7 +85,7 @@ struct pdn_ctx {
     double sur_dmg = 0.05, sur_res = 1e-3;
     // timing
     bool timing = false;
-    double t_en_ms = 0, t_ct_ms = 0;
+    double t_en_ms = 0, t_bk_ms = 0;
 };
 
 namespace {
@@ -310,8 +312,13 @@ int ensure_history(pdn_ctx *c, int64_t need)
     return PDN_OK;
 }
 
+// two term-major sets of block partials, then the books stage rows
+size_t partials_bytes(int prow) { return (2 * (size_t)PDN_NTERMS * prow + PDN_STAGE * PDN_NTERMS) * sizeof(double); }
+
+// arguments of an element/node pass reading buffer `in` and writing `out`;
+// contact = 1: the pass does the contact step on the top plane first
 template <typename R>
-ElemArgs<R> elem_args(pdn_ctx *c, int in, int out)
+ElemArgs<R> elem_args(pdn_ctx *c, int in, int out, int contact)
 {
     ElemArgs<R> a{};
     a.nx = c->nx; a.ny = c->ny; a.K = c->K; a.NL = c->NL;
@@ -330,7 +337,30 @@ ElemArgs<R> elem_args(pdn_ctx *c, int in, int out)
     a.ply = (const PlyC<R> *)c->ply;
     a.bc_bottom = c->bcb_d;
     a.fside = c->fside_d;
-    a.partials = c->partials_d;
+    // partial sets follow the buffers: a pass writes set `out`, the next pass
+    // (which reads buffer `out`) finds them as set `in`
+    a.partials = c->partials_d + (size_t)out * PDN_NTERMS * c->prow;
+    a.partials_prev = c->partials_d + (size_t)in * PDN_NTERMS * c->prow;
+    a.prow = c->prow;
+    a.stage = c->partials_d + 2 * (size_t)PDN_NTERMS * c->prow;
+    // owner tile of node column g along one axis (tiles overlap by one element
+    // column, a tile owns the nodes past its first line), widened by one tile
+    const int TX = pdn_tile_dims[c->tile][0], TY = pdn_tile_dims[c->tile][1];
+    auto owner = [](int g, int T, int nt) { return std::min(nt - 1, g > 0 ? (g - 1) / (T - 1) : 0); };
+    a.wt0 = std::max(0, owner(c->ci0, TX, c->tiles_x) - 1);
+    a.wt1 = std::min(c->tiles_x, owner(std::max(c->ci0, c->ci1 - 1), TX, c->tiles_x) + 2);
+    a.wu0 = std::max(0, owner(c->cj0, TY, c->tiles_y) - 1);
+    a.wu1 = std::min(c->tiles_y, owner(std::max(c->cj0, c->cj1 - 1), TY, c->tiles_y) + 2);
+    a.contact = contact;
+    a.gl = c->gl_d;
+    a.xs = c->xs_d; a.ys = c->ys_d;
+    a.ztop = c->zk[c->K - 1];
+    const size_t nc = (size_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
+    a.active_in = c->active_d + (size_t)in * nc;
+    a.active_out = c->active_d + (size_t)out * nc;
+    a.vprev = c->vprev_d; a.fcprev = c->fcprev_d;
+    a.cand = c->cand_d;
+    a.hist = c->hist_d;
     a.mlp = c->sur_d;
     a.sur_dmg = (float)c->sur_dmg;
     a.sur_res = (float)c->sur_res;
@@ -340,29 +370,29 @@ ElemArgs<R> elem_args(pdn_ctx *c, int in, int out)
 ContactArgs contact_args(pdn_ctx *c, int buf)
 {
     ContactArgs a{};
-    a.gl = c->gl_d;
     a.d = c->d[buf]; a.v = c->v[buf];
-    a.xs = c->xs_d; a.ys = c->ys_d; a.mx = c->mx_d; a.my = c->my_d;
-    a.ztop = c->zk[c->K - 1];
-    a.mztop = c->mz[c->K - 1];
     a.nx = c->nx; a.ny = c->ny; a.K = c->K;
-    a.clamp_lateral = c->bc == PDN_BC_CLAMPED_EDGES;
     a.ci0 = c->ci0; a.ci1 = c->ci1; a.cj0 = c->cj0; a.cj1 = c->cj1;
-    a.active = c->active_d; a.vprev = c->vprev_d; a.fcprev = c->fcprev_d; a.fside = c->fside_d;
-    a.partials = c->partials_d; a.nblocks = c->nblocks;
-    a.hist = c->hist_d;
-    a.blk = c->blk_d;
+    a.active = c->active_d; a.vprev = c->vprev_d; a.fcprev = c->fcprev_d; a.cand = c->cand_d;
     return a;
 }
 
-int launch_en(pdn_ctx *c, int in, int out)
+// one pass; a contact pass is closed by the books kernel (an event between
+// the two when mid is given)
+int launch_en(pdn_ctx *c, int in, int out, int contact, hipEvent_t mid = nullptr)
 {
     hipError_t e;
-    if (c->precision == PDN_MIXED)
-        e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out), c->tile, c->use_sur, c->stream);
+    const bool mx = c->precision == PDN_MIXED;
+    if (mx)
+        e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out, contact), c->tile, c->use_sur, c->stream);
     else
-        e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out), c->tile, c->use_sur, c->stream);
+        e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out, contact), c->tile, c->use_sur, c->stream);
     if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "element/node kernel launch: %s", hipGetErrorString(e));
+    if (!contact) return PDN_OK;
+    if (mid) HIPCHK(c, hipEventRecord(mid, c->stream));
+    e = mx ? pdn::launch_books<float>(elem_args<float>(c, in, out, contact), c->stream)
+           : pdn::launch_books<double>(elem_args<double>(c, in, out, contact), c->stream);
+    if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "books kernel launch: %s", hipGetErrorString(e));
     return PDN_OK;
 }
 
@@ -382,11 +412,22 @@ void set_tiles(pdn_ctx *c)
     c->nblocks = c->tiles_x * c->tiles_y;
 }
 
+// corrected top-surface candidates of the last contact pass into the state buffers
+int materialize(pdn_ctx *c)
+{
+    if (!c->cand_dirty) return PDN_OK;
+    hipError_t e = pdn::launch_cand_scatter(contact_args(c, c->cur), c->stream);
+    if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "candidate scatter: %s", hipGetErrorString(e));
+    c->cand_dirty = false;
+    return PDN_OK;
+}
+
 // restart the explicit scheme from the state in buffer c->cur
 int init_level(pdn_ctx *c, bool reset_contact)
 {
     const int in = c->cur, out = 1 - c->cur;
-    int rc = launch_en(c, in, out);
+    int rc = materialize(c);
+    if (!rc) rc = launch_en(c, in, out, 0);
     if (rc) return rc;
     if (reset_contact) {
         hipError_t e = pdn::launch_contact_init(contact_args(c, in), 1, c->stream);
@@ -399,7 +440,7 @@ int init_level(pdn_ctx *c, bool reset_contact)
 void free_all(pdn_ctx *c)
 {
     void *ps[] = {c->d[0], c->d[1], c->v[0], c->v[1], c->r, c->rd, c->hx, c->hy, c->ihx, c->ihy, c->ply, c->xs_d, c->ys_d,
-                  c->mx_d, c->my_d, c->mz_d, c->imx_d, c->imy_d, c->imz_d, c->blk_d,
+                  c->mx_d, c->my_d, c->mz_d, c->imx_d, c->imy_d, c->imz_d, c->cand_d,
                   c->layers_d, c->bulk_layer_d, c->coh_layer_d, c->bcb_d,
                   c->active_d, c->vprev_d, c->fcprev_d, c->fside_d, c->partials_d, c->gl_d, c->hist_d, c->dmg_d,
                   c->sur_d};
@@ -424,18 +465,15 @@ int alloc_contact_window(pdn_ctx *c)
     c->ci0 = ci0; c->ci1 = ci1; c->cj0 = cj0; c->cj1 = cj1;
     const size_t nc = (size_t)(ci1 - ci0) * (cj1 - cj0);
     int rc;
-    if (c->active_d) { (void)hipFree(c->active_d); (void)hipFree(c->vprev_d); (void)hipFree(c->fcprev_d); (void)hipFree(c->fside_d); (void)hipFree(c->blk_d); }
-    if ((rc = dalloc(c, (void **)&c->active_d, nc))) return rc;
+    if (c->active_d) { (void)hipFree(c->active_d); (void)hipFree(c->vprev_d); (void)hipFree(c->fcprev_d); (void)hipFree(c->fside_d); (void)hipFree(c->cand_d); }
+    if ((rc = dalloc(c, (void **)&c->active_d, 2 * nc))) return rc;             // two step parities
     if ((rc = dalloc(c, (void **)&c->vprev_d, 3 * nc * sizeof(double)))) return rc;
     if ((rc = dalloc(c, (void **)&c->fcprev_d, 3 * nc * sizeof(double)))) return rc;
     if ((rc = dalloc(c, (void **)&c->fside_d, 3 * nc * sizeof(double)))) return rc;
-    HIPCHK(c, hipMemsetAsync(c->active_d, 0, nc, c->stream));
+    if ((rc = dalloc(c, (void **)&c->cand_d, 6 * nc * sizeof(double)))) return rc;
+    HIPCHK(c, hipMemsetAsync(c->active_d, 0, 2 * nc, c->stream));
     HIPCHK(c, hipMemsetAsync(c->fside_d, 0, 3 * nc * sizeof(double), c->stream));
-    {
-        ContactArgs ca{};
-        ca.ci0 = ci0; ca.ci1 = ci1; ca.cj0 = cj0; ca.cj1 = cj1;
-        if ((rc = dalloc(c, (void **)&c->blk_d, (size_t)PDN_CQ * pdn::contact_blocks(ca) * sizeof(double)))) return rc;
-    }
+    c->cand_dirty = false;
     return PDN_OK;
 }
 
@@ -542,8 +580,8 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
         c->own_stream = true;
     }
     {   // default element tile: the preferred shape whose workgroup fits the device's LDS
-        const int pref_mixed[] = {PDN_TILE_15x15, PDN_TILE_16x16, PDN_TILE_32x8, PDN_TILE_8x8};
-        const int pref_fp64[] = {PDN_TILE_16x16, PDN_TILE_15x15, PDN_TILE_32x8, PDN_TILE_8x8};
+        const int pref_mixed[] = {PDN_TILE_15x15, PDN_TILE_16x16, PDN_TILE_31x15, PDN_TILE_32x8, PDN_TILE_8x8};
+        const int pref_fp64[] = {PDN_TILE_16x16, PDN_TILE_15x15, PDN_TILE_31x15, PDN_TILE_32x8, PDN_TILE_8x8};
         const int *pref = c->precision == PDN_MIXED ? pref_mixed : pref_fp64;
         c->tile = -1;
         for (int k = 0; k < PDN_TILE_COUNT && c->tile < 0; ++k)
@@ -581,7 +619,8 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
     if (!rc) rc = dalloc(c, (void **)&c->coh_layer_d, std::max<size_t>(1, c->coh_layer.size()) * sizeof(int));
     if (!rc) rc = dalloc(c, (void **)&c->bcb_d, c->plane);
     if (!rc) rc = dalloc(c, (void **)&c->gl_d, sizeof(DevGlobals));
-    if (!rc) rc = dalloc(c, (void **)&c->partials_d, (size_t)PDN_NTERMS * std::max(1, c->nblocks) * sizeof(double));
+    c->prow = std::max(1, c->nblocks);
+    if (!rc) rc = dalloc(c, (void **)&c->partials_d, partials_bytes(c->prow));
     if (rc) { free_all(c); if (c->own_stream) (void)hipStreamDestroy(c->stream); delete c; return rc; }
     // tables
     std::vector<double> hxv(c->nx), hyv(c->ny), ihxv(c->nx), ihyv(c->ny);
@@ -736,29 +775,29 @@ int pdn_step(pdn_ctx *c, int64_t n)
         ev.resize(3 * n);
         for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     }
+    // one pass per step: the element/node update of the whole plate with the
+    // contact step (Algorithms 1-2) on its top plane, then the books kernel
     for (int64_t s = 0; s < n; ++s) {
         const int pred = 1 - c->cur;
         if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s], c->stream));
-        hipError_t e = pdn::launch_contact(contact_args(c, pred), c->stream);
-        if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "contact kernel launch: %s", hipGetErrorString(e));
-        if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s + 1], c->stream));
-        if ((rc = launch_en(c, pred, c->cur))) return rc;
+        if ((rc = launch_en(c, pred, c->cur, 1, c->timing ? ev[3 * s + 1] : nullptr))) return rc;
         if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s + 2], c->stream));
         c->cur = pred;
+        c->cand_dirty = true;
     }
     if ((rc = sync_globals_from_device(c))) return rc;
     if (c->timing && n > 0) {
         double a = 0, b = 0;
         for (int64_t s = 0; s < n; ++s) {
-            float t1 = 0, t2 = 0;
-            HIPCHK(c, hipEventElapsedTime(&t1, ev[3 * s], ev[3 * s + 1]));
-            HIPCHK(c, hipEventElapsedTime(&t2, ev[3 * s + 1], ev[3 * s + 2]));
-            b += t1;
-            a += t2;
+            float t = 0, u = 0;
+            HIPCHK(c, hipEventElapsedTime(&t, ev[3 * s], ev[3 * s + 1]));
+            HIPCHK(c, hipEventElapsedTime(&u, ev[3 * s + 1], ev[3 * s + 2]));
+            a += t;
+            b += u;
         }
         for (auto &e : ev) (void)hipEventDestroy(e);
         c->t_en_ms = a / n;
-        c->t_ct_ms = b / n;
+        c->t_bk_ms = b / n;
     }
     if (c->gl.flag_unstable) {
         c->broken = true;
@@ -906,6 +945,8 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
         return PDN_OK;
     }
     if (kind == PDN_ARR_DISP || kind == PDN_ARR_VEL) {
+        int rc = materialize(c);
+        if (rc) return rc;
         const double *src = kind == PDN_ARR_DISP ? c->d[c->cur] : c->v[c->cur];
         HIPCHK(c, hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -938,6 +979,10 @@ int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
     if (n != need) return set_err(c, PDN_EINVAL, "array needs %lld values, got %lld", (long long)need, (long long)n);
     (void)hipSetDevice(c->device);
     if (kind == PDN_ARR_DISP || kind == PDN_ARR_VEL) {
+        // first the corrected candidates of the last step into both arrays (the
+        // array not replaced here keeps them)
+        int rc0 = materialize(c);
+        if (rc0) return rc0;
         // supported DOFs stay at rest
         std::vector<double> tmp(in, in + n);
         for (int k = 0; k < c->K; ++k)
@@ -1001,6 +1046,7 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     if (cap < (int64_t)need || !buf) return set_err(c, PDN_ERANGE, "checkpoint needs %zu bytes", need);
     (void)hipSetDevice(c->device);
     int rc = sync_globals_from_device(c);
+    if (!rc) rc = materialize(c);
     if (rc) return rc;
     char *p = (char *)buf;
     BlobHeader h{kMagic, c->nn, c->ne, c->npairs, ncand, hn, c->precision, 0};
@@ -1016,7 +1062,7 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     if ((rc = d2h(c->v[c->cur], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = d2h(c->r, 4 * c->ne * rs))) return rc;
     if ((rc = d2h(c->rd, c->npairs * rs))) return rc;
-    if ((rc = d2h(c->active_d, ncand))) return rc;
+    if ((rc = d2h(c->active_d + (size_t)(1 - c->cur) * ncand, ncand))) return rc;   // read by the next step
     if ((rc = d2h(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
     if ((rc = d2h(c->fcprev_d, 3 * ncand * sizeof(double)))) return rc;
     if ((rc = d2h(c->hist_d, 3 * hn * sizeof(double)))) return rc;
@@ -1054,7 +1100,7 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     if ((rc = h2d(c->v[0], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = h2d(c->r, 4 * c->ne * rs))) return rc;
     if ((rc = h2d(c->rd, c->npairs * rs))) return rc;
-    if ((rc = h2d(c->active_d, ncand))) return rc;
+    if ((rc = h2d(c->active_d + ncand, ncand))) return rc;            // cur = 0: the next step reads set 1
     if ((rc = h2d(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
     if ((rc = h2d(c->fcprev_d, 3 * ncand * sizeof(double)))) return rc;
     if ((rc = h2d(c->hist_d, 3 * h.hist_n * sizeof(double)))) return rc;
@@ -1062,6 +1108,7 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     if ((rc = push_globals(c))) return rc;
     c->needs_init = true;
     c->loaded_state = true;
+    c->cand_dirty = false;
     return PDN_OK;
 }
 
@@ -1077,14 +1124,16 @@ int pdn_set_tile(pdn_ctx *c, int32_t tx, int32_t ty)
     const int old = c->nblocks;
     c->tile = t;
     set_tiles(c);
-    if (c->nblocks > old) {
+    (void)old;
+    if (c->nblocks > c->prow) {
         (void)hipFree(c->partials_d);
         c->partials_d = nullptr;
-        int rc = dalloc(c, (void **)&c->partials_d, (size_t)PDN_NTERMS * c->nblocks * sizeof(double));
+        c->prow = c->nblocks;
+        int rc = dalloc(c, (void **)&c->partials_d, partials_bytes(c->prow));
         if (rc) return rc;
     }
-    // the contact kernel reduces the partials of the previous element pass:
-    // recompute them in the new block layout, keeping the contact state
+    // a contact pass reduces the partials of the previous pass: recompute them
+    // in the new block layout, keeping the contact state
     if (!c->needs_init) {
         c->needs_init = true;
         c->loaded_state = true;
@@ -1092,11 +1141,11 @@ int pdn_set_tile(pdn_ctx *c, int32_t tx, int32_t ty)
     return PDN_OK;
 }
 
-int pdn_kernel_times(const pdn_ctx *c, double *en, double *ct)
+int pdn_kernel_times(const pdn_ctx *c, double *en, double *bk)
 {
     if (!c) return PDN_EINVAL;
     if (en) *en = c->t_en_ms;
-    if (ct) *ct = c->t_ct_ms;
+    if (bk) *bk = c->t_bk_ms;
     return PDN_OK;
 }
 
@@ -1128,16 +1177,16 @@ struct pdn_batch {
     int device = 0, precision = 0, tile = -1;
     hipStream_t stream = nullptr;        // stream of the first case; every step runs here
     hipStream_t cap = nullptr;           // private stream used only to capture the step graph
-    void *eargs_d = nullptr;             // 2 x n element-kernel arguments (step parity 0, 1)
-    ContactArgs *cargs_d = nullptr;      // 2 x n contact-kernel arguments
-    int *estart_d = nullptr, *cstart_d = nullptr;
-    std::vector<int> estart, cstart;
+    // 3 x n element-pass arguments: steps of parity 0 and 1 (contact pass), and
+    // a restart pass of the current state (no contact) for the autotuner
+    void *eargs_d = nullptr;
+    int *estart_d = nullptr;
+    std::vector<int> estart;
     std::vector<unsigned char> eargs_h;
-    std::vector<ContactArgs> cargs_h;
-    int eblocks = 0, cblocks = 0;
+    int eblocks = 0;
     bool sur = false;                    // some case evaluates a surrogate network
-    hipGraphExec_t exec = nullptr;       // PDN_BATCH_GRAPH_STEPS steps, built for (tile, sur, eblocks, cblocks)
-    int graph_tile = -1, graph_eblocks = 0, graph_cblocks = 0;
+    hipGraphExec_t exec = nullptr;       // PDN_BATCH_GRAPH_STEPS steps, built for (tile, sur, eblocks)
+    int graph_tile = -1, graph_eblocks = 0;
     bool graph_sur = false;
 };
 
@@ -1166,7 +1215,8 @@ int berr(pdn_batch *b, int code, const char *fmt, ...)
                         #call, hipGetErrorString(e_));                                          \
     } while (0)
 
-const int kTileOrder[PDN_TILE_COUNT] = {PDN_TILE_15x15, PDN_TILE_16x16, PDN_TILE_32x8, PDN_TILE_8x8};
+const int kTileOrder[PDN_TILE_COUNT] = {PDN_TILE_15x15, PDN_TILE_16x16, PDN_TILE_31x15, PDN_TILE_32x8,
+                                        PDN_TILE_8x8};
 
 // tile measured fastest, per plate shape (single plates) or per batch composition
 std::map<std::string, int> &tune_cache()
@@ -1198,9 +1248,10 @@ int time_single(pdn_ctx *c, int reps, float *ms)
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
-    int rc = launch_en(c, c->cur, 1 - c->cur);            // warm
+    int rc = materialize(c);
+    if (!rc) rc = launch_en(c, c->cur, 1 - c->cur, 0);     // warm
     if (!rc) HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (int r = 0; r < reps && !rc; ++r) rc = launch_en(c, c->cur, 1 - c->cur);
+    for (int r = 0; r < reps && !rc; ++r) rc = launch_en(c, c->cur, 1 - c->cur, 0);
     if (!rc) HIPCHK(c, hipEventRecord(e1, c->stream));
     if (!rc) HIPCHK(c, hipEventSynchronize(e1));
     if (!rc) HIPCHK(c, hipEventElapsedTime(ms, e0, e1));
@@ -1214,14 +1265,15 @@ template <typename R>
 void fill_eargs(pdn_batch *b)
 {
     const size_t n = b->cs.size();
-    b->eargs_h.resize(2 * n * sizeof(ElemArgs<R>));
+    b->eargs_h.resize(3 * n * sizeof(ElemArgs<R>));
     ElemArgs<R> *ea = reinterpret_cast<ElemArgs<R> *>(b->eargs_h.data());
     for (int p = 0; p < 2; ++p)
         for (size_t i = 0; i < n; ++i) {
             pdn_ctx *c = b->cs[i];
             const int cur = c->cur ^ p, pred = 1 - cur;     // state of case i at a step of parity p
-            ea[p * n + i] = elem_args<R>(c, pred, cur);
+            ea[p * n + i] = elem_args<R>(c, pred, cur, 1);
         }
+    for (size_t i = 0; i < n; ++i) ea[2 * n + i] = elem_args<R>(b->cs[i], b->cs[i]->cur, 1 - b->cs[i]->cur, 0);
 }
 
 // argument tables and block offsets of the current layout, uploaded to the device
@@ -1229,65 +1281,48 @@ int upload_tables(pdn_batch *b)
 {
     const size_t n = b->cs.size();
     b->estart.assign(n + 1, 0);
-    b->cstart.assign(n + 1, 0);
-    b->cargs_h.resize(2 * n);
-    for (size_t i = 0; i < n; ++i) {
-        pdn_ctx *c = b->cs[i];
-        b->estart[i + 1] = b->estart[i] + c->nblocks;
-        for (int p = 0; p < 2; ++p) b->cargs_h[p * n + i] = contact_args(c, 1 - (c->cur ^ p));
-        b->cstart[i + 1] = b->cstart[i] + pdn::contact_blocks(b->cargs_h[i]);
-    }
+    for (size_t i = 0; i < n; ++i) b->estart[i + 1] = b->estart[i] + b->cs[i]->nblocks;
     b->eblocks = b->estart[n];
-    b->cblocks = b->cstart[n];
     b->sur = false;
     for (pdn_ctx *c : b->cs) b->sur = b->sur || c->use_sur;
     if (b->precision == PDN_MIXED) fill_eargs<float>(b);
     else fill_eargs<double>(b);
     if (!b->eargs_d) {
         BHIPCHK(b, hipMalloc(&b->eargs_d, b->eargs_h.size()));
-        BHIPCHK(b, hipMalloc((void **)&b->cargs_d, 2 * n * sizeof(ContactArgs)));
         BHIPCHK(b, hipMalloc((void **)&b->estart_d, (n + 1) * sizeof(int)));
-        BHIPCHK(b, hipMalloc((void **)&b->cstart_d, (n + 1) * sizeof(int)));
     }
     BHIPCHK(b, hipMemcpyAsync(b->eargs_d, b->eargs_h.data(), b->eargs_h.size(), hipMemcpyHostToDevice, b->stream));
-    BHIPCHK(b, hipMemcpyAsync(b->cargs_d, b->cargs_h.data(), 2 * n * sizeof(ContactArgs), hipMemcpyHostToDevice,
-                              b->stream));
     BHIPCHK(b, hipMemcpyAsync(b->estart_d, b->estart.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
-    BHIPCHK(b, hipMemcpyAsync(b->cstart_d, b->cstart.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));          // host tables are reused
     return PDN_OK;
 }
 
-hipError_t launch_batch_elem(pdn_batch *b, int parity, hipStream_t s)
+// table 0, 1: contact passes of the two step parities; table 2: restart passes
+hipError_t launch_batch_elem(pdn_batch *b, int table, hipStream_t s)
 {
     const int n = (int)b->cs.size();
+    const bool contact = table < 2;
     if (b->precision == PDN_MIXED)
-        return pdn::launch_elem_node_batch<float>(reinterpret_cast<ElemArgs<float> *>(b->eargs_d) + parity * n,
-                                                  b->estart_d, n, b->eblocks, b->tile, b->sur, s);
-    return pdn::launch_elem_node_batch<double>(reinterpret_cast<ElemArgs<double> *>(b->eargs_d) + parity * n,
-                                               b->estart_d, n, b->eblocks, b->tile, b->sur, s);
+        return pdn::launch_elem_node_batch<float>(reinterpret_cast<ElemArgs<float> *>(b->eargs_d) + table * n,
+                                                  b->estart_d, n, b->eblocks, b->tile, b->sur, contact, s);
+    return pdn::launch_elem_node_batch<double>(reinterpret_cast<ElemArgs<double> *>(b->eargs_d) + table * n,
+                                               b->estart_d, n, b->eblocks, b->tile, b->sur, contact, s);
 }
 
-// one step of every case: contact pass, then element/node pass
-hipError_t launch_batch_step(pdn_batch *b, int parity, hipStream_t s)
-{
-    const int n = (int)b->cs.size();
-    hipError_t e = pdn::launch_contact_batch(b->cargs_d + parity * n, b->cstart_d, n, b->cblocks, s);
-    if (e == hipSuccess) e = launch_batch_elem(b, parity, s);
-    return e;
-}
+// one step of every case: a contact + element/node pass
+hipError_t launch_batch_step(pdn_batch *b, int parity, hipStream_t s) { return launch_batch_elem(b, parity, s); }
 
-// Mean time of `reps` batched element passes.  The passes use the parity-1
-// tables, which read the last completed level and write the next predictor
-// (what the pass after a step already wrote), so no state changes.
+// Mean time of `reps` batched element passes.  The passes use the restart
+// tables (no contact), which read the last completed level and write the next
+// predictor (what the pass after a step already wrote), so no state changes.
 int time_batch(pdn_batch *b, int reps, float *ms)
 {
     hipEvent_t e0, e1;
     BHIPCHK(b, hipEventCreate(&e0));
     BHIPCHK(b, hipEventCreate(&e1));
-    hipError_t e = launch_batch_elem(b, 1, b->stream);      // warm
+    hipError_t e = launch_batch_elem(b, 2, b->stream);      // warm
     if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch_elem(b, 1, b->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch_elem(b, 2, b->stream);
     if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
@@ -1336,7 +1371,6 @@ int build_graph(pdn_batch *b)
     b->graph_tile = b->tile;
     b->graph_sur = b->sur;
     b->graph_eblocks = b->eblocks;
-    b->graph_cblocks = b->cblocks;
     return PDN_OK;
 }
 
@@ -1446,8 +1480,7 @@ int pdn_batch_step(pdn_batch *b, int64_t n)
         (void)hipStreamSynchronize(c->stream);
     }
     if ((rc = upload_tables(b))) return rc;
-    if (b->graph_tile != b->tile || b->graph_sur != b->sur || b->graph_eblocks != b->eblocks ||
-        b->graph_cblocks != b->cblocks)
+    if (b->graph_tile != b->tile || b->graph_sur != b->sur || b->graph_eblocks != b->eblocks)
         if ((rc = build_graph(b))) return rc;
     int64_t s = 0;
     for (; s + PDN_BATCH_GRAPH_STEPS <= n; s += PDN_BATCH_GRAPH_STEPS)
@@ -1461,6 +1494,7 @@ int pdn_batch_step(pdn_batch *b, int64_t n)
     for (size_t i = 0; i < b->cs.size(); ++i) {
         pdn_ctx *c = b->cs[i];
         if (n & 1) c->cur ^= 1;
+        if (n > 0) c->cand_dirty = true;
         int r2 = sync_globals_from_device(c);
         if (r2) return batch_case_err(b, i, r2);
         if (c->gl.flag_unstable) {
@@ -1497,9 +1531,7 @@ void pdn_batch_destroy(pdn_batch *b)
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->eargs_d) (void)hipFree(b->eargs_d);
-    if (b->cargs_d) (void)hipFree(b->cargs_d);
     if (b->estart_d) (void)hipFree(b->estart_d);
-    if (b->cstart_d) (void)hipFree(b->cstart_d);
     delete b;
 }
 

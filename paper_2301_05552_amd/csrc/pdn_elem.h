@@ -257,24 +257,112 @@ __device__ __forceinline__ void store_state<float>(float *r, int64_t e, const fl
     reinterpret_cast<float4 *>(r)[e] = make_float4(in[0], in[1], in[2], in[3]);
 }
 
-template <int NT>
-__device__ void block_reduce_store(double acc[PDN_NTERMS], double *out, double *sh)
+// stage rows of the books reduction: 64 or more tiles each, at most PDN_STAGE
+__device__ __forceinline__ int books_stage_rows(int nblk) { return rmax(1, rmin(PDN_STAGE, nblk / 64)); }
+
+// Sum of acc over the workgroup, deterministic (fixed shuffle tree per wave,
+// waves in order); the NTM totals land in out[0], out[stride], ... from threads 0..NTM-1.
+template <int NT, int NTM = PDN_NTERMS>
+__device__ void block_reduce_store(const double *acc, double *out, int stride, double *sh)
 {
     // deterministic: fixed shuffle tree inside each wave, waves summed in order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = NT / 64;
 #pragma unroll
-    for (int k = 0; k < PDN_NTERMS; ++k) {
+    for (int k = 0; k < NTM; ++k) {
         double v = acc[k];
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         if (lane == 0) sh[k * NW + wave] = v;
     }
     __syncthreads();
-    if (threadIdx.x < PDN_NTERMS) {
+    if (threadIdx.x < NTM) {
         double v = 0;
         for (int w = 0; w < NW; ++w) v += sh[threadIdx.x * NW + w];
-        out[threadIdx.x] = v;
+        out[threadIdx.x * stride] = v;
     }
+}
+
+// Closing a contact pass (one workgroup of NT threads, after the pass):
+// fixed-order sums of the previous pass's element partials and this pass's
+// contact partials give the energy books of the last complete level
+// (reported one step late), the striker is advanced and the history row of
+// the step written.
+template <int NT, typename R>
+__device__ void contact_books(const ElemArgs<R> &A, double *sh)
+{
+    __shared__ double tot[PDN_NTERMS];
+    const int t = threadIdx.x, nblk = A.tiles_x * A.tiles_y;
+    double q[PDN_NTERMS];
+#pragma unroll
+    for (int k = 0; k < PDN_NTERMS; ++k) q[k] = 0.0;
+    // element terms of the previous pass: its stage rows; contact terms of
+    // this pass: the tiles around the candidate window (others add zeros)
+    const int ns = books_stage_rows(nblk), wtx = A.wt1 - A.wt0, nw = wtx * (A.wu1 - A.wu0);
+    for (int b = t; b < ns; b += NT) {
+#pragma unroll
+        for (int k = 0; k < T_FC; ++k) q[k] += A.stage[b * PDN_NTERMS + k];
+    }
+    for (int b = t; b < nw; b += NT) {
+        const int tile = A.wt0 + b % wtx + A.tiles_x * (A.wu0 + b / wtx);
+#pragma unroll
+        for (int k = T_FC; k < PDN_NTERMS; ++k) q[k] += A.partials[(int64_t)k * A.prow + tile];
+    }
+    block_reduce_store<NT>(q, tot, 1, sh);
+    __syncthreads();
+    if (t != 0) return;
+    // every update is made on a register copy, loaded and stored back at once
+    DevGlobals G = *A.gl;
+    const double *P = tot;
+    const double dt = A.dt, g = A.grav, ms = G.ms;
+    // the striker prediction of the pass (same arithmetic as its workgroups)
+    const double Fz = G.Fprev[2];
+    const double az = -g - Fz / ms;
+    const double cz_old = G.c[2], Vz_old = G.V[2];
+    const double cz = cz_old + dt * Vz_old + 0.5 * dt * dt * az;
+    const double kes_level = 0.5 * ms * (G.V[0] * G.V[0] + G.V[1] * G.V[1] + G.V[2] * G.V[2]);
+    // books of level s (= completed steps), final now
+    if (!G.first) {
+        G.e_wint += G.half_int + P[T_WA];
+        G.e_wc += P[T_WCP];
+    } else {
+        G.mz0 = P[T_MZ];
+    }
+    // gravity is constant: its work is -g (sum m d_z - initial), the
+    // trapezoidal sum telescoped (phi = 1)
+    G.e_wgp = -g * (P[T_MZ] - G.mz0);
+    G.half_int = P[T_WB] + P[T_WIC];
+    G.e_kep = P[T_KE] + P[T_KEC];
+    G.e_uel = P[T_UEL];
+    G.e_kes = kes_level;
+    G.e_ws = G.ws_acc;
+    G.e_wgs = G.wgs_acc;
+    G.e_level = (double)G.step;
+    G.fallback_gp += P[T_AUX];
+    G.sur_gp += P[T_SURN];
+    // a non-finite displacement or velocity propagates into these sums
+    if (!(isfinite(P[T_KE]) && isfinite(P[T_WA]) && isfinite(P[T_WB]) && isfinite(P[T_MZ])))
+        G.flag_unstable = 1;
+    if (P[T_OVF] > 0.0) G.flag_overflow = 1;
+    // striker update and its works (force frozen over the step)
+    const double dz = cz - cz_old;
+    G.ws_acc += Fz * dz;
+    G.wgs_acc += ms * g * (-dz);
+    G.c[2] = cz;
+    G.V[2] = Vz_old + dt * az;
+    G.Fprev[0] = P[T_FC]; G.Fprev[1] = P[T_FC + 1]; G.Fprev[2] = P[T_FC + 2];
+    const int passes = P[T_REL] > 0.0 ? 2 : 1;
+    G.reset_passes += passes;
+    G.released += (int64_t)P[T_REL];
+    if (passes > G.max_passes) G.max_passes = passes;
+    G.active = (int64_t)P[T_ACT];
+    if (G.step < G.hist_cap) {
+        A.hist[3 * G.step + 0] = (double)(G.step + 1) * dt;
+        A.hist[3 * G.step + 1] = -P[T_FC + 2];
+        A.hist[3 * G.step + 2] = -(cz - G.c0[2]);
+    }
+    G.step += 1;
+    G.first = 0;
+    *A.gl = G;
 }
 
 // one workgroup's tile of one plate; block partials go to A.partials[tile].
@@ -417,6 +505,80 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         }
     };
 
+    // ---- contact step (Section 2.1, Eqs. 2-3, Algorithms 1-2) ----
+    // Detection on the predictor of a top-surface candidate, projection onto
+    // the sphere, reaction, release of adhesion nodes (Eq. 2) with the repeated
+    // pass.  A node's correction depends on that node only, so every workgroup
+    // that reads it (its owner and the neighbours reading it as halo) corrects
+    // its copy identically; the owner alone stores state and sums.
+    auto contact_correct = [&](double (&pd)[3], double (&pv)[3]) {
+        // Rigid body first (Gauss-Seidel): every workgroup advances the striker
+        // with the force of the plate's last step frozen over the step (the
+        // books kernel repeats this arithmetic and stores it).  Lateral motion
+        // of the striker is constrained.
+        const DevGlobals *G = A.gl;
+        const double Fz = G->Fprev[2];
+        const double az = -A.grav - Fz / G->ms;
+        const double cz = G->c[2] + A.dt * G->V[2] + 0.5 * A.dt * A.dt * az;
+        const double cx = G->c[0], cy = G->c[1], Rs = G->R;
+        if (!nvalid || gi < A.ci0 || gi >= A.ci1 || gj < A.cj0 || gj >= A.cj1) return;
+        const int64_t j = (gi - A.ci0) + (int64_t)(A.ci1 - A.ci0) * (gj - A.cj0);
+        const double dt = A.dt, phi = A.phi;
+        const bool lat = A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny);
+        const double m = mxy * cload(A.mz + (A.K - 1));
+        const double rx = A.xs[gi] + pd[0] - cx, ry = A.ys[gj] + pd[1] - cy, rz = A.ztop + pd[2] - cz;
+        const double dist = sqrt(rx * rx + ry * ry + rz * rz);
+        const double gap = dist - Rs;
+        double nv[3] = {0.0, 0.0, -1.0};
+        if (dist > 0.0) { nv[0] = rx / dist; nv[1] = ry / dist; nv[2] = rz / dist; }
+        bool act = A.active_in[j] != 0 || (gap < 0.0 && rz <= 0.0);
+        double fc[3] = {0, 0, 0};
+        int passes = 0, released = 0;
+        for (;;) {
+            ++passes;
+            bool rel = false;
+            if (act) {
+                double fn = 0;
+                for (int c = 0; c < 3; ++c) {
+                    const double d1 = lat ? 0.0 : -gap * nv[c];
+                    fc[c] = m * d1 / (phi * dt * dt);
+                    fn += fc[c] * nv[c];
+                }
+                if (fn < 0.0) { act = false; rel = true; ++released; fc[0] = fc[1] = fc[2] = 0.0; }
+            }
+            if (!rel || passes >= 8) break;
+        }
+        double dv[3] = {0, 0, 0};
+        if (act) {
+            for (int c = 0; c < 3; ++c) {
+                const double da = fc[c] / m;
+                dv[c] = dt * da;
+                pd[c] = pd[c] + phi * dt * dt * da;
+                pv[c] += dv[c];
+            }
+        }
+        if (!nown) return;
+        A.active_out[j] = act ? 1 : 0;
+        if (act) {
+            acc[T_ACT] += 1.0;
+            const bool ring = (gi == A.ci0 && gi > 0) || (gi == A.ci1 - 1 && gi < nx) ||
+                              (gj == A.cj0 && gj > 0) || (gj == A.cj1 - 1 && gj < ny);
+            if (ring) acc[T_OVF] += 1.0;                          // left the search window
+        }
+        acc[T_REL] += (double)released;
+        for (int c = 0; c < 3; ++c) {
+            const double vpv = A.vprev[3 * j + c];
+            acc[T_FC + c] += fc[c];                               // reaction sum
+            acc[T_KEC] += 0.5 * m * vpv * dv[c];                  // kinetic-energy correction
+            acc[T_WIC] += 0.5 * dt * dv[c] * A.fside[3 * j + c];  // internal-work correction
+            acc[T_WCP] += 0.5 * dt * vpv * (A.fcprev[3 * j + c] + fc[c]);   // contact work on the plate
+            A.vprev[3 * j + c] = pv[c];
+            A.fcprev[3 * j + c] = fc[c];
+            A.cand[6 * j + c] = pd[c];
+            A.cand[6 * j + 3 + c] = pv[c];
+        }
+    };
+
     // layer k-1 (between node planes k-1 and k), then the update of plane k-1
     auto layer_step = [&](int k, double (&pd)[3], double (&pv)[3]) {
         const LayerInfo Lk = cload(A.layers + (k - 1));
@@ -534,14 +696,41 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     fetch_plane(1, pdB, pvB);
     fetch_plane(2, pdA, pvA);
     fetch_r(0);
+    // layers below the top plane in pairs; the top plane is staged by one
+    // call site after the contact step (its predictor is moved to set B)
+    const int top = A.K - 1;
     int k = 1;
-    for (; k + 1 < A.K; k += 2) {
+    for (; k + 1 < top; k += 2) {
         layer_step(k, pdB, pvB);
         layer_step(k + 1, pdA, pvA);
     }
-    if (k < A.K) layer_step(k, pdB, pvB);
+    if (k < top) {
+        layer_step(k, pdB, pvB);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pdB[c] = pdA[c];
+            pvB[c] = pvA[c];
+        }
+    }
+    if (A.contact) contact_correct(pdB, pvB);
+    layer_step(top, pdB, pvB);
     if (nown) update_node(A.K - 1, carry);
-    block_reduce_store<NT>(acc, A.partials + (int64_t)tile * PDN_NTERMS, red);
+    block_reduce_store<NT>(acc, A.partials + tile, A.prow, red);
+    // first stage of the books of this pass: the element terms of the
+    // previous pass over a contiguous range of its tiles
+    const int nblk = A.tiles_x * A.tiles_y, ns = books_stage_rows(nblk);
+    if (A.contact && tile < ns) {
+        const int lo = (int)((int64_t)nblk * tile / ns), hi = (int)((int64_t)nblk * (tile + 1) / ns);
+        double q[T_FC];
+#pragma unroll
+        for (int k = 0; k < T_FC; ++k) q[k] = 0.0;
+        for (int b = lo + t; b < hi; b += NT) {
+#pragma unroll
+            for (int k = 0; k < T_FC; ++k) q[k] += A.partials_prev[(int64_t)k * A.prow + b];
+        }
+        __syncthreads();                    // red is reused
+        block_reduce_store<NT, T_FC>(q, A.stage + tile * PDN_NTERMS, 1, red);
+    }
 }
 
 template <typename R, int TX, int TY, bool SUR>
@@ -575,6 +764,23 @@ void k_elem_node_batch(const ElemArgs<R> *__restrict__ args, const int *__restri
     elem_node_tile<R, TX, TY, SUR>(A, b - start[c]);
 }
 
+#define PDN_BOOKS_THREADS 256
+template <typename R>
+__global__ __launch_bounds__(PDN_BOOKS_THREADS) void k_books(ElemArgs<R> A)
+{
+    __shared__ double red[PDN_NTERMS * (PDN_BOOKS_THREADS / 64)];
+    contact_books<PDN_BOOKS_THREADS>(A, red);
+}
+
+// one workgroup per case
+template <typename R>
+__global__ __launch_bounds__(PDN_BOOKS_THREADS) void k_books_batch(const ElemArgs<R> *__restrict__ args)
+{
+    __shared__ double red[PDN_NTERMS * (PDN_BOOKS_THREADS / 64)];
+    const ElemArgs<R> A = args[blockIdx.x];
+    contact_books<PDN_BOOKS_THREADS>(A, red);
+}
+
 // ---------------------------------------------------------------------------
 // launchers of one variant
 // ---------------------------------------------------------------------------
@@ -594,6 +800,7 @@ static hipError_t launch_elem_node_v(const ElemArgs<R> &a, int tile, hipStream_t
     case PDN_TILE_32x8: return launch_en<R, 32, 8, SUR>(a, s);
     case PDN_TILE_8x8: return launch_en<R, 8, 8, SUR>(a, s);
     case PDN_TILE_15x15: return launch_en<R, 15, 15, SUR>(a, s);
+    case PDN_TILE_31x15: return launch_en<R, 31, 15, SUR>(a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -615,6 +822,7 @@ static int lds_v(int tile)
     case PDN_TILE_32x8: return lds_of<R, 32, 8, SUR>();
     case PDN_TILE_8x8: return lds_of<R, 8, 8, SUR>();
     case PDN_TILE_15x15: return lds_of<R, 15, 15, SUR>();
+    case PDN_TILE_31x15: return lds_of<R, 31, 15, SUR>();
     default: return -1;
     }
 }
@@ -637,6 +845,7 @@ static hipError_t launch_elem_node_batch_v(const ElemArgs<R> *args, const int *s
     case PDN_TILE_32x8: return launch_enb<R, 32, 8, SUR>(args, start, ncase, nblocks, s);
     case PDN_TILE_8x8: return launch_enb<R, 8, 8, SUR>(args, start, ncase, nblocks, s);
     case PDN_TILE_15x15: return launch_enb<R, 15, 15, SUR>(args, start, ncase, nblocks, s);
+    case PDN_TILE_31x15: return launch_enb<R, 31, 15, SUR>(args, start, ncase, nblocks, s);
     default: return hipErrorInvalidValue;
     }
 }

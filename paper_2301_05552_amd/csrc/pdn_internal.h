@@ -6,11 +6,16 @@
 #define PDN_MAX_PLIES 64
 #define PDN_MAX_LAYERS (3 * PDN_MAX_PLIES)
 #define PDN_K1_THREADS 256
-#define PDN_NTERMS 7          // per-block partials of the element/node kernel (at most 8)
-// partial slots: 0.5 m v^n.v~^{n+1}, 0.5 dt v^n.f^n, 0.5 dt v~^{n+1}.f^n,
+#define PDN_NTERMS 16         // per-block partials of the element/node kernel
+#define PDN_STAGE 64          // rows of the first reduction stage of the books
+// element slots: 0.5 m v^n.v~^{n+1}, 0.5 dt v^n.f^n, 0.5 dt v~^{n+1}.f^n,
 // sum m d_z^n, secant energy, surrogate points updated by the exact law,
-// surrogate points updated in total
-enum { T_KE = 0, T_WA = 1, T_WB = 2, T_MZ = 3, T_UEL = 4, T_AUX = 5, T_SURN = 6 };
+// surrogate points updated in total;
+// contact slots (the contact step done in the same pass): reaction sum (3),
+// kinetic-energy correction, internal-work correction, contact work on the
+// plate, active nodes, nodes at the edge of the search window, released nodes
+enum { T_KE = 0, T_WA = 1, T_WB = 2, T_MZ = 3, T_UEL = 4, T_AUX = 5, T_SURN = 6, T_FC = 7, T_KEC = 10, T_WIC = 11,
+       T_WCP = 12, T_ACT = 13, T_OVF = 14, T_REL = 15 };
 
 // Per-ply constants in the arithmetic type R of the element kernel.
 template <typename R>
@@ -63,11 +68,9 @@ struct DevGlobals {
     int64_t reset_passes, released, max_passes, active;
     double fallback_gp;              // surrogate: GP updates that used the exact law
     double sur_gp;                   // surrogate: GP updates of surrogate plies
-    unsigned int ticket;             // contact-kernel workgroups finished (last one reduces)
     unsigned int pad1;
 };
 
-#define PDN_CQ 18                    // per-workgroup results of the contact kernel
 
 // Everything the element/node kernel needs, passed by value.
 template <typename R>
@@ -90,24 +93,37 @@ struct ElemArgs {
     const PlyC<R> *ply;              // n_plies
     const uint8_t *bc_bottom;        // (nx+1)(ny+1) fixed-DOF bits of plane 0
     double *fside;                   // 3 per candidate: internal force at level n
-    double *partials;                // PDN_NTERMS per block
+    double *partials;                // term-major [PDN_NTERMS][prow], a column per block (written by this pass)
+    int prow;                        // term stride of the partials
+    // books reduction: a contact pass's first PDN_STAGE tiles sum the element
+    // terms of the previous pass into stage rows (PDN_NTERMS apart); contact
+    // terms are summed over tiles [wt0, wt1) x [wu0, wu1), which hold every
+    // owner of a candidate node
+    double *stage;
+    int wt0, wt1, wu0, wu1;
+    // contact step (Algorithms 1-2) done by this pass on the top plane; 0 for
+    // passes that only restart the scheme from a state
+    int contact;
+    DevGlobals *gl;                  // striker, books, counters
+    const double *xs, *ys;           // grid lines (top-plane node positions)
+    double ztop;
+    const uint8_t *active_in;        // per candidate: active set found in the previous step
+    uint8_t *active_out;
+    double *vprev, *fcprev;          // per candidate, 3 each: velocity and reaction of the last step
+    double *cand;                    // per candidate: corrected displacement and velocity (3 + 3)
+    const double *partials_prev;     // block partials of the previous pass
+    double *hist;                    // 3 per step
     // constitutive surrogate: packed networks (PlyC::sur selects one), fallback thresholds
     const uint4 *mlp;
     float sur_dmg, sur_res;
 };
 
+// candidate bookkeeping of the contact step (initialisation, state arrays)
 struct ContactArgs {
-    DevGlobals *gl;
-    double *d, *v;                   // predictor buffer, corrected in place
-    const double *xs, *ys, *mx, *my; // grid lines and mass factors
-    double ztop, mztop;
-    int nx, ny, K, clamp_lateral;
-    int ci0, ci1, cj0, cj1;
-    uint8_t *active;                 // per candidate
+    double *d, *v;                   // state buffers of the last completed level
+    int nx, ny, K;
+    int ci0, ci1, cj0, cj1;          // candidate window (node columns, half-open)
+    uint8_t *active;                 // 2 per candidate (the two step parities)
     double *vprev, *fcprev;          // per candidate, 3 each
-    const double *fside;             // per candidate internal force (from the element kernel)
-    const double *partials;          // element-kernel block partials
-    int nblocks;
-    double *hist;                    // 3 per step
-    double *blk;                     // PDN_CQ per contact workgroup
+    double *cand;                    // per candidate, 6
 };

@@ -6,28 +6,32 @@
 // threads of an element-tile workgroup: one per element column and one per node column
 #define PDN_TILE_THREADS(TX, TY) ((PDN_MAX2((TX) * (TY), ((TX) + 1) * ((TY) + 1)) + 63) / 64 * 64)
 
-enum { PDN_TILE_16x16 = 0, PDN_TILE_32x8 = 1, PDN_TILE_8x8 = 2, PDN_TILE_15x15 = 3, PDN_TILE_COUNT = 4 };
-static const int pdn_tile_dims[PDN_TILE_COUNT][2] = {{16, 16}, {32, 8}, {8, 8}, {15, 15}};
+enum { PDN_TILE_16x16 = 0, PDN_TILE_32x8 = 1, PDN_TILE_8x8 = 2, PDN_TILE_15x15 = 3, PDN_TILE_31x15 = 4,
+       PDN_TILE_COUNT = 5 };
+static const int pdn_tile_dims[PDN_TILE_COUNT][2] = {{16, 16}, {32, 8}, {8, 8}, {15, 15}, {31, 15}};
 
 namespace pdn {
 // sur: the instantiation that evaluates the surrogate network on plies of law 2
 template <typename R>
 hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, hipStream_t s);
+// closes a contact pass (a.contact): books, striker update, history row
+template <typename R>
+hipError_t launch_books(const ElemArgs<R> &a, hipStream_t s);
 template <typename R>
 hipError_t launch_elem_node_sur(const ElemArgs<R> &a, int tile, hipStream_t s);
 // batched launches: case c owns blocks start[c] .. start[c+1]-1 (args and start in device memory)
+// contact: the arguments are contact passes; a books kernel closes each case's step
 template <typename R>
 hipError_t launch_elem_node_batch(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
-                                  bool sur, hipStream_t s);
+                                  bool sur, bool contact, hipStream_t s);
 template <typename R>
 hipError_t launch_elem_node_batch_sur(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
                                       hipStream_t s);
-hipError_t launch_contact_batch(const ContactArgs *args, const int *start, int ncase, int nblocks, hipStream_t s);
-int contact_blocks(const ContactArgs &c);
+
 int elem_node_lds_bytes(int mixed, int tile, bool sur);   // static LDS of one workgroup (-1 on error)
 int elem_node_lds_bytes_sur(int mixed, int tile);
-hipError_t launch_contact(const ContactArgs &c, hipStream_t s);
 hipError_t launch_contact_init(const ContactArgs &c, int reset_active, hipStream_t s);
+hipError_t launch_cand_scatter(const ContactArgs &c, hipStream_t s);
 template <typename R>
 hipError_t launch_damage_bulk(const R *r, const LayerInfo *layers, const int *bulk_layer, const PlyC<R> *ply,
                               const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind, double *out,

@@ -125,7 +125,7 @@ def test_tile_shape_invariance_bitwise(prec):
     cfg = copy.deepcopy(W.tiny(47, 23, 3, 1, angles=[0, 45, 90], cohesive=1, law=W.LAW_CDM, lx=47e-3,
                                ly=23e-3, ply_thickness=0.5e-3, v0=8.0, mass=0.1, R=4e-3, precision=prec))
     res = []
-    for tile in ((15, 15), (16, 16), (32, 8), (8, 8)):
+    for tile in ((15, 15), (16, 16), (32, 8), (8, 8), (31, 15)):
         try:
             g = pdn.Simulation(cfg, tile=tile)
         except pdn.PdnError as e:                 # workgroup does not fit this device's LDS
