@@ -162,9 +162,11 @@ def _train_networks(cfg, steps: int) -> tuple:
     return [nets[(m["YT"], m["SL"])] for m in cfg["materials"]], list(reps.values())
 
 
-def _run(cfg, stream, tile, nets, res, pre, warmup, steps):
+def _run(cfg, stream, tile, nets, res, pre, warmup, steps, areas=None):
     """Pre-roll, warm-up and timed steps of one configuration; returns
-    (ms per step, info, peak force over the whole run)."""
+    (ms per step, info, peak force over the whole run).  With a dict in
+    `areas` it also receives the projected fibre and matrix damage areas at
+    the end (d > 0, d >= 0.5, d >= 0.999)."""
     import torch
     import paper_2301_05552_amd as pdn
     sim = pdn.Simulation(cfg, stream=stream, tile=tile)
@@ -179,6 +181,13 @@ def _run(cfg, stream, tile, nets, res, pre, warmup, steps):
     el = time.perf_counter() - t0
     info = sim.info()
     f = sim.contact_force()[1]
+    if areas is not None:
+        m = cfg["mesh"]
+        cell = (m["lx"] / m["nx"]) * (m["ly"] / m["ny"])
+        for name, kind in (("fibre", pdn.DMG_PROJ_FIBRE), ("matrix", pdn.DMG_PROJ_MATRIX)):
+            d = sim.damage_field(kind)
+            areas[name] = {thr: float(((d > 0) if thr == "0" else (d >= float(thr))).sum()) * cell
+                           for thr in ("0", "0.5", "0.999")}
     sim.close()
     return 1e3 * el / steps, info, float(f.max()) if len(f) else 0.0
 
@@ -187,8 +196,8 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
     """The metric's second half: the same plate with the intralaminar update
     by the trained network (exact law as fallback), at the stated residual bar
     1e-3 and at a looser 3e-2; speed against the plain path on this GPU, and
-    the peak-force error against the FP64 oracle on the 300 x 200 x 8 plate
-    run to 3 ms (when its stored oracle run is present)."""
+    the peak-force and damage-area errors against the FP64 oracle on the
+    300 x 200 x 8 plate run to 3 ms (when its stored oracle run is present)."""
     import workloads as W
     cfg = W.config3(1)
     t0 = time.perf_counter()
@@ -217,10 +226,17 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
                 "oracle_peak_force_N": g["peak_force_N"] if n == g["steps"] else None}
         for name, nn, res in (("plain_mixed", None, 0), ("surrogate_res_0.001", nets2, 1e-3),
                               ("surrogate_res_0.03", nets2, 3e-2)):
-            ms, info, fpk = _run(c2, stream, (15, 15), nn, res, 0, 0, n)
+            ar = {}
+            ms, info, fpk = _run(c2, stream, (15, 15), nn, res, 0, 0, n, areas=ar)
             e = {"peak_force_N": fpk, "ms_per_step": ms}
             if gate["oracle_peak_force_N"]:
                 e["peak_force_rel_err"] = abs(fpk - g["peak_force_N"]) / g["peak_force_N"]
+                # projected damage areas against the oracle's (the 2 % bar)
+                e["damage_area_rel_err"] = {
+                    f"{k}_{thr}": abs(ar[k][thr] - g["projected_damage"][k][thr]["area_m2"]) /
+                    g["projected_damage"][k][thr]["area_m2"]
+                    for k in ("fibre", "matrix") for thr in ("0", "0.5", "0.999")
+                    if g["projected_damage"][k][thr]["area_m2"] > 0}
             if nn is not None:
                 e["fallback_fraction"] = info["fallback_fraction"]
             gate[name] = e

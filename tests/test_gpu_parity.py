@@ -84,6 +84,20 @@ def test_cdm_fp64_with_damage():
         assert rel(g.damage_field(kind), o.damage_field(kind), floor=1.0) <= 1e-9
 
 
+def test_tw_phi_1033_fp64():
+    """The dissipative Tchamwa-Wielgosz member (phi = 1.033, Section 2.2.1)
+    with damage and contact: same 1e-10 bar as phi = 1.  The window is 300
+    steps: at 400 the softening points have amplified the summation-order
+    round-off to 2e-10 in the force (the phi = 1 case sits just below)."""
+    _note("cdm fp64 12x12x4 phi=1.033 300 steps")
+    cfg = cdm_case()
+    cfg["mesh"]["phi"] = 1.033
+    o, g = run_both(cfg, 300)
+    d = compare(o, g, cfg)
+    _check64(d, "tw phi 1.033")
+    assert o.history()[1].max() > 0
+
+
 def test_czm_fp64_with_delamination():
     """Window ends ~100 steps after the first node pairs separate completely:
     beyond that the softening interface amplifies round-off (~10x per 100
