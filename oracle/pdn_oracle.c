@@ -234,15 +234,15 @@ static void compliance_normal(const orc_material *m, double d1, double d2, doubl
     H[1][2] = H[2][1] = -m->nu23 / m->E2;
 }
 
-/* sigma = H(d)^{-1} eps with shear damage on 23 (d2) and 13, 12 (d6) */
-static void stress_from_compliance(const orc_material *m, double d1, double d2, double d6,
+/* sigma = H(d)^{-1} eps with shear damage d4 on 23 and d6 on 13, 12 */
+static void stress_from_compliance(const orc_material *m, double d1, double d2, double d4, double d6,
                                    const double eps[6], double sig[6])
 {
     double H[3][3], C[3][3];
     compliance_normal(m, d1, d2, H);
     inv3(H, C);
     for (int i = 0; i < 3; ++i) sig[i] = C[i][0] * eps[0] + C[i][1] * eps[1] + C[i][2] * eps[2];
-    sig[3] = (1.0 - d2) * m->G23 * eps[3];
+    sig[3] = (1.0 - d4) * m->G23 * eps[3];
     sig[4] = (1.0 - d6) * m->G13 * eps[4];
     sig[5] = (1.0 - d6) * m->G12 * eps[5];
 }
@@ -306,7 +306,7 @@ void orc_cdm(const orc_material *m, double lc, const double eps[6], double r[4],
     /* Algorithm 4, elastic-damage reading: effective stress, loading
      * functions, thresholds, damage variables, nominal stress. */
     double se[6];
-    stress_from_compliance(m, 0, 0, 0, eps, se);          /* effective stress */
+    stress_from_compliance(m, 0, 0, 0, 0, eps, se);       /* effective stress */
     if (m->law == 0) {
         for (int i = 0; i < 6; ++i) sig[i] = se[i];
         if (dmg) for (int i = 0; i < 5; ++i) dmg[i] = 0;
@@ -347,9 +347,13 @@ void orc_cdm(const orc_material *m, double lc, const double eps[6], double r[4],
     double d2p = dmg_expo(r[2], YT, m->E2, m->GYT, lc);
     double d2m = dmg_expo(r[3], YC, m->E2, m->GYC, lc);
     double d6 = dmg_expo(r[2], SL, m->G12, m->GSL, lc);
+    /* crack closure (tension or compression variable by the sign of the
+     * effective stress) acts on the normal terms only; the transverse shear
+     * keeps the tensile matrix damage, so that no closed strain cycle
+     * returns energy (the model is thermodynamically consistent, Sec. 2.3.1) */
     double d1 = se[0] >= 0 ? d1p : d1m;
     double d2 = se[1] >= 0 ? d2p : d2m;
-    stress_from_compliance(m, d1, d2, d6, eps, sig);
+    stress_from_compliance(m, d1, d2, d2p, d6, eps, sig);
     if (dmg) { dmg[0] = d1p; dmg[1] = d1m; dmg[2] = d2p; dmg[3] = d2m; dmg[4] = d6; }
 }
 

@@ -75,7 +75,10 @@ __device__ __forceinline__ void cdm_nominal(const PlyC<R> &P, R lc, R YT, R YC, 
     sg[0] = (c00 * e[0] + c01 * e[1] + c02 * e[2]) * inv;
     sg[1] = (c01 * e[0] + c11 * e[1] + c12 * e[2]) * inv;
     sg[2] = (c02 * e[0] + c12 * e[1] + c22 * e[2]) * inv;
-    sg[3] = (R(1) - d2) * P.G23 * e[3];
+    // crack closure acts on the normal terms only: the transverse shear keeps
+    // the tensile matrix damage, so no closed strain cycle returns energy
+    // (thermodynamic consistency, Section 2.3.1)
+    sg[3] = (R(1) - d2p) * P.G23 * e[3];
     sg[4] = (R(1) - d6) * P.G13 * e[4];
     sg[5] = (R(1) - d6) * P.G12 * e[5];
 }

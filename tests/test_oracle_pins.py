@@ -442,6 +442,40 @@ def test_cdm_irreversible_secant_unloading():
     assert np.nanmax(np.abs(un - un[0])) <= 1e-12 * abs(un[0])
 
 
+def test_cdm_closed_strain_cycle_returns_no_energy():
+    """Second law (the model is thermodynamically consistent, Section 2.3.1):
+    after matrix damage in transverse tension, a closed cycle in
+    (eps22, gamma23) that opens the crack, shears it, closes it and unshears
+    it, with no new damage, returns no energy: the net work of the stress
+    around the cycle is not negative (here it is zero, the cycle is elastic).
+    A shear stiffness that followed the crack-closure switch would give
+    -d2+ G23 gamma^2 / 2."""
+    m = W.material_cfrp(False, 0.5e-3)
+    e0 = m["YT"] / m["E2"]
+    r = np.ones(4)
+    for e in np.concatenate([np.linspace(0, 3 * e0, 300), np.linspace(3 * e0, 0, 300)]):
+        eps = np.zeros(6)
+        eps[1] = e
+        _, r, d = oracle.cdm(m, LC3, eps, r)
+    assert d[2] > 0.3 and d[3] == 0.0                   # tensile matrix damage only
+    a, g = 0.5 * e0, 0.5 * m["SL"] / m["G23"]
+    corners = [(0.0, 0.0), (a, 0.0), (a, g), (-a, g), (-a, 0.0), (0.0, 0.0)]
+    t = np.linspace(0.0, 1.0, 2001)
+    path = np.concatenate([np.stack([p + (u - p) * t, q + (v - q) * t], 1)
+                           for (p, q), (u, v) in zip(corners[:-1], corners[1:])])
+    sig = np.zeros_like(path)
+    for k, (e22, g23) in enumerate(path):
+        eps = np.zeros(6)
+        eps[1], eps[3] = e22, g23
+        s, r2, _ = oracle.cdm(m, LC3, eps, r)
+        assert (r2 == r).all()                          # no new damage on the cycle
+        sig[k] = s[1], s[3]
+    work = float(np.sum(0.5 * (sig[1:] + sig[:-1]) * np.diff(path, axis=0)))
+    scale = 0.5 * m["G23"] * g * g
+    assert work >= -1e-9 * scale
+    assert abs(work) <= 1e-6 * scale
+
+
 # ---------------------------------------------------------------------------
 # cohesive law (Algorithm 5 reading)
 # ---------------------------------------------------------------------------
