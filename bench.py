@@ -254,7 +254,7 @@ def main():
     ap.add_argument("--tile", default="15x15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-case batched leg")
-    ap.add_argument("--batched-steps", type=int, default=100)
+    ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--sur-train-steps", type=int, default=16000)
     ap.add_argument("--gate-steps", type=int, default=61000,

@@ -712,7 +712,10 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             pvB[c] = pvA[c];
         }
     }
-    if (A.contact) contact_correct(pdB, pvB);
+    // only workgroups whose node columns (halo included) meet the candidate
+    // window have contact work (the others would load the striker for nothing)
+    if (A.contact && e0x < A.ci1 && e0x + TX >= A.ci0 && e0y < A.cj1 && e0y + TY >= A.cj0)
+        contact_correct(pdB, pvB);
     layer_step(top, pdB, pvB);
     if (nown) update_node(A.K - 1, carry);
     block_reduce_store<NT>(acc, A.partials + tile, A.prow, red);
