@@ -495,11 +495,14 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     };
 
     // lumped-mass integration of plane kp with total internal force f; next predictor
+    // fixed-DOF bits: lateral clamp, and the bottom plane's support bits
+    // (read once; the loop then needs neither the flag nor the table)
+    const int fix_lat = (A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny)) ? 7 : 0;
+    const int fix_bot = fix_lat | (nvalid ? (int)A.bc_bottom[col] : 0);
     auto update_node = [&](int kp, const double f[3]) {
         const int p = kp & 1;
         const int64_t n = col + plane * kp;
-        const int fix_lat = (A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny)) ? 7 : 0;
-        const int bits = fix_lat | (kp == 0 ? (int)A.bc_bottom[col] : 0);
+        const int bits = kp == 0 ? fix_bot : fix_lat;
         const double m = mxy * cload(A.mz + kp);
         const double im = imxy * cload(A.imz + kp);
         const double dt = A.dt, g = A.grav;
@@ -519,12 +522,6 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         }
         store_xyz(A.d_out + 3 * n, dn);
         store_xyz(A.v_out + 3 * n, vn);
-        if (kp == A.K - 1 && gi >= A.ci0 && gi < A.ci1 && gj >= A.cj0 && gj < A.cj1) {
-            const int64_t ci = (gi - A.ci0) + (int64_t)(A.ci1 - A.ci0) * (gj - A.cj0);
-            A.fside[3 * ci + 0] = f[0];
-            A.fside[3 * ci + 1] = f[1];
-            A.fside[3 * ci + 2] = f[2];
-        }
     };
 
     // ---- contact step (Section 2.1, Eqs. 2-3, Algorithms 1-2) ----
@@ -739,7 +736,16 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     if (A.contact && e0x < A.ci1 && e0x + TX >= A.ci0 && e0y < A.cj1 && e0y + TY >= A.cj0)
         contact_correct(pdB, pvB);
     layer_step(top, pdB, pvB);
-    if (nown) update_node(A.K - 1, carry);
+    if (nown) {
+        update_node(A.K - 1, carry);
+        // internal force of a top-plane candidate (the contact step's internal-work correction)
+        if (gi >= A.ci0 && gi < A.ci1 && gj >= A.cj0 && gj < A.cj1) {
+            const int64_t ci = (gi - A.ci0) + (int64_t)(A.ci1 - A.ci0) * (gj - A.cj0);
+            A.fside[3 * ci + 0] = carry[0];
+            A.fside[3 * ci + 1] = carry[1];
+            A.fside[3 * ci + 2] = carry[2];
+        }
+    }
     block_reduce_store<NT>(acc, A.partials + tile, A.prow, red);
     // first stage of the books of this pass: the element terms of the
     // previous pass over a contiguous range of its tiles
