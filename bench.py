@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -144,6 +145,56 @@ def batched_leg(steps: int, warmup: int, stream) -> dict:
             "create_and_autotune_s": setup}
 
 
+# Section 3.2.2, Table 4: the paper's own numerical results for the AS4/8552
+# coupon (its fully integrated elements, graded mesh); context, not targets
+COUPON_PAPER = {0: {"f_max_kN": 8.70, "d_max_mm": 3.60, "E_dis_J": 7.70, "A_del_mm2": 4723.1},
+                1: {"f_max_kN": 8.30, "d_max_mm": 3.70, "E_dis_J": 7.90, "A_del_mm2": 5249.2}}
+
+
+def coupon_leg(levels, stream) -> dict:
+    """The AS4/8552 drop-weight coupon (Section 3.2.2; Table 3's meshes, phi =
+    1.033) run to 5 ms in mixed precision: speed of the whole run and the
+    quantities Table 4 tabulates."""
+    import torch
+    import paper_2301_05552_amd as pdn
+    import workloads as W
+    out = {}
+    for lv in levels:
+        cfg = W.coupon_as4(lv, W.PREC_MIXED)
+        sim = pdn.Simulation(cfg, stream=stream)
+        sim.step(0)                      # set-up (stable time step) without stepping
+        info = sim.info()
+        n = int(math.ceil(cfg["t_end"] / info["dt"]))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < n:
+            k = min(20000, n - done)
+            sim.step(k)
+            done += k
+            log(f"coupon level {lv}: {done}/{n} steps")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        t, f, x = sim.contact_force()
+        e = sim.energies()
+        m = cfg["mesh"]
+        cell = (m["lx"] / m["nx"]) * (m["ly"] / m["ny"])
+        dcoh = sim.damage_field(pdn.DMG_PROJ_COHESIVE)
+        out[f"level{lv}"] = {
+            "mesh": f"{m['nx']}x{m['ny']} in-plane, {m['elems_per_ply']} element(s) per cluster, 6 interfaces",
+            "bulk_gauss_points": info["n_bulk"], "interface_pairs": info["n_pairs"],
+            "dt_s": info["dt"], "steps": n, "wall_s": el, "ms_per_step": 1e3 * el / n,
+            "value": info["n_bulk"] * n / el, "unit": "GP-updates/s",
+            "f_max_kN": float(f.max()) / 1e3, "d_max_mm": float(x.max()) * 1e3,
+            "E_dis_J": e["w_int"] - e["u_el"], "E_absorbed_J": e["ke0"] - e["ke_striker"],
+            "A_del_mm2": {"D>0": float((dcoh > 0).sum()) * cell * 1e6,
+                          "D>=0.5": float((dcoh >= 0.5).sum()) * cell * 1e6,
+                          "D>=0.999": float((dcoh >= 0.999).sum()) * cell * 1e6},
+            "paper_numerical": COUPON_PAPER[lv]}
+        sim.close()
+    return out
+
+
 def _crack_band(cfg) -> float:
     m = cfg["mesh"]
     return (m["lx"] / m["nx"] * m["ly"] / m["ny"] * m["ply_thickness"] / m["elems_per_ply"]) ** (1.0 / 3.0)
@@ -255,6 +306,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-case batched leg")
     ap.add_argument("--batched-steps", type=int, default=1000)
+    ap.add_argument("--coupon-levels", default="0",
+                    help="refinement levels of the AS4/8552 coupon run to 5 ms ('' = skip, '0,1' = both)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--sur-train-steps", type=int, default=16000)
     ap.add_argument("--gate-steps", type=int, default=61000,
@@ -350,6 +403,10 @@ def main():
         log("batched leg: 64 cases")
         res["batched"] = batched_leg(args.batched_steps, 10, stream.cuda_stream)
         log(f"batched: {res['batched']['ms_per_step']:.3f} ms/step, tile {res['batched']['tile']}")
+    if args.coupon_levels:
+        lvls = [int(v) for v in args.coupon_levels.split(",")]
+        log(f"coupon leg: AS4/8552 coupon, levels {lvls}, to 5 ms")
+        res["coupon"] = coupon_leg(lvls, stream.cuda_stream)
     if not args.no_cpu_baseline:
         threads = min(os.cpu_count() or 1, 16)
         log(f"cpu baseline: oracle, {threads} threads")

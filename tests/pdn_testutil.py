@@ -37,10 +37,10 @@ def rel(a, b, floor=0.0):
     return float(np.abs(a - b).max() / den)
 
 
-def run_both(cfg, steps, precision=W.PREC_FP64, tile=None, chunks=1):
+def run_both(cfg, steps, precision=W.PREC_FP64, tile=None, chunks=1, threads=None):
     cfg = copy.deepcopy(cfg)
     cfg["mesh"]["precision"] = precision
-    o = oracle.Oracle(cfg)
+    o = oracle.Oracle(cfg) if threads is None else oracle.Oracle(cfg, threads=threads)
     g = pdn.Simulation(cfg, tile=tile)
     o.step(steps)
     left = steps

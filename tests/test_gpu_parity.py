@@ -98,6 +98,23 @@ def test_tw_phi_1033_fp64():
     assert o.history()[1].max() > 0
 
 
+def test_as4_coupon_fp64():
+    """The AS4/8552 coupon of Section 3.2.2 as meshed at refinement level 0
+    (183 x 131 x 8 clusters, six interfaces, Table 3's counts), with the
+    dissipative phi = 1.033, through first contact.  No node lies under the
+    striker axis on this grid (the nearest is 0.56 mm off it, where the sphere
+    is 20 um higher), so contact starts after about 30 um of travel, near step
+    300.  The largest force difference is that of the first touch (1.7e-8 N
+    on an 84 N reaction, a difference quotient of nearly equal positions) and
+    does not grow; over 500 steps it is 8e-11 of the history's peak."""
+    _note("as4 coupon level 0 fp64 phi=1.033 500 steps")
+    cfg = W.coupon_as4(0, W.PREC_FP64)
+    o, g = run_both(cfg, 500, threads=8)
+    d = compare(o, g, cfg)
+    _check64(d, "as4 coupon")
+    assert o.history()[1].max() > 0
+
+
 def test_czm_fp64_with_delamination():
     """Window ends ~100 steps after the first node pairs separate completely:
     beyond that the softening interface amplifies round-off (~10x per 100

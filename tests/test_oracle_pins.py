@@ -62,6 +62,16 @@ def test_table3_counts(level):
     assert c["n_nodes"] == lv["n_nodes"]
 
 
+@pytest.mark.parametrize("level", [0, 1])
+def test_as4_coupon_workload_matches_table3(level):
+    """The coupon workload's mesh is the one whose counts Table 3 prints."""
+    _, lv, _ = _table3_mesh(level)
+    c = oracle.mesh_counts(W.coupon_as4(level)["mesh"])
+    assert c["n_bulk"] + c["n_cohesive"] == lv["n_elements"]
+    assert c["n_nodes"] == lv["n_nodes"]
+    assert c["n_cohesive"] == 6 * lv["nx"] * lv["ny"]      # six interfaces between differing clusters
+
+
 def test_eq_mmu_element_count():
     """Eq. (mmu): n_e = 8 n_e^0 - 4 n_e,ELINT^0 with n_e^0 all base elements."""
     _, _, m0 = _table3_mesh(0)

@@ -185,6 +185,51 @@ def config5(precision=PREC_MIXED) -> dict:
     return c
 
 
+# The AS4/8552 drop-weight coupon of Section 3.2.2: [45_4/0_4/-45_4/90_4]_S of
+# 0.181 mm plies, modelled as eight clusters of four plies (the two middle 90
+# clusters form the eight-ply cluster), interface elements between clusters of
+# different angle (six), 150 x 100 mm on the 125 x 75 mm window, 5 kg striker
+# of radius 8 mm at 2.78 m/s (19.3 J), 5 ms.  The in-plane grid reproduces the
+# element and node counts of Table 3 at both refinement levels.
+AS4_PLY = 0.181e-3
+AS4_CLUSTERS = [45, 0, -45, 90, 90, -45, 0, 45]
+
+
+def material_as4_8552(outer: bool, t_lam: float, law: int = LAW_CDM) -> dict:
+    """Table 1, Hexply AS4/8552 column, in SI.  ``outer`` selects the outer
+    cluster's in-situ strengths (Y_T = 74.2, S_L = 94.4 MPa) instead of the
+    embedded ones (Y_T = 117.5, S_L = 120.8 MPa; the same for 4- and 8-ply
+    clusters).  Interface: tau_I = Y_T, tau_II = S_L of the base material,
+    penalty K_I = 50 E2 / t_lam (Section 2.3.2's bound; Table 1's value
+    violates it)."""
+    E2 = 7.63e9
+    return dict(E1=128.0e9, E2=E2, E3=E2, nu12=0.35, nu13=0.35, nu23=0.45,
+                G12=4.358e9, G13=4.358e9, G23=2.631e9, rho=1590.0, law=law,
+                XT=2300.0e6, XC=1531.0e6,
+                YT=(74.2e6 if outer else 117.5e6), YC=199.8e6,
+                SL=(94.4e6 if outer else 120.8e6), alpha0_deg=53.0,
+                GXT=81.5e3, GXC=106.3e3, GYT=280.0, GYC=1313.0, GSL=790.0,
+                fXT=0.1, fGT=0.6, fXC=0.1, fGC=0.9,
+                KI=50.0 * E2 / t_lam, tauI=74.2e6, tauII=94.36e6,
+                GIc=280.0, GIIc=790.0, eta_bk=1.45)
+
+
+def coupon_as4(level: int = 0, precision=PREC_MIXED, phi: float = 1.033) -> dict:
+    """The AS4/8552 coupon at refinement level 0 (183 x 131, one element per
+    cluster) or 1 (366 x 262, two), with the dissipative Tchamwa-Wielgosz
+    member phi = 1.033 of Section 2.2.1 by default."""
+    nx, ny, epc = ((183, 131, 1), (366, 262, 2))[level]
+    t = 4 * AS4_PLY
+    return dict(
+        name=f"as4-8552-coupon-level{level}",
+        mesh=_mesh(nx, ny, 8, epc, 0.150, 0.100, t, AS4_CLUSTERS, cohesive=1,
+                   bc=BC_ASTM_WINDOW, window_lx=0.125, window_ly=0.075,
+                   clamp_radius=5.0e-3, precision=precision, phi=phi),
+        materials=[material_as4_8552(p in (0, 7), t) for p in range(8)],
+        impactor=impactor(8.0e-3, 5.0, v0=2.78),
+        t_end=5.0e-3)
+
+
 def config4_cases(n_cases=64, base_seed=0x9D5EED00) -> list:
     """Uneven batch: per case s, SplitMix64(base_seed + s) draws, in this order,
     plies P ~ U{4..16}, P angles from {0, 45, -45, 90}, target elements
