@@ -103,7 +103,7 @@ def copy_calibration(nbytes: int):
 def cpu_baseline(steps: int, threads: int) -> dict:
     import oracle
     import workloads as W
-    cfg = W.scaled(W.config3(W.PREC_FP64), 150, 100, lx=150 * 0.125e-3, ly=100 * 0.125e-3)
+    cfg = W.scaled(W.plate_qi8_1200x800x16(W.PREC_FP64), 150, 100, lx=150 * 0.125e-3, ly=100 * 0.125e-3)
     cfg["mesh"]["bc"] = W.BC_CLAMPED_EDGES
     o = oracle.Oracle(cfg, threads=threads)
     o.step(2)                                  # set-up outside the timed region
@@ -123,7 +123,7 @@ def batched_leg(steps: int, warmup: int, stream) -> dict:
     import torch
     import paper_2301_05552_amd as pdn
     import workloads as W
-    cfgs = W.config4_cases()
+    cfgs = W.batch_cases_64()
     sims = [pdn.Simulation(c, stream=stream) for c in cfgs]
     t0 = time.perf_counter()
     b = pdn.Batch(sims)
@@ -253,7 +253,7 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
     the peak-force and damage-area errors against the FP64 oracle on the
     300 x 200 x 8 plate run to 3 ms (when its stored oracle run is present)."""
     import workloads as W
-    cfg = W.config3(1)
+    cfg = W.plate_qi8_1200x800x16(1)
     t0 = time.perf_counter()
     nets, reps = _train_networks(cfg, train_steps)
     out = {"training": {"networks": len(reps), "wall_s": time.perf_counter() - t0,
@@ -269,11 +269,11 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
         out[f"res_{res:g}"] = {"value": info["n_bulk"] / (ms * 1e-3), "unit": "GP-updates/s", "ms_per_step": ms,
                                "speedup_vs_plain": plain_ms / ms, "fallback_fraction": info["fallback_fraction"],
                                "peak_force_N": fpk, "plain_peak_force_N": f_plain}
-    gold = os.path.join(ROOT, "tests", "golden", "config2_fp64_oracle.json")
+    gold = os.path.join(ROOT, "tests", "golden", "qi8_300x200x8_fp64_oracle.json")
     if gate_steps and os.path.exists(gold):
         with open(gold) as fh:
             g = json.load(fh)
-        c2 = W.config2(1)
+        c2 = W.plate_qi8_300x200x8(1)
         nets2, _ = _train_networks(c2, train_steps)
         n = min(gate_steps, g["steps"])
         gate = {"workload": "300x200x8 [0/45/-45/90]s plate, 15 J, to %.2f ms" % (n * g["dt"] * 1e3),
@@ -313,7 +313,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="config3", choices=["config2", "config3"])
+    ap.add_argument("--workload", default="plate1200x800x16", choices=["plate300x200x8", "plate1200x800x16"])
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--tile", default="15x15")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -347,7 +347,8 @@ def main():
     dev = int(os.environ.get("LOCAL_RANK", "0"))
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
-    cfg = W.config3(args.precision) if args.config == "config3" else W.config2(args.precision)
+    big = args.workload == "plate1200x800x16"
+    cfg = W.plate_qi8_1200x800x16(args.precision) if big else W.plate_qi8_300x200x8(args.precision)
     tx, ty = (int(v) for v in args.tile.split("x"))
     log(f"building {cfg['name']} on cuda:{dev}")
     sim = pdn.Simulation(cfg, device=dev, stream=stream.cuda_stream, tile=(tx, ty))
@@ -376,7 +377,7 @@ def main():
     log(f"timed {args.steps} steps in {elapsed:.3f} s; element/node {en_ms:.4f} ms, books {bk_ms:.4f} ms")
 
     gp = info["n_bulk"]
-    wkey = f"{args.config}/prec{args.precision}/tile{tx}x{ty}"
+    wkey = f"{args.workload}/prec{args.precision}/tile{tx}x{ty}"
     value = gp * args.steps / elapsed
     bytes_launch = algorithmic_bytes(info, args.precision)
     achieved = bytes_launch / (en_ms * 1e-3) / 1e9 if en_ms > 0 else 0.0
@@ -396,7 +397,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": ("[0/45/-45/90]s CFRP plate 1200x800x16 hex8 (2 el/ply) + 6 cohesive "
                                 "interfaces, 150x100 mm, ASTM window supports, R=8 mm 5.5 kg striker at 25 J"
-                                if args.config == "config3" else
+                                if big else
                                 "[0/45/-45/90]s CFRP plate 300x200x8 hex8, 150x100 mm, 15 J"),
                    "bulk_gauss_points": gp, "nodes": info["n_nodes"], "interface_pairs": info["n_pairs"],
                    "dt_s": info["dt"], "preroll_steps": pre, "tile": f"{tx}x{ty}", "precision": "mixed" if args.precision else "fp64",

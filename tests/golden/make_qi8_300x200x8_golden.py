@@ -1,4 +1,4 @@
-"""Write config2_fp64_oracle.json: the FP64 oracle's run of the 8-ply
+"""Write qi8_300x200x8_fp64_oracle.json: the FP64 oracle's run of the 8-ply
 [0/45/-45/90]s plate (300 x 200 x 8 hex8, intralaminar damage, ASTM window
 supports, 5.5 kg striker at 15 J) to 3 ms.
 
@@ -10,7 +10,7 @@ projected damage areas within 2 % of this FP64 run.
 Only the oracle and the input generators are called.  Usage (about two hours
 on 5 cores):
 
-    python tests/golden/make_config2_golden.py [--threads 5] [--t-end 3e-3]
+    python tests/golden/make_qi8_300x200x8_golden.py [--threads 5] [--t-end 3e-3]
 """
 import argparse
 import json
@@ -49,10 +49,10 @@ def main():
     ap.add_argument("--threads", type=int, default=5)
     ap.add_argument("--t-end", type=float, default=3e-3)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                                  "config2_fp64_oracle.json"))
+                                                  "qi8_300x200x8_fp64_oracle.json"))
     args = ap.parse_args()
     oracle.build(force=False)
-    cfg = W.config2(W.PREC_FP64)
+    cfg = W.plate_qi8_300x200x8(W.PREC_FP64)
     o = oracle.Oracle(cfg, threads=args.threads)
     steps = int(math.ceil(args.t_end / o.dt))
     t0 = time.time()
@@ -66,7 +66,7 @@ def main():
     t, f, x = o.history()
     i = int(np.argmax(f))
     res = {
-        "source": "FP64 oracle (oracle/pdn_oracle.c) on workloads.config2, written by make_config2_golden.py",
+        "source": "FP64 oracle (oracle/pdn_oracle.c) on workloads.plate_qi8_300x200x8, written by make_qi8_300x200x8_golden.py",
         "basis": "laminate, supports and striker of the drop-weight coupon (Sec. 4), Table 1 material; "
                  "contact force and projected damage are the outputs of Tabs. 2 and 4 and Fig. 9",
         "dt": o.dt, "steps": steps, "t_end": float(t[-1]),

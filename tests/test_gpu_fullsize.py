@@ -53,7 +53,7 @@ def _samples(nx, ny, rs, n_random=12):
 @pytest.mark.parametrize("prec", [W.PREC_FP64, W.PREC_MIXED])
 def test_full_size_one_step_sampled_columns(prec):
     _note(f"full size 1200x800x16+6 one step prec={prec}")
-    cfg = W.config3(prec)
+    cfg = W.plate_qi8_1200x800x16(prec)
     m = cfg["mesh"]
     nx, ny = m["nx"], m["ny"]
     g = pdn.Simulation(cfg, tile=(15, 15))

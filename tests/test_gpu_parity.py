@@ -61,13 +61,13 @@ def test_contact_elastic_fp64():
     assert o.history()[1].max() > 0
 
 
-def test_config1_fp64():
-    """Config 1 as stated: 20x20x4 isotropic plate, 2000 steps, history and energies."""
-    _note("config1 fp64 2000 steps")
-    cfg = W.config1()
+def test_isotropic_plate_20x20x4_fp64():
+    """The 20x20x4 isotropic plate (50 x 50 x 2 mm, clamped edges, 0.5 kg at 2 m/s), 2000 steps, history and energies."""
+    _note("isotropic plate 20x20x4 fp64 2000 steps")
+    cfg = W.plate_iso_20x20x4()
     o, g = run_both(cfg, 2000, chunks=3)
     d = compare(o, g, cfg)
-    _check64(d, "config1")
+    _check64(d, "isotropic plate")
     e = g.energies()
     assert abs(e["residual"]) <= 1e-6 * e["ke0"]
 

@@ -4,7 +4,7 @@ The 8-ply [0/45/-45/90]s plate (150 x 100 mm, 300 x 200 x 8 hex8,
 intralaminar damage, window supports of the drop-weight coupon, 5.5 kg
 striker of radius 8 mm at 15 J; Sec. 3.2, Table 1) is run to 3 ms on the GPU
 and compared with the FP64 oracle's run of the same case, stored in
-tests/golden/config2_fp64_oracle.json by tests/golden/make_config2_golden.py
+tests/golden/qi8_300x200x8_fp64_oracle.json by tests/golden/make_qi8_300x200x8_golden.py
 (which calls only the oracle and the input generators).
 
 The run is deterministic only up to the first releases of contact nodes
@@ -39,7 +39,7 @@ import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_fp64_oracle.json")
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "qi8_300x200x8_fp64_oracle.json")
 THRESHOLDS = ("0", "0.5", "0.999")
 EARLY = 5800                    # steps of the deterministic window
 
@@ -56,7 +56,7 @@ def gold():
 
 
 def _run(prec, g, energy_scale=1.0):
-    cfg = W.config2(prec)
+    cfg = W.plate_qi8_300x200x8(prec)
     cfg["impactor"]["energy"] *= energy_scale
     sim = pdn.Simulation(cfg)
     try:
@@ -90,7 +90,7 @@ def _oracle(g):
 
 @pytest.fixture(scope="module")
 def runs(gold):
-    _note("config2 to 3 ms: fp64, mixed, three fp64 runs with the energy perturbed by 1e-12")
+    _note("300x200x8 plate to 3 ms: fp64, mixed, three fp64 runs with the energy perturbed by 1e-12")
     out = {"oracle": _oracle(gold), "fp64": _run(W.PREC_FP64, gold), "mixed": _run(W.PREC_MIXED, gold)}
     out["ensemble"] = [_run(W.PREC_FP64, gold, 1.0 + 1e-12 * k) for k in (1, 2, 3)]
     return out

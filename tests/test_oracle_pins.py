@@ -94,9 +94,9 @@ def test_table3_stable_increment_sanity(level):
     assert 0.85 < lv["stable_dt_s"] / dt < 1.15
 
 
-def test_config_counts():
-    assert oracle.mesh_counts(W.config1()["mesh"])["n_nodes"] == 21 * 21 * 5
-    c3 = oracle.mesh_counts(W.config3()["mesh"])
+def test_workload_counts():
+    assert oracle.mesh_counts(W.plate_iso_20x20x4()["mesh"])["n_nodes"] == 21 * 21 * 5
+    c3 = oracle.mesh_counts(W.plate_qi8_1200x800x16()["mesh"])
     assert c3["n_planes"] == 23 and c3["n_bulk"] == 15360000 and c3["n_cohesive"] == 5760000
     assert c3["n_nodes"] == 22126023
 
@@ -557,8 +557,8 @@ def test_czm_t800_equal_penalties_table1():
 # integration: energy, contact conditions, momentum, release
 # ---------------------------------------------------------------------------
 
-def test_config1_energy_identity():
-    o = oracle.Oracle(W.config1())
+def test_isotropic_plate_energy_identity():
+    o = oracle.Oracle(W.plate_iso_20x20x4())
     o.step(2000)
     e = o.energies()
     assert e["level"] == 1999

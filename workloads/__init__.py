@@ -141,7 +141,7 @@ def impactor(R, mass, *, v0=0.0, energy=0.0, gap=1.0e-5, x0=None, y0=None):
 LAYUP_QI8 = [0, 45, -45, 90, 90, -45, 45, 0]      # [0/45/-45/90]s
 
 
-def config1() -> dict:
+def plate_iso_20x20x4() -> dict:
     """Isotropic plate 20x20x4, 50x50x2 mm, clamped edges, 0.5 kg at 2 m/s."""
     return dict(
         name="plain-fp64-isotropic-20x20x4",
@@ -151,7 +151,7 @@ def config1() -> dict:
         steps=2000)
 
 
-def config2(precision=PREC_MIXED) -> dict:
+def plate_qi8_300x200x8(precision=PREC_MIXED) -> dict:
     """[0/45/-45/90]s, 150x100 mm, 300x200x8, CDM, 5.5 kg at 15 J."""
     t = 0.5e-3
     return dict(
@@ -164,7 +164,7 @@ def config2(precision=PREC_MIXED) -> dict:
         steps=61000)
 
 
-def config3(precision=PREC_MIXED) -> dict:
+def plate_qi8_1200x800x16(precision=PREC_MIXED) -> dict:
     """Same laminate at 1200x800x16 (2 elements/ply) with cohesive interfaces, 25 J."""
     t = 0.5e-3
     return dict(
@@ -177,8 +177,8 @@ def config3(precision=PREC_MIXED) -> dict:
         steps=20000)
 
 
-def config5(precision=PREC_MIXED) -> dict:
-    c = config3(precision)
+def plate_qi8_1200x800x16_surrogate(precision=PREC_MIXED) -> dict:
+    c = plate_qi8_1200x800x16(precision)
     c["name"] = "surrogate-qi8-1200x800x16"
     for m in c["materials"]:
         m["law"] = LAW_CDM_SURROGATE
@@ -230,7 +230,7 @@ def coupon_as4(level: int = 0, precision=PREC_MIXED, phi: float = 1.033) -> dict
         t_end=5.0e-3)
 
 
-def config4_cases(n_cases=64, base_seed=0x9D5EED00) -> list:
+def batch_cases_64(n_cases=64, base_seed=0x9D5EED00) -> list:
     """Uneven batch: per case s, SplitMix64(base_seed + s) draws, in this order,
     plies P ~ U{4..16}, P angles from {0, 45, -45, 90}, target elements
     N_e ~ U[20k, 400k], impact energy ~ U[5, 40] J and mass ~ U[1, 6] kg."""
