@@ -45,7 +45,8 @@ class MeshDesc(C.Structure):
                 ("cohesive", C.c_int32), ("bc", C.c_int32), ("window_lx", C.c_double),
                 ("window_ly", C.c_double), ("clamp_radius", C.c_double), ("phi", C.c_double),
                 ("cfl_safety", C.c_double), ("gravity", C.c_double),
-                ("hourglass_kappa", C.c_double), ("node_coords", C.POINTER(C.c_double))]
+                ("hourglass_kappa", C.c_double), ("node_coords", C.POINTER(C.c_double)),
+                ("integration", C.c_int32)]
 
 
 _MAT_FIELDS = ["E1", "E2", "E3", "nu12", "nu13", "nu23", "G12", "G13", "G23", "rho", "law",
@@ -102,6 +103,8 @@ def lib():
         L.orc_hex8_geometry.argtypes = [dp, dp, dp, dp]
         L.orc_hex8_force_elastic.restype = C.c_double
         L.orc_hex8_force_elastic.argtypes = [dp, dp, P(Material), C.c_double, C.c_double, dp]
+        L.orc_hex8_force_elastic_full.restype = C.c_double
+        L.orc_hex8_force_elastic_full.argtypes = [dp, dp, P(Material), C.c_double, dp]
         L.orc_hex8_mass.argtypes = [dp, C.c_double, dp]
         L.orc_cdm.argtypes = [P(Material), C.c_double, dp, dp, dp, dp]
         L.orc_czm.restype = C.c_double
@@ -130,7 +133,8 @@ def mesh_desc(mesh: dict, node_coords: np.ndarray | None = None):
                  window_ly=mesh["window_ly"], clamp_radius=mesh["clamp_radius"],
                  phi=mesh["phi"], cfl_safety=mesh["cfl_safety"], gravity=mesh["gravity"],
                  hourglass_kappa=mesh["hourglass_kappa"],
-                 node_coords=(_dp(node_coords) if node_coords is not None else None))
+                 node_coords=(_dp(node_coords) if node_coords is not None else None),
+                 integration=int(mesh.get("integration", 1)))
     return d, (ang, node_coords)
 
 
@@ -193,7 +197,8 @@ class Oracle:
         return lib().orc_dt(self.h)
 
     def get(self, kind: int) -> np.ndarray:
-        size = {DISP: 3 * self.nn, VEL: 3 * self.nn, FINT: 3 * self.nn, GP_R: 4 * self.ne,
+        ngp = 8 if self.cfg["mesh"].get("integration", 1) == 8 else 1
+        size = {DISP: 3 * self.nn, VEL: 3 * self.nn, FINT: 3 * self.nn, GP_R: 4 * ngp * self.ne,
                 COH_R_IP: 4 * self.nc, COH_R_BY_BOTTOM_NODE: self.nn, MASS: self.nn,
                 COORDS: 3 * self.nn, ACTIVE: self.nn, FCONTACT: 3 * self.nn}[kind]
         out = np.zeros(max(size, 1))
@@ -239,6 +244,16 @@ def hex8_geometry(X: np.ndarray):
     b, V, g = np.zeros(24), np.zeros(1), np.zeros(32)
     lib().orc_hex8_geometry(_dp(X), _dp(b), _dp(V), _dp(g))
     return b.reshape(8, 3), V[0], g.reshape(4, 8)
+
+
+def hex8_force_elastic_full(X, u, mat: dict, angle_deg=0.0):
+    """Element force and strain energy with full 2x2x2 Gauss integration."""
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(24)
+    u = np.ascontiguousarray(u, dtype=np.float64).reshape(24)
+    f = np.zeros(24)
+    m = material(mat)
+    W = lib().orc_hex8_force_elastic_full(_dp(X), _dp(u), C.byref(m), angle_deg, _dp(f))
+    return f.reshape(8, 3), W
 
 
 def hex8_force_elastic(X, u, mat: dict, angle_deg=0.0, kappa=0.05):

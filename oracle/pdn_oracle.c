@@ -30,6 +30,7 @@ struct orc_sim {
     char err[256];
     /* mesh */
     int nx, ny, P, epp, K, NL, cohesive, bc;
+    int ngp;                       /* Gauss points of a bulk element: 1 or 8 */
     int64_t nn, ne, nc, ntop;
     int layer_is_coh[4 * MAXPLY + 8];
     int layer_ply[4 * MAXPLY + 8];
@@ -60,7 +61,7 @@ struct orc_sim {
     double *fint_prev;             /* f_int at level n-1 */
     double *fc, *fc_prev;          /* contact force found in the last step / the one before */
     double *v_prev;                /* v at level n-1 */
-    double *r;                     /* 4 ne */
+    double *r;                     /* 4 per Gauss point: 4 ne ngp */
     double *rd;                    /* 4 nc */
     unsigned char *active;         /* nn */
     double *ework;                 /* per-element scratch: 24 forces */
@@ -390,21 +391,17 @@ double orc_czm(const orc_material *m, const double dl[3], double *rd, double tau
 
 /* f = V sum_J (F S)_{iJ} b_{aJ} + hourglass; updates r (if law) ;
  * returns the element's secant energy 0.5 V sigma.eps + 0.5 k q.q */
-static double hex8_force(const double *b, double V, const double *gam, const double *u,
-                         const orc_material *m, double angle_deg, double kappa, double lc,
-                         double *r, double f[24])
+/* Response at one point of displacement gradient H (= F - I): Green strain,
+ * material frame, law (thresholds r, updated), back to the global frame and
+ * the nominal stress Pn = F S.  Returns the secant energy density S:E/2. */
+static double point_response(const double H[3][3], const orc_material *m, double angle_deg, double lc,
+                             double *r, double Pn[3][3])
 {
-    /* F = I + H with H = sum_a u_a (x) b_a; the Green strain E = (F^T F - I)/2
-     * is evaluated as (H + H^T + H^T H)/2, the same tensor without the
-     * cancellation of 1 + small - 1 at small strain */
-    double H[3][3], F[3][3];
+    /* the Green strain E = (F^T F - I)/2 is evaluated as (H + H^T + H^T H)/2,
+     * the same tensor without the cancellation of 1 + small - 1 */
+    double F[3][3];
     for (int i = 0; i < 3; ++i)
-        for (int J = 0; J < 3; ++J) {
-            double s = 0.0;
-            for (int a = 0; a < 8; ++a) s += u[3 * a + i] * b[3 * a + J];
-            H[i][J] = s;
-            F[i][J] = s + ((i == J) ? 1.0 : 0.0);
-        }
+        for (int J = 0; J < 3; ++J) F[i][J] = H[i][J] + ((i == J) ? 1.0 : 0.0);
     double E[3][3];
     for (int I = 0; I < 3; ++I)
         for (int J = 0; J < 3; ++J) {
@@ -446,13 +443,30 @@ static double hex8_force(const double *b, double V, const double *gam, const dou
             for (int k = 0; k < 3; ++k) t += T[i][k] * Q[k][j];
             S[i][j] = t;
         }
-    double Pn[3][3];
     for (int i = 0; i < 3; ++i)
         for (int J = 0; J < 3; ++J) {
             double t = 0;
             for (int K = 0; K < 3; ++K) t += F[i][K] * S[K][J];
             Pn[i][J] = t;
         }
+    double w = 0;
+    for (int k = 0; k < 6; ++k) w += sg[k] * eps[k];
+    return 0.5 * w;
+}
+
+static double hex8_force(const double *b, double V, const double *gam, const double *u,
+                         const orc_material *m, double angle_deg, double kappa, double lc,
+                         double *r, double f[24])
+{
+    /* one point: H = sum_a u_a (x) b_a with the mean gradients b */
+    double H[3][3], Pn[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int J = 0; J < 3; ++J) {
+            double s = 0.0;
+            for (int a = 0; a < 8; ++a) s += u[3 * a + i] * b[3 * a + J];
+            H[i][J] = s;
+        }
+    double wd = point_response(H, m, angle_deg, lc, r, Pn);
     for (int a = 0; a < 8; ++a)
         for (int i = 0; i < 3; ++i) {
             double t = 0;
@@ -478,9 +492,51 @@ static double hex8_force(const double *b, double V, const double *gam, const dou
             for (int al = 0; al < 4; ++al) t += gam[8 * al + a] * q[al][i];
             f[3 * a + i] += khg * t;
         }
-    double w = 0;
-    for (int k = 0; k < 6; ++k) w += sg[k] * eps[k];
-    return 0.5 * V * w + ehg;
+    return V * wd + ehg;
+}
+
+/* Full integration (the paper's element, Section 2): 2x2x2 Gauss points of
+ * weight 1; at each, the Jacobian of the reference map, dN_a/dX by cofactors,
+ * H = sum_a u_a (x) dN_a/dX, the law with the point's own thresholds
+ * r[4 g .. 4 g + 3], and f_a += det J Pn dN_a/dX.  No hourglass control. */
+static double hex8_force_full(const double X[24], const double *u, const orc_material *m, double angle_deg,
+                              double lc, double *r, double f[24])
+{
+    const double gp = 1.0 / sqrt(3.0);
+    double energy = 0;
+    for (int i = 0; i < 24; ++i) f[i] = 0;
+    for (int g = 0; g < 8; ++g) {
+        double xi = (g & 1) ? gp : -gp, eta = (g & 2) ? gp : -gp, zeta = (g & 4) ? gp : -gp;
+        double dN[8][3], J[3][3] = {{0}}, C[3][3];
+        dN_nat(xi, eta, zeta, dN);
+        for (int a = 0; a < 8; ++a)
+            for (int I = 0; I < 3; ++I)
+                for (int k = 0; k < 3; ++k) J[I][k] += X[3 * a + I] * dN[a][k];
+        cofactor3(J, C);
+        double dJ = det3(J);
+        double B[8][3];
+        for (int a = 0; a < 8; ++a)
+            for (int I = 0; I < 3; ++I) {
+                double t = 0;
+                for (int k = 0; k < 3; ++k) t += C[I][k] * dN[a][k];
+                B[a][I] = t / dJ;
+            }
+        double H[3][3], Pn[3][3];
+        for (int i = 0; i < 3; ++i)
+            for (int I = 0; I < 3; ++I) {
+                double t = 0;
+                for (int a = 0; a < 8; ++a) t += u[3 * a + i] * B[a][I];
+                H[i][I] = t;
+            }
+        energy += dJ * point_response(H, m, angle_deg, lc, r ? r + 4 * g : NULL, Pn);
+        for (int a = 0; a < 8; ++a)
+            for (int i = 0; i < 3; ++i) {
+                double t = 0;
+                for (int I = 0; I < 3; ++I) t += Pn[i][I] * B[a][I];
+                f[3 * a + i] += dJ * t;
+            }
+    }
+    return energy;
 }
 
 double orc_hex8_force_elastic(const double X[24], const double u[24], const orc_material *m,
@@ -491,6 +547,16 @@ double orc_hex8_force_elastic(const double X[24], const double u[24], const orc_
     orc_material me = *m;
     me.law = 0;
     return hex8_force(b, V, gam, u, &me, angle_deg, kappa, cbrt(V), NULL, f);
+}
+
+double orc_hex8_force_elastic_full(const double X[24], const double u[24], const orc_material *m,
+                                   double angle_deg, double f[24])
+{
+    double b[24], V;
+    orc_hex8_geometry(X, b, &V, NULL);
+    orc_material me = *m;
+    me.law = 0;
+    return hex8_force_full(X, u, &me, angle_deg, cbrt(V), NULL, f);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -565,6 +631,8 @@ orc_sim *orc_create(const orc_mesh_desc *d)
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
     int64_t cnt[7];
     if (orc_mesh_counts(d, cnt) != 0) { free(s); return NULL; }
+    if (d->integration != 0 && d->integration != 1 && d->integration != 8) { free(s); return NULL; }
+    s->ngp = d->integration == 8 ? 8 : 1;
     s->nx = d->nx; s->ny = d->ny; s->P = d->n_plies; s->epp = d->elems_per_ply;
     build_layers(d, s->layer_is_coh, s->layer_ply, &s->NL);
     s->K = s->NL + 1;
@@ -679,12 +747,12 @@ orc_sim *orc_create(const orc_mesh_desc *d)
     s->fc = (double *)calloc(3 * nn, sizeof(double));
     s->fc_prev = (double *)calloc(3 * nn, sizeof(double));
     s->v_prev = (double *)calloc(3 * nn, sizeof(double));
-    s->r = (double *)calloc(4 * (ne ? ne : 1), sizeof(double));
+    s->r = (double *)calloc(4 * s->ngp * (ne ? ne : 1), sizeof(double));
     s->rd = (double *)calloc(4 * (nc ? nc : 1), sizeof(double));
     s->active = (unsigned char *)calloc(nn, 1);
     s->ework = (double *)calloc(24 * (ne ? ne : 1), sizeof(double));
     s->cwork = (double *)calloc(24 * (nc ? nc : 1), sizeof(double));
-    for (int64_t i = 0; i < 4 * ne; ++i) s->r[i] = 1.0;
+    for (int64_t i = 0; i < 4 * s->ngp * ne; ++i) s->r[i] = 1.0;
     s->needs_init = 1;
     return s;
 }
@@ -842,8 +910,16 @@ static void internal_force(orc_sim *s)
         for (int a = 0; a < 8; ++a)
             for (int i = 0; i < 3; ++i) ue[3 * a + i] = s->d[3 * s->conn[8 * e + a] + i];
         int p = s->eply[e];
-        uel += hex8_force(&s->eb[24 * e], s->evol[e], &s->egam[32 * e], ue, &s->mat[p], s->ang[p],
-                          s->kappa, s->elc_band[e], &s->r[4 * e], &s->ework[24 * e]);
+        if (s->ngp == 8) {
+            double Xe[24];
+            for (int a = 0; a < 8; ++a)
+                for (int i = 0; i < 3; ++i) Xe[3 * a + i] = s->X[3 * s->conn[8 * e + a] + i];
+            uel += hex8_force_full(Xe, ue, &s->mat[p], s->ang[p], s->elc_band[e], &s->r[32 * e],
+                                   &s->ework[24 * e]);
+        } else {
+            uel += hex8_force(&s->eb[24 * e], s->evol[e], &s->egam[32 * e], ue, &s->mat[p], s->ang[p],
+                              s->kappa, s->elc_band[e], &s->r[4 * e], &s->ework[24 * e]);
+        }
     }
 #ifdef _OPENMP
 #pragma omp parallel for schedule(static) num_threads(s->nthreads) reduction(+ : uel)
@@ -1077,7 +1153,7 @@ int orc_get(const orc_sim *s, int32_t kind, double *out, int64_t cap)
     case ORC_VEL: n = 3 * s->nn; if (cap < n) return -1; memcpy(out, s->v, n * 8); return 0;
     case ORC_FINT: n = 3 * s->nn; if (cap < n) return -1; memcpy(out, s->fint, n * 8); return 0;
     case ORC_FCONTACT: n = 3 * s->nn; if (cap < n) return -1; memcpy(out, s->fc, n * 8); return 0;
-    case ORC_GP_R: n = 4 * s->ne; if (cap < n) return -1; memcpy(out, s->r, n * 8); return 0;
+    case ORC_GP_R: n = 4 * s->ngp * s->ne; if (cap < n) return -1; memcpy(out, s->r, n * 8); return 0;
     case ORC_COH_R_IP: n = 4 * s->nc; if (cap < n) return -1; memcpy(out, s->rd, n * 8); return 0;
     case ORC_MASS: n = s->nn; if (cap < n) return -1; memcpy(out, s->mass, n * 8); return 0;
     case ORC_COORDS: n = 3 * s->nn; if (cap < n) return -1; memcpy(out, s->X, n * 8); return 0;
@@ -1100,7 +1176,7 @@ int orc_set(orc_sim *s, int32_t kind, const double *in, int64_t n)
     switch (kind) {
     case ORC_DISP: if (n != 3 * s->nn) return -1; memcpy(s->d, in, n * 8); break;
     case ORC_VEL: if (n != 3 * s->nn) return -1; memcpy(s->v, in, n * 8); break;
-    case ORC_GP_R: if (n != 4 * s->ne) return -1; memcpy(s->r, in, n * 8); break;
+    case ORC_GP_R: if (n != 4 * s->ngp * s->ne) return -1; memcpy(s->r, in, n * 8); break;
     case ORC_COH_R_IP: if (n != 4 * s->nc) return -1; memcpy(s->rd, in, n * 8); break;
     case ORC_COH_R_BY_BOTTOM_NODE:
         if (n != s->nn) return -1;
@@ -1195,20 +1271,22 @@ int64_t orc_damage_field(const orc_sim *s, int32_t kind, double *out, int64_t ca
     for (int64_t e = 0; e < s->ne; ++e) {
         const orc_material *m = &s->mat[s->eply[e]];
         double val = 0;
-        if (m->law != 0) {
-            double lc = s->elc_band[e];
-            const double *r = &s->r[4 * e];
+        /* largest over the element's Gauss points */
+        for (int g = 0; g < s->ngp && m->law != 0; ++g) {
+            double lc = s->elc_band[e], vg;
+            const double *r = &s->r[4 * (s->ngp * e + g)];
             if (base == ORC_DMG_FIBRE) {
                 double a = dmg_bilinear(r[0], m->XT, m->E1, m->GXT, m->fXT, m->fGT, lc);
                 double b = dmg_bilinear(r[1], m->XC, m->E1, m->GXC, m->fXC, m->fGC, lc);
-                val = a > b ? a : b;
+                vg = a > b ? a : b;
             } else if (base == ORC_DMG_MATRIX) {
                 double a = dmg_expo(r[2], capped_strength(m->YT, m->E2, m->GYT, lc), m->E2, m->GYT, lc);
                 double b = dmg_expo(r[3], capped_strength(m->YC, m->E2, m->GYC, lc), m->E2, m->GYC, lc);
-                val = a > b ? a : b;
+                vg = a > b ? a : b;
             } else {
-                val = dmg_expo(r[2], capped_strength(m->SL, m->G12, m->GSL, lc), m->G12, m->GSL, lc);
+                vg = dmg_expo(r[2], capped_strength(m->SL, m->G12, m->GSL, lc), m->G12, m->GSL, lc);
             }
+            if (vg > val) val = vg;
         }
         if (proj) { int64_t c = e % ncol; if (val > out[c]) out[c] = val; }
         else out[e] = val;

@@ -40,6 +40,8 @@ typedef struct {
     double window_lx, window_ly, clamp_radius;
     double phi, cfl_safety, gravity, hourglass_kappa;
     const double *node_coords;        /* optional 3*n_nodes reference coordinates */
+    int32_t integration;              /* bulk element: 1 (or 0) one point + hourglass control,
+                                         8 full 2x2x2 Gauss with its own state per point */
 } orc_mesh_desc;
 
 typedef struct {
@@ -96,6 +98,9 @@ void orc_hex8_geometry(const double X[24], double b[24], double *vol, double gam
 /* element internal force (elastic law) at displacement u; returns strain energy */
 double orc_hex8_force_elastic(const double X[24], const double u[24], const orc_material *m,
                               double angle_deg, double kappa, double f[24]);
+/* the same with full 2x2x2 Gauss integration (no hourglass control) */
+double orc_hex8_force_elastic_full(const double X[24], const double u[24], const orc_material *m,
+                                   double angle_deg, double f[24]);
 /* lumped mass of one hex8: m[8] */
 void orc_hex8_mass(const double X[24], double rho, double m[8]);
 /* intralaminar law: eps Voigt (eng. shear), r[4] in/out, lc crack band; sigma out, dmg[5] */

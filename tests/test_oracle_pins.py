@@ -128,10 +128,13 @@ def _homog_cfg(angle=30.0, n=3):
     return cfg
 
 
-def test_patch_test_distorted_large_deformation():
+@pytest.mark.parametrize("integration", [1, 8])
+def test_patch_test_distorted_large_deformation(integration):
     """A linear displacement field on a distorted mesh leaves interior nodes in
-    equilibrium (uniform F, E and S; hourglass forces vanish)."""
+    equilibrium (uniform F, E and S; hourglass forces vanish), with one-point
+    and with full integration."""
     cfg = _homog_cfg()
+    cfg["mesh"]["integration"] = integration
     Xd = _distorted(cfg, 0.2, 1)
     o = oracle.Oracle(cfg, node_coords=Xd.reshape(-1))
     A = np.array([[0.04, 0.01, -0.02], [0.015, -0.03, 0.01], [0.02, 0.005, 0.05]])
@@ -190,6 +193,83 @@ def test_hourglass_energy_gradient_pure_mode():
     f1, W1 = oracle.hex8_force_elastic(X, u, mat, 0.0, 0.05)
     assert np.abs(f0).max() < 1e-6 * np.abs(f1).max()   # 1-point element: zero energy mode
     assert W1 > 0 and np.abs(f1).max() > 0
+
+
+# ---------------------------------------------------------------------------
+# full 2x2x2 Gauss integration (the paper's element)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("angle", [0.0, 30.0])
+def test_full_integration_force_is_energy_gradient(angle):
+    """f = dW/du with W the sum over the eight Gauss points of det J times the
+    SVK energy density (central differences, large strain)."""
+    X = _one_hex(7)
+    mat = _elastic(W.material_cfrp(False, 1e-3))
+    g = np.random.default_rng(9)
+    u = g.uniform(-1, 1, (8, 3)) * 1e-4
+    f, _ = oracle.hex8_force_elastic_full(X, u, mat, angle)
+    fd = np.zeros(24)
+    du = 1e-9
+    uf = u.reshape(-1)
+    for k in range(24):
+        up, um = uf.copy(), uf.copy()
+        up[k] += du
+        um[k] -= du
+        fd[k] = (oracle.hex8_force_elastic_full(X, up, mat, angle)[1]
+                 - oracle.hex8_force_elastic_full(X, um, mat, angle)[1]) / (2 * du)
+    assert np.abs(fd - f.reshape(-1)).max() <= 1e-6 * np.abs(f).max()
+
+
+def test_full_integration_matches_one_point_on_homogeneous_deformation():
+    """A linear displacement field has the same gradient at every Gauss point,
+    so both element forms give the same force (the hourglass part vanishes),
+    also on a distorted element."""
+    X = _one_hex(11)
+    mat = _elastic(W.material_cfrp(False, 1e-3))
+    A = np.array([[0.03, 0.01, -0.02], [0.015, -0.02, 0.01], [0.02, 0.005, 0.04]])
+    u = X @ A.T + np.array([1e-5, 0.0, -2e-5])
+    f1, w1 = oracle.hex8_force_elastic(X, u, mat, 30.0, 0.05)
+    f8, w8 = oracle.hex8_force_elastic_full(X, u, mat, 30.0)
+    assert np.abs(f8 - f1).max() <= 1e-10 * np.abs(f1).max()
+    assert abs(w8 - w1) <= 1e-10 * abs(w1)
+
+
+def _stiffness(force, X, mat, h=1e-9):
+    u0 = np.zeros(24)
+    K = np.zeros((24, 24))
+    for k in range(24):
+        up, um = u0.copy(), u0.copy()
+        up[k] += h
+        um[k] -= h
+        K[:, k] = (force(X, up, mat).reshape(-1) - force(X, um, mat).reshape(-1)) / (2 * h)
+    return 0.5 * (K + K.T)
+
+
+def test_full_integration_has_only_rigid_zero_modes():
+    """Small-strain stiffness of one element: full integration has exactly the
+    six rigid-body zero-energy modes; one point without hourglass control has
+    twelve more (the hourglass modes)."""
+    X = _one_hex(13, amp=0.1)
+    mat = _elastic(W.material_isotropic(70e9, 0.3, 2700.0))
+    K8 = _stiffness(lambda X, u, m: oracle.hex8_force_elastic_full(X, u, m, 0.0)[0], X, mat)
+    K1 = _stiffness(lambda X, u, m: oracle.hex8_force_elastic(X, u, m, 0.0, 0.0)[0], X, mat)
+    for K, zeros in ((K8, 6), (K1, 18)):
+        ev = np.sort(np.abs(np.linalg.eigvalsh(K)))
+        assert (ev[:zeros] <= 1e-6 * ev[-1]).all()
+        assert ev[zeros] > 1e-4 * ev[-1]
+
+
+def test_full_integration_plate_energy_identity():
+    """The energy identity holds with full integration over an impact with
+    contact (isotropic plate, clamped edges)."""
+    cfg = W.plate_iso_20x20x4()
+    cfg["mesh"]["integration"] = 8
+    o = oracle.Oracle(cfg)
+    o.step(600)
+    e = o.energies()
+    assert o.history()[1].max() > 0
+    assert abs(e["residual"]) <= 1e-6 * e["ke0"]
+    assert o.get(oracle.GP_R).size == 4 * 8 * o.ne
 
 
 def test_rigid_rotation_gives_zero_force():

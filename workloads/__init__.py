@@ -121,14 +121,14 @@ def ply_materials(n_plies: int, ply_thickness: float, law: int = LAW_CDM) -> lis
 def _mesh(nx, ny, n_plies, elems_per_ply, lx, ly, ply_thickness, angles, *,
           cohesive=0, bc=BC_CLAMPED_EDGES, window_lx=0.0, window_ly=0.0,
           clamp_radius=0.0, precision=PREC_FP64, phi=1.0, cfl_safety=0.9,
-          gravity=9.81, hourglass_kappa=0.05):
+          gravity=9.81, hourglass_kappa=0.05, integration=1):
     return dict(nx=nx, ny=ny, n_plies=n_plies, elems_per_ply=elems_per_ply,
                 lx=lx, ly=ly, ply_thickness=ply_thickness,
                 ply_angle_deg=[float(a) for a in angles], cohesive=cohesive,
                 bc=bc, window_lx=window_lx, window_ly=window_ly,
                 clamp_radius=clamp_radius, precision=precision, phi=phi,
                 cfl_safety=cfl_safety, gravity=gravity,
-                hourglass_kappa=hourglass_kappa)
+                hourglass_kappa=hourglass_kappa, integration=integration)
 
 
 def impactor(R, mass, *, v0=0.0, energy=0.0, gap=1.0e-5, x0=None, y0=None):
