@@ -82,6 +82,10 @@ typedef struct {
     const double *y_coords;        /* optional ny+1 graded grid lines (NULL = uniform) */
     int32_t device;                /* HIP device ordinal */
     void *stream;                  /* hipStream_t to run on; NULL = the context's own */
+    int32_t integration;           /* bulk element: 0 or 1 = one point with hourglass control;
+                                      8 = full 2x2x2 Gauss integration (Section 2), one damage
+                                      state per point, no hourglass control (tiles 15x15 and
+                                      16x16; no surrogate plies).  Other values: PDN_EINVAL */
 } pdn_mesh_desc;
 
 /* Ply material (Table 1 fields).  law = PDN_LAW_ELASTIC uses only the elastic

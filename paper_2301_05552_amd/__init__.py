@@ -43,7 +43,7 @@ class MeshDesc(C.Structure):
                 ("precision", C.c_int32), ("phi", C.c_double), ("cfl_safety", C.c_double),
                 ("gravity", C.c_double), ("hourglass_kappa", C.c_double),
                 ("x_coords", C.POINTER(C.c_double)), ("y_coords", C.POINTER(C.c_double)),
-                ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("integration", C.c_int32)]
 
 
 _MAT = ["E1", "E2", "E3", "nu12", "nu13", "nu23", "G12", "G13", "G23", "rho", "law",
@@ -217,7 +217,7 @@ class Simulation:
                      cfl_safety=m["cfl_safety"], gravity=m["gravity"], hourglass_kappa=m["hourglass_kappa"],
                      x_coords=None if self._xc is None else _dp(self._xc),
                      y_coords=None if self._yc is None else _dp(self._yc),
-                     device=device, stream=stream)
+                     device=device, stream=stream, integration=int(m.get("integration", 1)))
         h = C.c_void_p()
         rc = L.pdn_mesh_create(C.byref(d), C.byref(h))
         if rc != 0:

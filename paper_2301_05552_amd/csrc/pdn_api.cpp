@@ -81,6 +81,7 @@ struct pdn_ctx {
     uint4 *sur_d = nullptr;
     int n_nets = 0;
     bool use_sur = false;             // some ply evaluates a network (kernel variant)
+    int ngp = 1;                      // Gauss points of a bulk element: 1 (hourglass control) or 8
     std::vector<int> ply_net;
     double sur_dmg = 0.05, sur_res = 1e-3;
     // timing
@@ -384,9 +385,11 @@ int launch_en(pdn_ctx *c, int in, int out, int contact, hipEvent_t mid = nullptr
     hipError_t e;
     const bool mx = c->precision == PDN_MIXED;
     if (mx)
-        e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out, contact), c->tile, c->use_sur, c->stream);
+        e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out, contact), c->tile, c->use_sur, c->ngp,
+                                         c->stream);
     else
-        e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out, contact), c->tile, c->use_sur, c->stream);
+        e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out, contact), c->tile, c->use_sur, c->ngp,
+                                          c->stream);
     if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "element/node kernel launch: %s", hipGetErrorString(e));
     if (!contact) return PDN_OK;
     if (mid) HIPCHK(c, hipEventRecord(mid, c->stream));
@@ -507,9 +510,11 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
     if (D.nx < 1 || D.ny < 1 || D.n_plies < 1 || D.n_plies > PDN_MAX_PLIES || D.elems_per_ply < 1 ||
         !(D.lx > 0) || !(D.ly > 0) || !(D.ply_thickness > 0) || !D.ply_angle_deg ||
         (D.precision != PDN_FP64 && D.precision != PDN_MIXED) || D.bc < 0 || D.bc > 2 ||
-        !(D.cfl_safety > 0) || !(D.phi >= 1.0) || D.hourglass_kappa < 0)
+        !(D.cfl_safety > 0) || !(D.phi >= 1.0) || D.hourglass_kappa < 0 ||
+        (D.integration != 0 && D.integration != 1 && D.integration != 8))
         return PDN_EINVAL;
     pdn_ctx *c = new pdn_ctx();
+    c->ngp = D.integration == 8 ? 8 : 1;
     c->device = D.device;
     c->nx = D.nx; c->ny = D.ny; c->P = D.n_plies; c->epp = D.elems_per_ply;
     c->cohesive = D.cohesive; c->bc = D.bc; c->precision = D.precision;
@@ -585,7 +590,7 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
         const int *pref = c->precision == PDN_MIXED ? pref_mixed : pref_fp64;
         c->tile = -1;
         for (int k = 0; k < PDN_TILE_COUNT && c->tile < 0; ++k)
-            if (tile_fits(c, pref[k])) c->tile = pref[k];
+            if (tile_fits(c, pref[k]) && (c->ngp == 1 || pdn::tile_has_full(pref[k]))) c->tile = pref[k];
         if (c->tile < 0) {
             if (c->own_stream) (void)hipStreamDestroy(c->stream);
             delete c;
@@ -599,7 +604,7 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
         rc = dalloc(c, (void **)&c->d[b], 3 * c->nn * sizeof(double));
         if (!rc) rc = dalloc(c, (void **)&c->v[b], 3 * c->nn * sizeof(double));
     }
-    if (!rc) rc = dalloc(c, &c->r, 4 * c->ne * rs);
+    if (!rc) rc = dalloc(c, &c->r, 4 * c->ngp * c->ne * rs);
     if (!rc) rc = dalloc(c, &c->rd, c->npairs * rs);
     if (!rc) rc = dalloc(c, &c->hx, c->nx * rs);
     if (!rc) rc = dalloc(c, &c->hy, c->ny * rs);
@@ -656,11 +661,11 @@ int pdn_mesh_create(const pdn_mesh_desc *desc, pdn_ctx **out)
         (void)hipMemsetAsync(c->rd, 0, std::max<int64_t>(1, c->npairs) * rs, c->stream);
         if (c->ne > 0) {
             if (c->precision == PDN_MIXED) {
-                std::vector<float> ones(4 * c->ne, 1.0f);
+                std::vector<float> ones(4 * c->ngp * c->ne, 1.0f);
                 rc = upload(c, (float *)c->r, ones);
                 if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = PDN_EDEVICE;
             } else {
-                std::vector<double> ones(4 * c->ne, 1.0);
+                std::vector<double> ones(4 * c->ngp * c->ne, 1.0);
                 rc = upload(c, (double *)c->r, ones);
                 if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = PDN_EDEVICE;
             }
@@ -863,11 +868,11 @@ int pdn_damage_field(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, 
                                                (const PlyC<double> *)c->ply, c->nx, c->ny, nelem, c->dmg_d, c->stream);
     } else {
         if (c->precision == PDN_MIXED)
-            e = pdn::launch_damage_bulk<float>((const float *)c->r, c->layers_d, c->bulk_layer_d,
+            e = pdn::launch_damage_bulk<float>((const float *)c->r, c->ngp, c->layers_d, c->bulk_layer_d,
                                                (const PlyC<float> *)c->ply, (const float *)c->hx,
                                                (const float *)c->hy, c->nx, c->ny, nelem, base, c->dmg_d, c->stream);
         else
-            e = pdn::launch_damage_bulk<double>((const double *)c->r, c->layers_d, c->bulk_layer_d,
+            e = pdn::launch_damage_bulk<double>((const double *)c->r, c->ngp, c->layers_d, c->bulk_layer_d,
                                                 (const PlyC<double> *)c->ply, (const double *)c->hx,
                                                 (const double *)c->hy, c->nx, c->ny, nelem, base, c->dmg_d, c->stream);
     }
@@ -927,7 +932,7 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
     int64_t n;
     switch (kind) {
     case PDN_ARR_DISP: case PDN_ARR_VEL: n = 3 * c->nn; break;
-    case PDN_ARR_GP_R: n = 4 * c->ne; break;
+    case PDN_ARR_GP_R: n = 4 * c->ngp * c->ne; break;
     case PDN_ARR_COH_R: n = c->npairs; break;
     case PDN_ARR_MASS: n = c->nn; break;
     default: return set_err(c, PDN_EINVAL, "unknown array kind %d", kind);
@@ -972,7 +977,7 @@ int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
     int64_t need;
     switch (kind) {
     case PDN_ARR_DISP: case PDN_ARR_VEL: need = 3 * c->nn; break;
-    case PDN_ARR_GP_R: need = 4 * c->ne; break;
+    case PDN_ARR_GP_R: need = 4 * c->ngp * c->ne; break;
     case PDN_ARR_COH_R: need = c->npairs; break;
     default: return set_err(c, PDN_EINVAL, "array kind %d cannot be set", kind);
     }
@@ -1028,8 +1033,9 @@ struct BlobHeader {
     uint64_t magic;
     int64_t nn, ne, npairs, ncand, hist_n;
     int32_t precision, cur;
+    int32_t ngp, pad;
 };
-const uint64_t kMagic = 0x31304b4350444e50ull;   // "PNDPCK01"
+const uint64_t kMagic = 0x32304b4350444e50ull;   // "PNDPCK02"
 }  // namespace
 
 int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
@@ -1040,7 +1046,8 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     const size_t rs = rsize(c);
     const int64_t ncand = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
     const int64_t hn = c->gl.step;
-    const size_t need = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) + 4 * c->ne * rs +
+    const size_t need = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) +
+                        4 * c->ngp * c->ne * rs +
                         c->npairs * rs + ncand * (1 + 6 * sizeof(double)) + 3 * hn * sizeof(double);
     if (n_out) *n_out = (int64_t)need;
     if (cap < (int64_t)need || !buf) return set_err(c, PDN_ERANGE, "checkpoint needs %zu bytes", need);
@@ -1049,7 +1056,7 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     if (!rc) rc = materialize(c);
     if (rc) return rc;
     char *p = (char *)buf;
-    BlobHeader h{kMagic, c->nn, c->ne, c->npairs, ncand, hn, c->precision, 0};
+    BlobHeader h{kMagic, c->nn, c->ne, c->npairs, ncand, hn, c->precision, 0, c->ngp, 0};
     std::memcpy(p, &h, sizeof h); p += sizeof h;
     std::memcpy(p, &c->gl, sizeof(DevGlobals)); p += sizeof(DevGlobals);
     auto d2h = [&](const void *src, size_t bytes) -> int {
@@ -1060,7 +1067,7 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     };
     if ((rc = d2h(c->d[c->cur], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = d2h(c->v[c->cur], 3 * c->nn * sizeof(double)))) return rc;
-    if ((rc = d2h(c->r, 4 * c->ne * rs))) return rc;
+    if ((rc = d2h(c->r, 4 * c->ngp * c->ne * rs))) return rc;
     if ((rc = d2h(c->rd, c->npairs * rs))) return rc;
     if ((rc = d2h(c->active_d + (size_t)(1 - c->cur) * ncand, ncand))) return rc;   // read by the next step
     if ((rc = d2h(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
@@ -1080,7 +1087,7 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     std::memcpy(&h, p, sizeof h); p += sizeof h;
     const int64_t ncand = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
     if (h.magic != kMagic || h.nn != c->nn || h.ne != c->ne || h.npairs != c->npairs || h.ncand != ncand ||
-        h.precision != c->precision)
+        h.precision != c->precision || h.ngp != c->ngp)
         return set_err(c, PDN_EINVAL, "checkpoint does not match this context");
     (void)hipSetDevice(c->device);
     int rc;
@@ -1098,7 +1105,7 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     c->cur = 0;
     if ((rc = h2d(c->d[0], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = h2d(c->v[0], 3 * c->nn * sizeof(double)))) return rc;
-    if ((rc = h2d(c->r, 4 * c->ne * rs))) return rc;
+    if ((rc = h2d(c->r, 4 * c->ngp * c->ne * rs))) return rc;
     if ((rc = h2d(c->rd, c->npairs * rs))) return rc;
     if ((rc = h2d(c->active_d + ncand, ncand))) return rc;            // cur = 0: the next step reads set 1
     if ((rc = h2d(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
@@ -1120,6 +1127,8 @@ int pdn_set_tile(pdn_ctx *c, int32_t tx, int32_t ty)
     for (int k = 0; k < PDN_TILE_COUNT; ++k)
         if (pdn_tile_dims[k][0] == tx && pdn_tile_dims[k][1] == ty) t = k;
     if (t < 0) return set_err(c, PDN_EINVAL, "unsupported tile %dx%d", tx, ty);
+    if (c->ngp == 8 && !pdn::tile_has_full(t))
+        return set_err(c, PDN_EINVAL, "full integration is built for the 15x15 and 16x16 tiles");
     if (!tile_fits(c, t)) return set_err(c, PDN_EINVAL, "tile %dx%d does not fit the device's LDS", tx, ty);
     const int old = c->nblocks;
     c->tile = t;
@@ -1175,6 +1184,7 @@ struct pdn_batch {
     std::string err;
     std::vector<pdn_ctx *> cs;
     int device = 0, precision = 0, tile = -1;
+    int ngp = 1;                         // element integration shared by all cases
     hipStream_t stream = nullptr;        // stream of the first case; every step runs here
     hipStream_t cap = nullptr;           // private stream used only to capture the step graph
     // 3 x n element-pass arguments: steps of parity 0 and 1 (contact pass), and
@@ -1228,7 +1238,8 @@ std::map<std::string, int> &tune_cache()
 std::string shape_key(const pdn_ctx *c)
 {
     char k[96];
-    snprintf(k, sizeof k, "%d:%d:%d:%d:%d:%d;", c->device, c->precision, (int)c->use_sur, c->nx, c->ny, c->K);
+    snprintf(k, sizeof k, "%d:%d:%d:%d:%d:%d:%d;", c->device, c->precision, (int)c->use_sur, c->ngp, c->nx, c->ny,
+             c->K);
     return k;
 }
 
@@ -1304,9 +1315,9 @@ hipError_t launch_batch_elem(pdn_batch *b, int table, hipStream_t s)
     const bool contact = table < 2;
     if (b->precision == PDN_MIXED)
         return pdn::launch_elem_node_batch<float>(reinterpret_cast<ElemArgs<float> *>(b->eargs_d) + table * n,
-                                                  b->estart_d, n, b->eblocks, b->tile, b->sur, contact, s);
+                                                  b->estart_d, n, b->eblocks, b->tile, b->sur, b->ngp, contact, s);
     return pdn::launch_elem_node_batch<double>(reinterpret_cast<ElemArgs<double> *>(b->eargs_d) + table * n,
-                                               b->estart_d, n, b->eblocks, b->tile, b->sur, contact, s);
+                                               b->estart_d, n, b->eblocks, b->tile, b->sur, b->ngp, contact, s);
 }
 
 // one step of every case: a contact + element/node pass
@@ -1392,7 +1403,7 @@ int pdn_autotune(pdn_ctx *c, int32_t *tile_x, int32_t *tile_y)
     } else {
         float best_ms = 0;
         for (int t : kTileOrder) {
-            if (!tile_fits(c, t)) continue;
+            if (!tile_fits(c, t) || (c->ngp == 8 && !pdn::tile_has_full(t))) continue;
             float ms = 0;
             if ((rc = use_tile(c, t)) || (rc = time_single(c, 3, &ms))) return rc;
             if (best < 0 || ms < best_ms) { best = t; best_ms = ms; }
@@ -1418,13 +1429,14 @@ int pdn_batch_create(pdn_ctx *const *cases, int32_t n, pdn_batch **out)
             if (cases[j] == c) return set_err(c, PDN_EINVAL, "a context appears twice in the batch");
         if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
         if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "materials and striker must be set first");
-        if (c->device != cases[0]->device || c->precision != cases[0]->precision)
-            return set_err(c, PDN_EINVAL, "batched cases must share device and precision");
+        if (c->device != cases[0]->device || c->precision != cases[0]->precision || c->ngp != cases[0]->ngp)
+            return set_err(c, PDN_EINVAL, "batched cases must share device, precision and element integration");
     }
     pdn_batch *b = new pdn_batch;
     b->cs.assign(cases, cases + n);
     b->device = cases[0]->device;
     b->precision = cases[0]->precision;
+    b->ngp = cases[0]->ngp;
     b->stream = cases[0]->stream;
     (void)hipSetDevice(b->device);
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -1442,7 +1454,7 @@ int pdn_batch_create(pdn_ctx *const *cases, int32_t n, pdn_batch **out)
     } else {
         float best_ms = 0;
         for (int t : kTileOrder) {
-            bool fits = true;
+            bool fits = b->ngp == 1 || pdn::tile_has_full(t);
             for (pdn_ctx *c : b->cs) fits = fits && tile_fits(c, t);
             if (!fits) continue;
             float ms = 0;
@@ -1801,6 +1813,7 @@ int pdn_surrogate_set(pdn_ctx *c, int32_t ply, const float *weights, int64_t n, 
     if (!weights || n != SUR_NPARAM) return set_err(c, PDN_EINVAL, "surrogate needs %d parameters", SUR_NPARAM);
     if (ply < -1 || ply >= c->P) return set_err(c, PDN_EINVAL, "ply index %d out of range", ply);
     if (!(dmg_thresh >= 0) || !(res_thresh >= 0)) return set_err(c, PDN_EINVAL, "thresholds must be >= 0");
+    if (c->ngp != 1) return set_err(c, PDN_EINVAL, "surrogate plies need one-point integration");
     for (int p = 0; p < c->P; ++p)
         if ((ply < 0 || p == ply) && (!c->mat_set[p] || c->mat[p].law == PDN_LAW_ELASTIC))
             return set_err(c, PDN_ESTATE, "ply %d has no damage law to replace", p);

@@ -115,19 +115,16 @@ __device__ __forceinline__ void inv8(const Modes<R> &c, R f[8])
     f[4] = q0 + r0; f[5] = q1 + r1; f[6] = q2 + r2; f[7] = q3 + r3;
 }
 
-// Returns the force coefficients on the corner basis (forces = inv8 of each).
+// One point of a box element: Green strain of the displacement gradient G
+// (= F - I, row-major), ply frame, law (thresholds r), back to the global
+// frame, nominal stress Pn = F S (row-major).  Returns S:E in the ply frame
+// (twice the secant energy density).
 template <typename R, bool SUR>
-__device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
-                              R ihx, R ihy, R ihz, const PlyC<R> &P, R kappa, R r[4], bool &changed,
-                              Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel,
-                              const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact)
+__device__ __forceinline__ R box_point(const R G[9], const PlyC<R> &P, R vol, R r[4], bool &changed, R Pn[9],
+                                       const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact)
 {
-    Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
-    const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
-    // displacement gradient G = F - I
-    R G00 = sx.xi * gx, G01 = sx.eta * gy, G02 = sx.zeta * gz;
-    R G10 = sy.xi * gx, G11 = sy.eta * gy, G12 = sy.zeta * gz;
-    R G20 = sz.xi * gx, G21 = sz.eta * gy, G22 = sz.zeta * gz;
+    const R G00 = G[0], G01 = G[1], G02 = G[2], G10 = G[3], G11 = G[4], G12 = G[5];
+    const R G20 = G[6], G21 = G[7], G22 = G[8];
     // Green strain E = (G + G^T + G^T G)/2, formed without the 1 + small - 1 cancellation
     R E00 = G00 + R(0.5) * (G00 * G00 + G10 * G10 + G20 * G20);
     R E11 = G11 + R(0.5) * (G01 * G01 + G11 * G11 + G21 * G21);
@@ -145,7 +142,6 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
     e[4] = R(2) * (c * E02 + s * E12);
     e[5] = R(2) * (-cs * E00 + (cc - ss) * E01 + cs * E11);
     R sg[6];
-    const R vol = hx * hy * hz;
     exact = 0;
     if constexpr (SUR) {
         if (P.law == 2)
@@ -165,30 +161,102 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
     R S12 = s * sg[4] + c * sg[3];
     // nominal stress P = F S (index form (F S)_{iJ})
     R F00 = R(1) + G00, F11 = R(1) + G11, F22 = R(1) + G22;
-    R P00 = F00 * S00 + G01 * S01 + G02 * S02;
-    R P01 = F00 * S01 + G01 * S11 + G02 * S12;
-    R P02 = F00 * S02 + G01 * S12 + G02 * S22;
-    R P10 = G10 * S00 + F11 * S01 + G12 * S02;
-    R P11 = G10 * S01 + F11 * S11 + G12 * S12;
-    R P12 = G10 * S02 + F11 * S12 + G12 * S22;
-    R P20 = G20 * S00 + G21 * S01 + F22 * S02;
-    R P21 = G20 * S01 + G21 * S11 + F22 * S12;
-    R P22 = G20 * S02 + G21 * S12 + F22 * S22;
+    Pn[0] = F00 * S00 + G01 * S01 + G02 * S02;
+    Pn[1] = F00 * S01 + G01 * S11 + G02 * S12;
+    Pn[2] = F00 * S02 + G01 * S12 + G02 * S22;
+    Pn[3] = G10 * S00 + F11 * S01 + G12 * S02;
+    Pn[4] = G10 * S01 + F11 * S11 + G12 * S12;
+    Pn[5] = G10 * S02 + F11 * S12 + G12 * S22;
+    Pn[6] = G20 * S00 + G21 * S01 + F22 * S02;
+    Pn[7] = G20 * S01 + G21 * S11 + F22 * S12;
+    Pn[8] = G20 * S02 + G21 * S12 + F22 * S22;
+    return sg[0] * e[0] + sg[1] * e[1] + sg[2] * e[2] + sg[3] * e[3] + sg[4] * e[4] + sg[5] * e[5];
+}
+
+// One point with hourglass control.  Returns the force coefficients on the
+// corner basis (forces = inv8 of each).
+template <typename R, bool SUR>
+__device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
+                              R ihx, R ihy, R ihz, const PlyC<R> &P, R kappa, R r[4], bool &changed,
+                              Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel,
+                              const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact)
+{
+    Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
+    const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
+    // displacement gradient G = F - I (mean gradient)
+    const R G[9] = {sx.xi * gx, sx.eta * gy, sx.zeta * gz, sy.xi * gx, sy.eta * gy, sy.zeta * gz,
+                    sz.xi * gx, sz.eta * gy, sz.zeta * gz};
+    const R vol = hx * hy * hz;
+    R Pn[9];
+    const R w = box_point<R, SUR>(G, P, vol, r, changed, Pn, sur_pk, sur_dmg, sur_res, exact);
     const R ax = R(0.25) * hy * hz, ay = R(0.25) * hx * hz, az = R(0.25) * hx * hy;
     // hourglass: k = kappa Cmax V sum b^2 / 3, q = s/8, force coefficient k s / 64
     const R khg = kappa * P.cmax * vol * (ihx * ihx + ihy * ihy + ihz * ihz) * R(1.0 / 6.0);
     const R kh = khg * R(1.0 / 64.0);
-    cx.xi = P00 * ax; cx.eta = P01 * ay; cx.zeta = P02 * az;
-    cy.xi = P10 * ax; cy.eta = P11 * ay; cy.zeta = P12 * az;
-    cz.xi = P20 * ax; cz.eta = P21 * ay; cz.zeta = P22 * az;
+    cx.xi = Pn[0] * ax; cx.eta = Pn[1] * ay; cx.zeta = Pn[2] * az;
+    cy.xi = Pn[3] * ax; cy.eta = Pn[4] * ay; cy.zeta = Pn[5] * az;
+    cz.xi = Pn[6] * ax; cz.eta = Pn[7] * ay; cz.zeta = Pn[8] * az;
     cx.ez = kh * sx.ez; cx.xz = kh * sx.xz; cx.xe = kh * sx.xe; cx.xez = kh * sx.xez;
     cy.ez = kh * sy.ez; cy.xz = kh * sy.xz; cy.xe = kh * sy.xe; cy.xez = kh * sy.xez;
     cz.ez = kh * sz.ez; cz.xz = kh * sz.xz; cz.xe = kh * sz.xe; cz.xez = kh * sz.xez;
-    R w = sg[0] * e[0] + sg[1] * e[1] + sg[2] * e[2] + sg[3] * e[3] + sg[4] * e[4] + sg[5] * e[5];
     R q2 = sx.ez * sx.ez + sx.xz * sx.xz + sx.xe * sx.xe + sx.xez * sx.xez
          + sy.ez * sy.ez + sy.xz * sy.xz + sy.xe * sy.xe + sy.xez * sy.xez
          + sz.ez * sz.ez + sz.xz * sz.xz + sz.xe * sz.xe + sz.xez * sz.xez;
     uel = R(0.5) * vol * w + R(0.5) * khg * q2 * R(1.0 / 64.0);
+}
+
+// Full 2x2x2 Gauss integration of the same box (the paper's element,
+// Section 2).  At the point (xi, eta, zeta) = (+-g, +-g, +-g), g = 1/sqrt(3),
+// the gradient of the trilinear field is the mean gradient plus the mixed
+// corner modes weighted by the point's coordinates, e.g.
+//   du/dx = (s.xi + eta s.xe + zeta s.xz + eta zeta s.xez) / (4 hx);
+// each point calls the law with its own thresholds r[g], and its virtual work
+// (weight det J = V/8) lands on all seven corner-basis coefficients.  There
+// is no hourglass control.  Bit g of changed is set when r[g] changed.
+template <typename R>
+__device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
+                                   R ihx, R ihy, R ihz, const PlyC<R> &P, R r[8][4], unsigned &changed,
+                                   Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel)
+{
+    const Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
+    const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
+    const R vol = hx * hy * hz, wq = R(0.125) * vol;
+    const R gp = R(0.57735026918962576451);
+    const R ax = wq * gx, ay = wq * gy, az = wq * gz;
+    cx = cy = cz = Modes<R>{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
+    R wsum = R(0);
+    changed = 0u;
+#pragma unroll 1
+    for (int g = 0; g < 8; ++g) {
+        const R xi = (g & 1) ? gp : -gp, eta = (g & 2) ? gp : -gp, zeta = (g & 4) ? gp : -gp;
+        const R ez = eta * zeta, xz = xi * zeta, xe = xi * eta;
+        R G[9];
+        const Modes<R> *sm[3] = {&sx, &sy, &sz};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const Modes<R> &m = *sm[c];
+            G[3 * c + 0] = gx * (m.xi + eta * m.xe + zeta * m.xz + ez * m.xez);
+            G[3 * c + 1] = gy * (m.eta + xi * m.xe + zeta * m.ez + xz * m.xez);
+            G[3 * c + 2] = gz * (m.zeta + xi * m.xz + eta * m.ez + xe * m.xez);
+        }
+        R Pn[9];
+        bool ch = false;
+        int ex;
+        wsum += box_point<R, false>(G, P, vol, r[g], ch, Pn, nullptr, 0.f, 0.f, ex);
+        changed |= (ch ? 1u : 0u) << g;
+        Modes<R> *cm[3] = {&cx, &cy, &cz};
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            Modes<R> &m = *cm[c];
+            const R q0 = ax * Pn[3 * c], q1 = ay * Pn[3 * c + 1], q2 = az * Pn[3 * c + 2];
+            m.xi += q0; m.eta += q1; m.zeta += q2;
+            m.xe += eta * q0 + xi * q1;
+            m.xz += zeta * q0 + xi * q2;
+            m.ez += zeta * q1 + eta * q2;
+            m.xez += ez * q0 + xz * q1 + xe * q2;
+        }
+    }
+    uel = R(0.5) * wq * wsum;
 }
 
 // ---------------------------------------------------------------------------
@@ -391,7 +459,7 @@ __device__ void contact_books(const ElemArgs<R> &A, double *sh)
 // one workgroup's tile of one plate; block partials go to A.partials[tile].
 // SUR: plies with law 2 use the surrogate network (a separate instantiation,
 // so that the plain path keeps its register budget)
-template <typename R, int TX, int TY, bool SUR>
+template <typename R, int TX, int TY, bool SUR, int NGP>
 __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int tile)
 {
     constexpr int NE = TX * TY, NCX = TX + 1, NCY = TY + 1, NC = NCX * NCY;
@@ -490,7 +558,7 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         const int lt = uni(Lr.type), li = uni(Lr.index);
         const int64_t eidx = lt == 0 ? iv + (int64_t)nx * (jv + (int64_t)ny * li) : 0;
         const int64_t pidx = lt == 0 ? 0 : (nvalid ? col : 0) + plane * li;
-        load_state(A.r, eidx, rn);
+        if constexpr (NGP == 1) load_state(A.r, eidx, rn);
         rdn = A.rd[pidx];
     };
 
@@ -606,6 +674,15 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         stage_plane(k, pd, pv);
         R r[4] = {rn[0], rn[1], rn[2], rn[3]};
         const R rdl = rdn;
+        // full integration: the eight points' thresholds of this layer, issued
+        // before the plane prefetch so that waiting for them leaves it in flight
+        // (a fixed address in a cohesive layer keeps the load pattern static)
+        R r8[NGP][4];
+        if constexpr (NGP == 8) {
+            const int64_t e8 = ltype == 0 ? 8 * (iv + (int64_t)nx * (jv + (int64_t)ny * lidx)) : 0;
+#pragma unroll
+            for (int g = 0; g < 8; ++g) load_state(A.r, e8 + g, r8[g]);
+        }
         // thresholds first: the wait for them next layer then leaves the plane
         // loads (issued after them) in flight
         fetch_r(k);
@@ -630,14 +707,27 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                 R uel;
                 int exact;
                 Modes<R> cm[3];
-                hex_box_force<R, SUR>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P,
-                              A.kappa, r, changed, cm[0], cm[1], cm[2], uel, A.mlp, A.sur_dmg, A.sur_res, exact);
-                if (eown) {
-                    if (changed) store_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * lidx), r);
-                    acc[T_UEL] += (double)uel;
-                    if (P.law == 2) {
-                        acc[T_AUX] += (double)exact;
-                        acc[T_SURN] += 1.0;
+                if constexpr (NGP == 8) {
+                    unsigned chm;
+                    hex_box_force_full<R>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, r8, chm, cm[0], cm[1],
+                                          cm[2], uel);
+                    if (eown) {
+                        const int64_t e8 = 8 * (ie + (int64_t)nx * (je + (int64_t)ny * lidx));
+#pragma unroll
+                        for (int g = 0; g < 8; ++g)
+                            if ((chm >> g) & 1u) store_state(A.r, e8 + g, r8[g]);
+                        acc[T_UEL] += (double)uel;
+                    }
+                } else {
+                    hex_box_force<R, SUR>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.kappa, r, changed,
+                                          cm[0], cm[1], cm[2], uel, A.mlp, A.sur_dmg, A.sur_res, exact);
+                    if (eown) {
+                        if (changed) store_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * lidx), r);
+                        acc[T_UEL] += (double)uel;
+                        if (P.law == 2) {
+                            acc[T_AUX] += (double)exact;
+                            acc[T_SURN] += 1.0;
+                        }
                     }
                 }
                 if (erole) {
@@ -764,11 +854,11 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     }
 }
 
-template <typename R, int TX, int TY, bool SUR>
+template <typename R, int TX, int TY, bool SUR, int NGP = 1>
 __global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
 void k_elem_node(ElemArgs<R> A)
 {
-    elem_node_tile<R, TX, TY, SUR>(A, xcd_tile(blockIdx.x, gridDim.x));
+    elem_node_tile<R, TX, TY, SUR, NGP>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // case of global block b in a batch: the last c with start[c] <= b
@@ -785,14 +875,14 @@ __device__ __forceinline__ int batch_case(const int *start, int ncase, int b)
 
 // many plates in one launch: tiles of case c are blocks start[c] .. start[c+1)-1
 // (after the XCD remap, so that one case's neighbouring tiles share an L2)
-template <typename R, int TX, int TY, bool SUR>
+template <typename R, int TX, int TY, bool SUR, int NGP = 1>
 __global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
 void k_elem_node_batch(const ElemArgs<R> *__restrict__ args, const int *__restrict__ start, int ncase)
 {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
     const int c = batch_case(start, ncase, b);
     const ElemArgs<R> A = args[c];
-    elem_node_tile<R, TX, TY, SUR>(A, b - start[c]);
+    elem_node_tile<R, TX, TY, SUR, NGP>(A, b - start[c]);
 }
 
 #define PDN_BOOKS_THREADS 256
@@ -815,11 +905,11 @@ __global__ __launch_bounds__(PDN_BOOKS_THREADS) void k_books_batch(const ElemArg
 // ---------------------------------------------------------------------------
 // launchers of one variant
 // ---------------------------------------------------------------------------
-template <typename R, int TX, int TY, bool SUR>
+template <typename R, int TX, int TY, bool SUR, int NGP = 1>
 static hipError_t launch_en(const ElemArgs<R> &a, hipStream_t s)
 {
     const int nb = a.tiles_x * a.tiles_y;
-    hipLaunchKernelGGL((k_elem_node<R, TX, TY, SUR>), dim3(nb), dim3(PDN_TILE_THREADS(TX, TY)), 0, s, a);
+    hipLaunchKernelGGL((k_elem_node<R, TX, TY, SUR, NGP>), dim3(nb), dim3(PDN_TILE_THREADS(TX, TY)), 0, s, a);
     return hipGetLastError();
 }
 
@@ -836,11 +926,11 @@ static hipError_t launch_elem_node_v(const ElemArgs<R> &a, int tile, hipStream_t
     }
 }
 
-template <typename R, int TX, int TY, bool SUR>
+template <typename R, int TX, int TY, bool SUR, int NGP = 1>
 static int lds_of()
 {
     hipFuncAttributes at;
-    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_elem_node<R, TX, TY, SUR>)) != hipSuccess)
+    if (hipFuncGetAttributes(&at, reinterpret_cast<const void *>(&k_elem_node<R, TX, TY, SUR, NGP>)) != hipSuccess)
         return -1;
     return (int)at.sharedSizeBytes;
 }
@@ -858,10 +948,10 @@ static int lds_v(int tile)
     }
 }
 
-template <typename R, int TX, int TY, bool SUR>
+template <typename R, int TX, int TY, bool SUR, int NGP = 1>
 static hipError_t launch_enb(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_elem_node_batch<R, TX, TY, SUR>), dim3(nblocks), dim3(PDN_TILE_THREADS(TX, TY)), 0, s,
+    hipLaunchKernelGGL((k_elem_node_batch<R, TX, TY, SUR, NGP>), dim3(nblocks), dim3(PDN_TILE_THREADS(TX, TY)), 0, s,
                        args, start, ncase);
     return hipGetLastError();
 }
@@ -877,6 +967,29 @@ static hipError_t launch_elem_node_batch_v(const ElemArgs<R> *args, const int *s
     case PDN_TILE_8x8: return launch_enb<R, 8, 8, SUR>(args, start, ncase, nblocks, s);
     case PDN_TILE_15x15: return launch_enb<R, 15, 15, SUR>(args, start, ncase, nblocks, s);
     case PDN_TILE_31x15: return launch_enb<R, 31, 15, SUR>(args, start, ncase, nblocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// full integration: the tiles it is built for
+template <typename R>
+static hipError_t launch_elem_node_full_v(const ElemArgs<R> &a, int tile, hipStream_t s)
+{
+    switch (tile) {
+    case PDN_TILE_16x16: return launch_en<R, 16, 16, false, 8>(a, s);
+    case PDN_TILE_15x15: return launch_en<R, 15, 15, false, 8>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+static hipError_t launch_elem_node_batch_full_v(const ElemArgs<R> *args, const int *start, int ncase, int nblocks,
+                                                int tile, hipStream_t s)
+{
+    if (ncase < 1 || nblocks < 1) return hipErrorInvalidValue;
+    switch (tile) {
+    case PDN_TILE_16x16: return launch_enb<R, 16, 16, false, 8>(args, start, ncase, nblocks, s);
+    case PDN_TILE_15x15: return launch_enb<R, 15, 15, false, 8>(args, start, ncase, nblocks, s);
     default: return hipErrorInvalidValue;
     }
 }

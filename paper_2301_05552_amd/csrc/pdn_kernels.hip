@@ -61,28 +61,32 @@ __global__ void k_cand_scatter(ContactArgs C)
 // damage fields
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void k_damage_bulk(const R *r, const LayerInfo *layers, const int *bulk_layer, const PlyC<R> *ply,
-                              const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind, double *out)
+__global__ void k_damage_bulk(const R *r, int ngp, const LayerInfo *layers, const int *bulk_layer,
+                              const PlyC<R> *ply, const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind,
+                              double *out)
 {
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ne; e += (int64_t)gridDim.x * blockDim.x) {
         const int ie = (int)(e % nx), je = (int)((e / nx) % ny), lb = (int)(e / ((int64_t)nx * ny));
         const LayerInfo L = layers[bulk_layer[lb]];
         const PlyC<R> &P = ply[L.ply];
         double val = 0;
-        if (P.law != 0) {
+        // the largest over the element's Gauss points
+        for (int g = 0; g < ngp && P.law != 0; ++g) {
             const R lc = cbrt(hx[ie] * hy[je] * (R)L.hz);
-            const R *q = r + 4 * e;
+            const R *q = r + 4 * (ngp * e + g);
+            double vg;
             if (kind == 0) {
                 R a = damage_bilinear(q[0], P.XT, P.E1, P.GXT, P.fXT, P.fGT, lc);
                 R b = damage_bilinear(q[1], P.XC, P.E1, P.GXC, P.fXC, P.fGC, lc);
-                val = (double)rmax(a, b);
+                vg = (double)rmax(a, b);
             } else if (kind == 1) {
                 R a = damage_exp(q[2], cap_strength(P.YT, P.E2, P.GYT, lc), P.E2, P.GYT, lc);
                 R b = damage_exp(q[3], cap_strength(P.YC, P.E2, P.GYC, lc), P.E2, P.GYC, lc);
-                val = (double)rmax(a, b);
+                vg = (double)rmax(a, b);
             } else {
-                val = (double)damage_exp(q[2], cap_strength(P.SL, P.G12v, P.GSL, lc), P.G12v, P.GSL, lc);
+                vg = (double)damage_exp(q[2], cap_strength(P.SL, P.G12v, P.GSL, lc), P.G12v, P.GSL, lc);
             }
+            val = fmax(val, vg);
         }
         out[e] = val;
     }
@@ -127,12 +131,13 @@ __global__ void k_project_max(const double *in, int64_t ncol, int nlayers, doubl
 // ---------------------------------------------------------------------------
 
 template <typename R>
-hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, hipStream_t s)
+hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, int ngp, hipStream_t s)
 {
+    if (ngp == 8) return sur ? hipErrorInvalidValue : launch_elem_node_full<R>(a, tile, s);
     return sur ? launch_elem_node_sur<R>(a, tile, s) : launch_elem_node_v<R, false>(a, tile, s);
 }
-template hipError_t launch_elem_node<float>(const ElemArgs<float> &, int, bool, hipStream_t);
-template hipError_t launch_elem_node<double>(const ElemArgs<double> &, int, bool, hipStream_t);
+template hipError_t launch_elem_node<float>(const ElemArgs<float> &, int, bool, int, hipStream_t);
+template hipError_t launch_elem_node<double>(const ElemArgs<double> &, int, bool, int, hipStream_t);
 
 template <typename R>
 hipError_t launch_books(const ElemArgs<R> &a, hipStream_t s)
@@ -151,20 +156,22 @@ int elem_node_lds_bytes(int mixed, int tile, bool sur)
 
 template <typename R>
 hipError_t launch_elem_node_batch(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
-                                  bool sur, bool contact, hipStream_t s)
+                                  bool sur, int ngp, bool contact, hipStream_t s)
 {
-    hipError_t e = sur ? launch_elem_node_batch_sur<R>(args, start, ncase, nblocks, tile, s)
-                       : launch_elem_node_batch_v<R, false>(args, start, ncase, nblocks, tile, s);
+    hipError_t e = ngp == 8 ? (sur ? hipErrorInvalidValue
+                                   : launch_elem_node_batch_full<R>(args, start, ncase, nblocks, tile, s))
+                 : sur      ? launch_elem_node_batch_sur<R>(args, start, ncase, nblocks, tile, s)
+                            : launch_elem_node_batch_v<R, false>(args, start, ncase, nblocks, tile, s);
     if (e == hipSuccess && contact) {
         hipLaunchKernelGGL(k_books_batch<R>, dim3(ncase), dim3(PDN_BOOKS_THREADS), 0, s, args);
         e = hipGetLastError();
     }
     return e;
 }
-template hipError_t launch_elem_node_batch<float>(const ElemArgs<float> *, const int *, int, int, int, bool, bool,
-                                                  hipStream_t);
-template hipError_t launch_elem_node_batch<double>(const ElemArgs<double> *, const int *, int, int, int, bool, bool,
-                                                   hipStream_t);
+template hipError_t launch_elem_node_batch<float>(const ElemArgs<float> *, const int *, int, int, int, bool, int,
+                                                  bool, hipStream_t);
+template hipError_t launch_elem_node_batch<double>(const ElemArgs<double> *, const int *, int, int, int, bool, int,
+                                                   bool, hipStream_t);
 
 hipError_t launch_contact_init(const ContactArgs &c, int reset_active, hipStream_t s)
 {
@@ -183,23 +190,23 @@ hipError_t launch_cand_scatter(const ContactArgs &c, hipStream_t s)
 }
 
 template <typename R>
-hipError_t launch_damage_bulk(const R *r, const LayerInfo *layers, const int *bulk_layer, const PlyC<R> *ply,
-                              const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind, double *out,
-                              hipStream_t s)
+hipError_t launch_damage_bulk(const R *r, int ngp, const LayerInfo *layers, const int *bulk_layer,
+                              const PlyC<R> *ply, const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind,
+                              double *out, hipStream_t s)
 {
     int64_t nb = (ne + 255) / 256;
     if (nb > 65536) nb = 65536;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_damage_bulk<R>, dim3((unsigned)nb), dim3(256), 0, s, r, layers, bulk_layer, ply, hx, hy,
-                       nx, ny, ne, kind, out);
+    hipLaunchKernelGGL(k_damage_bulk<R>, dim3((unsigned)nb), dim3(256), 0, s, r, ngp, layers, bulk_layer, ply, hx,
+                       hy, nx, ny, ne, kind, out);
     return hipGetLastError();
 }
-template hipError_t launch_damage_bulk<float>(const float *, const LayerInfo *, const int *, const PlyC<float> *,
-                                              const float *, const float *, int, int, int64_t, int, double *,
-                                              hipStream_t);
-template hipError_t launch_damage_bulk<double>(const double *, const LayerInfo *, const int *, const PlyC<double> *,
-                                               const double *, const double *, int, int, int64_t, int, double *,
-                                               hipStream_t);
+template hipError_t launch_damage_bulk<float>(const float *, int, const LayerInfo *, const int *,
+                                              const PlyC<float> *, const float *, const float *, int, int, int64_t,
+                                              int, double *, hipStream_t);
+template hipError_t launch_damage_bulk<double>(const double *, int, const LayerInfo *, const int *,
+                                               const PlyC<double> *, const double *, const double *, int, int,
+                                               int64_t, int, double *, hipStream_t);
 
 template <typename R>
 hipError_t launch_damage_coh(const R *rd, const double *d, const LayerInfo *layers, const int *coh_layer,

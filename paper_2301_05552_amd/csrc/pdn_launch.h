@@ -11,9 +11,17 @@ enum { PDN_TILE_16x16 = 0, PDN_TILE_32x8 = 1, PDN_TILE_8x8 = 2, PDN_TILE_15x15 =
 static const int pdn_tile_dims[PDN_TILE_COUNT][2] = {{16, 16}, {32, 8}, {8, 8}, {15, 15}, {31, 15}};
 
 namespace pdn {
-// sur: the instantiation that evaluates the surrogate network on plies of law 2
+// sur: the instantiation that evaluates the surrogate network on plies of law 2;
+// ngp: Gauss points of a bulk element (1 with hourglass control, or 8)
 template <typename R>
-hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, hipStream_t s);
+hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, int ngp, hipStream_t s);
+// full integration (ngp 8): built for the 15x15 and 16x16 tiles
+template <typename R>
+hipError_t launch_elem_node_full(const ElemArgs<R> &a, int tile, hipStream_t s);
+template <typename R>
+hipError_t launch_elem_node_batch_full(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
+                                       hipStream_t s);
+inline bool tile_has_full(int tile) { return tile == PDN_TILE_15x15 || tile == PDN_TILE_16x16; }
 // closes a contact pass (a.contact): books, striker update, history row
 template <typename R>
 hipError_t launch_books(const ElemArgs<R> &a, hipStream_t s);
@@ -23,7 +31,7 @@ hipError_t launch_elem_node_sur(const ElemArgs<R> &a, int tile, hipStream_t s);
 // contact: the arguments are contact passes; a books kernel closes each case's step
 template <typename R>
 hipError_t launch_elem_node_batch(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
-                                  bool sur, bool contact, hipStream_t s);
+                                  bool sur, int ngp, bool contact, hipStream_t s);
 template <typename R>
 hipError_t launch_elem_node_batch_sur(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
                                       hipStream_t s);
@@ -32,10 +40,11 @@ int elem_node_lds_bytes(int mixed, int tile, bool sur);   // static LDS of one w
 int elem_node_lds_bytes_sur(int mixed, int tile);
 hipError_t launch_contact_init(const ContactArgs &c, int reset_active, hipStream_t s);
 hipError_t launch_cand_scatter(const ContactArgs &c, hipStream_t s);
+// per element: the largest over its ngp Gauss points
 template <typename R>
-hipError_t launch_damage_bulk(const R *r, const LayerInfo *layers, const int *bulk_layer, const PlyC<R> *ply,
-                              const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind, double *out,
-                              hipStream_t s);
+hipError_t launch_damage_bulk(const R *r, int ngp, const LayerInfo *layers, const int *bulk_layer,
+                              const PlyC<R> *ply, const R *hx, const R *hy, int nx, int ny, int64_t ne, int kind,
+                              double *out, hipStream_t s);
 template <typename R>
 hipError_t launch_damage_coh(const R *rd, const double *d, const LayerInfo *layers, const int *coh_layer,
                              const PlyC<R> *ply, int nx, int ny, int64_t nce, double *out, hipStream_t s);
