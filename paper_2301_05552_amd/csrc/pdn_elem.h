@@ -115,6 +115,30 @@ __device__ __forceinline__ void inv8(const Modes<R> &c, R f[8])
     f[4] = q0 + r0; f[5] = q1 + r1; f[6] = q2 + r2; f[7] = q3 + r3;
 }
 
+template <typename R>
+__device__ __forceinline__ void load_state(const R *r, int64_t e, R out[4])
+{
+    const R *p = r + 4 * e;
+    out[0] = p[0]; out[1] = p[1]; out[2] = p[2]; out[3] = p[3];
+}
+template <>
+__device__ __forceinline__ void load_state<float>(const float *r, int64_t e, float out[4])
+{
+    float4 v = reinterpret_cast<const float4 *>(r)[e];
+    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+}
+template <typename R>
+__device__ __forceinline__ void store_state(R *r, int64_t e, const R in[4])
+{
+    R *p = r + 4 * e;
+    p[0] = in[0]; p[1] = in[1]; p[2] = in[2]; p[3] = in[3];
+}
+template <>
+__device__ __forceinline__ void store_state<float>(float *r, int64_t e, const float in[4])
+{
+    reinterpret_cast<float4 *>(r)[e] = make_float4(in[0], in[1], in[2], in[3]);
+}
+
 // One point of a box element: Green strain of the displacement gradient G
 // (= F - I, row-major), ply frame, law (thresholds r), back to the global
 // frame, nominal stress Pn = F S (row-major).  Returns S:E in the ply frame
@@ -212,10 +236,12 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
 //   du/dx = (s.xi + eta s.xe + zeta s.xz + eta zeta s.xez) / (4 hx);
 // each point calls the law with its own thresholds r[g], and its virtual work
 // (weight det J = V/8) lands on all seven corner-basis coefficients.  There
-// is no hourglass control.  Bit g of changed is set when r[g] changed.
+// is no hourglass control.  The thresholds of point g are record e8 + g of
+// rstate, read just before the point's law call and written back (by the
+// owning lane) when they changed, so only one point's state is live at a time.
 template <typename R>
 __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
-                                   R ihx, R ihy, R ihz, const PlyC<R> &P, R r[8][4], unsigned &changed,
+                                   R ihx, R ihy, R ihz, const PlyC<R> &P, R *rstate, int64_t e8, bool own,
                                    Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel)
 {
     const Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
@@ -225,9 +251,10 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
     const R ax = wq * gx, ay = wq * gy, az = wq * gz;
     cx = cy = cz = Modes<R>{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
     R wsum = R(0);
-    changed = 0u;
 #pragma unroll 1
     for (int g = 0; g < 8; ++g) {
+        R rg[4];
+        load_state(rstate, e8 + g, rg);
         const R xi = (g & 1) ? gp : -gp, eta = (g & 2) ? gp : -gp, zeta = (g & 4) ? gp : -gp;
         const R ez = eta * zeta, xz = xi * zeta, xe = xi * eta;
         R G[9];
@@ -242,8 +269,8 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
         R Pn[9];
         bool ch = false;
         int ex;
-        wsum += box_point<R, false>(G, P, vol, r[g], ch, Pn, nullptr, 0.f, 0.f, ex);
-        changed |= (ch ? 1u : 0u) << g;
+        wsum += box_point<R, false>(G, P, vol, rg, ch, Pn, nullptr, 0.f, 0.f, ex);
+        if (own && ch) store_state(rstate, e8 + g, rg);
         Modes<R> *cm[3] = {&cx, &cy, &cz};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -301,29 +328,6 @@ __device__ __forceinline__ double uni(double x)
     return __builtin_bit_cast(double, make_int2(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y)));
 }
 
-template <typename R>
-__device__ __forceinline__ void load_state(const R *r, int64_t e, R out[4])
-{
-    const R *p = r + 4 * e;
-    out[0] = p[0]; out[1] = p[1]; out[2] = p[2]; out[3] = p[3];
-}
-template <>
-__device__ __forceinline__ void load_state<float>(const float *r, int64_t e, float out[4])
-{
-    float4 v = reinterpret_cast<const float4 *>(r)[e];
-    out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
-}
-template <typename R>
-__device__ __forceinline__ void store_state(R *r, int64_t e, const R in[4])
-{
-    R *p = r + 4 * e;
-    p[0] = in[0]; p[1] = in[1]; p[2] = in[2]; p[3] = in[3];
-}
-template <>
-__device__ __forceinline__ void store_state<float>(float *r, int64_t e, const float in[4])
-{
-    reinterpret_cast<float4 *>(r)[e] = make_float4(in[0], in[1], in[2], in[3]);
-}
 
 // A node's xyz (24 bytes, 8-byte aligned) as a 16-byte and an 8-byte access:
 // two memory instructions per node and array instead of three.
@@ -674,15 +678,6 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         stage_plane(k, pd, pv);
         R r[4] = {rn[0], rn[1], rn[2], rn[3]};
         const R rdl = rdn;
-        // full integration: the eight points' thresholds of this layer, issued
-        // before the plane prefetch so that waiting for them leaves it in flight
-        // (a fixed address in a cohesive layer keeps the load pattern static)
-        R r8[NGP][4];
-        if constexpr (NGP == 8) {
-            const int64_t e8 = ltype == 0 ? 8 * (iv + (int64_t)nx * (jv + (int64_t)ny * lidx)) : 0;
-#pragma unroll
-            for (int g = 0; g < 8; ++g) load_state(A.r, e8 + g, r8[g]);
-        }
         // thresholds first: the wait for them next layer then leaves the plane
         // loads (issued after them) in flight
         fetch_r(k);
@@ -708,16 +703,11 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                 int exact;
                 Modes<R> cm[3];
                 if constexpr (NGP == 8) {
-                    unsigned chm;
-                    hex_box_force_full<R>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, r8, chm, cm[0], cm[1],
-                                          cm[2], uel);
-                    if (eown) {
-                        const int64_t e8 = 8 * (ie + (int64_t)nx * (je + (int64_t)ny * lidx));
-#pragma unroll
-                        for (int g = 0; g < 8; ++g)
-                            if ((chm >> g) & 1u) store_state(A.r, e8 + g, r8[g]);
-                        acc[T_UEL] += (double)uel;
-                    }
+                    // lanes without an element read a valid record (clamped) and write nothing
+                    const int64_t e8 = 8 * (iv + (int64_t)nx * (jv + (int64_t)ny * lidx));
+                    hex_box_force_full<R>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.r, e8, eown, cm[0],
+                                          cm[1], cm[2], uel);
+                    if (eown) acc[T_UEL] += (double)uel;
                 } else {
                     hex_box_force<R, SUR>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.kappa, r, changed,
                                           cm[0], cm[1], cm[2], uel, A.mlp, A.sur_dmg, A.sur_res, exact);
