@@ -237,8 +237,8 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
 // each point calls the law with its own thresholds r[g], and its virtual work
 // (weight det J = V/8) lands on all seven corner-basis coefficients.  There
 // is no hourglass control.  The thresholds of point g are record e8 + g of
-// rstate, read just before the point's law call and written back (by the
-// owning lane) when they changed, so only one point's state is live at a time.
+// rstate, read one point ahead and written back (by the owning lane) when they
+// changed, so at most two points' states are live at a time.
 template <typename R>
 __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
                                    R ihx, R ihy, R ihz, const PlyC<R> &P, R *rstate, int64_t e8, bool own,
@@ -251,10 +251,13 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
     const R ax = wq * gx, ay = wq * gy, az = wq * gz;
     cx = cy = cz = Modes<R>{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
     R wsum = R(0);
+    // the next point's thresholds are loaded while this point is computed
+    R rn[4];
+    load_state(rstate, e8, rn);
 #pragma unroll 1
     for (int g = 0; g < 8; ++g) {
-        R rg[4];
-        load_state(rstate, e8 + g, rg);
+        R rg[4] = {rn[0], rn[1], rn[2], rn[3]};
+        load_state(rstate, e8 + (g < 7 ? g + 1 : 7), rn);
         const R xi = (g & 1) ? gp : -gp, eta = (g & 2) ? gp : -gp, zeta = (g & 4) ? gp : -gp;
         const R ez = eta * zeta, xz = xi * zeta, xe = xi * eta;
         R G[9];
