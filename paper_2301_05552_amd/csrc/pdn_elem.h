@@ -582,7 +582,7 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         const double im = imxy * cload(A.imz + kp);
         const double dt = A.dt, g = A.grav;
         acc[T_MZ] += m * D64[p][2][t];         // gravity work = -g (sum m d_z - its initial value)
-        double dn[3], vn[3];
+        double dn[3], vn[3], vvn = 0.0, vf = 0.0, vnf = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double d = D64[p][c][t], v = V64[p][c][t];
@@ -591,10 +591,14 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             const double a = fx ? 0.0 : (fe - f[c]) * im;
             vn[c] = fx ? 0.0 : v + dt * a;
             dn[c] = fx ? d : d + dt * v + A.phi * dt * dt * a;
-            acc[T_KE] += 0.5 * m * v * vn[c];
-            acc[T_WA] += 0.5 * dt * v * f[c];
-            acc[T_WB] += 0.5 * dt * vn[c] * f[c];
+            vvn += v * vn[c];
+            vf += v * f[c];
+            vnf += vn[c] * f[c];
         }
+        // half-step kinetic energy and the two halves of the trapezoidal internal work
+        acc[T_KE] += 0.5 * m * vvn;
+        acc[T_WA] += 0.5 * dt * vf;
+        acc[T_WB] += 0.5 * dt * vnf;
         store_xyz(A.d_out + 3 * n, dn);
         store_xyz(A.v_out + 3 * n, vn);
     };
