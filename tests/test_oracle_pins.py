@@ -701,6 +701,53 @@ def test_non_penetration_and_eq2_every_step():
     assert seen > 0
 
 
+def _graded(h0, w0, ratio, total):
+    """Grid lines from 0: spacing h0 up to w0, then growing by `ratio` up to `total`."""
+    xs = list(np.arange(0.0, w0 + 1e-12, h0))
+    h = h0
+    while xs[-1] < total - 1e-12:
+        h *= ratio
+        xs.append(xs[-1] + h)
+    return np.array(xs)
+
+
+def test_quasi_static_hertz_indentation():
+    """The PDN contact (Section 2.1, Eqs. 2-3) against Hertz's closed form.
+
+    A rigid sphere of radius 8 mm indents an elastic block (E = 70 GPa,
+    nu = 0.3) at 1 m/s: the striker mass is 1e9 kg, so its displacement is
+    prescribed to round-off and the load rises slowly against the block's
+    wave transit time.  The block is 27 x 27 x 13.5 mm with its bottom fixed,
+    deep enough that the rigid base stiffens it by well under 1 % (a 16 x 16 x 8
+    mm block reads 1-3 % high), meshed at 0.1 mm under the striker and
+    graded outwards.  At indentations of 20 and 50 um (contact radii 0.40 and
+    0.63 mm) the force equals (4/3) E/(1 - nu^2) sqrt(R) delta^(3/2) =
+    820.5 N and 3243 N within 3 %."""
+    side = _graded(0.1e-3, 0.6e-3, 1.45, 12e-3)
+    xs = np.concatenate([-side[::-1], side[1:]]) + side[-1]
+    depth = _graded(0.1e-3, 0.6e-3, 1.45, 12e-3)
+    H = depth[-1]
+    zs = H - depth[::-1]
+    nx, nz, L = len(xs) - 1, len(zs) - 1, xs[-1]
+    E, nu = 70e9, 0.3
+    cfg = dict(mesh=W._mesh(nx, nx, 1, nz, L, L, H, [0.0], bc=W.BC_FREE, gravity=0.0),
+               materials=[W.material_isotropic(E, nu, 2700.0)],
+               impactor=W.impactor(8e-3, 1e9, v0=1.0, gap=1e-7))
+    X = np.stack(np.meshgrid(xs, xs, zs, indexing="ij"), axis=-1).transpose(2, 1, 0, 3).reshape(-1, 3)
+    o = oracle.Oracle(cfg, node_coords=X.reshape(-1), threads=min(8, os.cpu_count() or 1))
+    fix = np.zeros_like(X)
+    fix[:(nx + 1) * (nx + 1)] = 1.0                 # bottom plane
+    o.set(oracle.FIX, fix.reshape(-1))
+    o.step(int((52e-6 + 1e-7) / 1.0 / o.dt) + 1)
+    t, f, x = o.history()
+    delta = x - 1e-7                                 # the sphere touches the centre node at x = gap
+    Es = E / (1 - nu * nu)
+    for d, F_h in ((20e-6, 820.5), (50e-6, 3243.4)):
+        assert abs(4.0 / 3.0 * Es * np.sqrt(8e-3) * d ** 1.5 - F_h) <= 1e-3 * F_h
+        F = np.interp(d, delta, f)
+        assert abs(F - F_h) <= 0.03 * F_h, (d, F, F_h)
+
+
 def test_free_plate_momentum_closure():
     cfg = _contact_cfg()
     cfg["mesh"]["bc"] = 2
