@@ -282,6 +282,14 @@ def _run(cfg, stream, tile, nets, res, pre, warmup, steps, areas=None):
     return 1e3 * el / steps, info, float(f.max()) if len(f) else 0.0
 
 
+def _consulted(info) -> float:
+    """Fraction of the run's GP updates on which the network was consulted
+    (the others were screened elastic by the law); fallback_fraction is the
+    share of the consulted ones that the exact law produced."""
+    n = info["n_bulk"] * info["steps"]
+    return info["sur_consulted"] / n if n else 0.0
+
+
 def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_steps) -> dict:
     """The metric's second half: the same plate with the intralaminar update
     by the trained network (exact law as fallback), at the stated residual bar
@@ -303,7 +311,9 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
     for res in (1e-3, 3e-2):
         ms, info, fpk = _run(cfg, stream, tile, nets, res, pre, warmup, steps)
         out[f"res_{res:g}"] = {"value": info["n_bulk"] / (ms * 1e-3), "unit": "GP-updates/s", "ms_per_step": ms,
-                               "speedup_vs_plain": plain_ms / ms, "fallback_fraction": info["fallback_fraction"],
+                               "speedup_vs_plain": plain_ms / ms,
+                               "network_consulted_fraction": _consulted(info),
+                               "fallback_fraction": info["fallback_fraction"],
                                "peak_force_N": fpk, "plain_peak_force_N": f_plain}
     gold = os.path.join(ROOT, "tests", "golden", "qi8_300x200x8_fp64_oracle.json")
     if gate_steps and os.path.exists(gold):
@@ -338,6 +348,7 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
                     for k in ("fibre", "matrix") for thr in ("0", "0.5", "0.999")
                     if g["projected_damage"][k][thr]["area_m2"] > 0}
             if nn is not None:
+                e["network_consulted_fraction"] = _consulted(info)
                 e["fallback_fraction"] = info["fallback_fraction"]
             gate[name] = e
         out["accuracy_gate"] = gate

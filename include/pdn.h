@@ -128,8 +128,11 @@ typedef struct {
     double dt;
     int64_t n_nodes, n_bulk, n_cohesive, n_pairs, n_planes, n_layers, n_candidates;
     int64_t steps, reset_passes, released, active, max_passes;
-    double fallback_fraction;     /* surrogate: fraction of GP updates by the exact law */
+    double fallback_fraction;     /* surrogate: of the GP updates on which the network was consulted,
+                                     the fraction that the exact law produced (0 when none was) */
     int32_t precision, tile_x, tile_y, blocks;
+    double sur_consulted;         /* surrogate: GP updates on which the network was consulted; the
+                                     others of surrogate plies were screened elastic by the law */
 } pdn_info;
 
 /* Build the plate mesh and allocate device state on desc->device. */

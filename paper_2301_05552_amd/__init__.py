@@ -69,7 +69,7 @@ class Info(C.Structure):
         "n_nodes", "n_bulk", "n_cohesive", "n_pairs", "n_planes", "n_layers", "n_candidates",
         "steps", "reset_passes", "released", "active", "max_passes")] + [
         ("fallback_fraction", C.c_double), ("precision", C.c_int32), ("tile_x", C.c_int32),
-        ("tile_y", C.c_int32), ("blocks", C.c_int32)]
+        ("tile_y", C.c_int32), ("blocks", C.c_int32), ("sur_consulted", C.c_double)]
 
 
 def lib():

@@ -919,6 +919,7 @@ int pdn_info_get(const pdn_ctx *c, pdn_info *o)
     o->active = c->gl.active; o->max_passes = c->gl.max_passes;
     o->fallback_fraction = c->gl.sur_gp > 0 ? c->gl.fallback_gp / c->gl.sur_gp : 0.0;
     o->precision = c->precision;
+    o->sur_consulted = c->gl.sur_gp;
     o->tile_x = pdn_tile_dims[c->tile][0];
     o->tile_y = pdn_tile_dims[c->tile][1];
     o->blocks = c->nblocks;

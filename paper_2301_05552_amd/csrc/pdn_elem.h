@@ -12,17 +12,29 @@ namespace pdn {
 // ---------------------------------------------------------------------------
 // intralaminar update by the surrogate network with the exact law as fallback
 //
-// A point keeps the exact law when any damage variable of its incoming
-// thresholds exceeds dmg_thr, or when the network's stress disagrees with
-// the nominal stress of the network's own new thresholds by more than
-// res_thr (relative to |C0 e|, at least 1e-3 Y_T).  Every lane of the wave
-// must call it together (the network runs on the matrix cores); exact = 1
-// when the exact law produced the result.
+// A point that the law's screen proves elastic takes the law's exact answer
+// (C0 e, thresholds unchanged) without the network; a wave made of such
+// points does not run the network at all.  Of the other points, one keeps
+// the exact law when any damage variable of its incoming thresholds exceeds
+// dmg_thr, or when the network's stress disagrees with the nominal stress of
+// the network's own new thresholds by more than res_thr (relative to |C0 e|,
+// at least 1e-3 Y_T).  Every lane of the wave must call it together (the
+// network runs on the matrix cores).  exact: 0 the network's result, 1 the
+// exact law after the network was consulted, 2 screened elastic.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6], bool &changed,
                            const uint4 *__restrict__ pk, float dmg_thr, float res_thr, int &exact)
 {
+    R sel[6];
+    const bool el = cdm_screen<true>(P, vol, e, r, sel);
+    if (__ballot(!el) == 0) {                                   // uniform across the wave
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sg[k] = sel[k];
+        changed = false;
+        exact = 2;
+        return;
+    }
     const R lc = cbrt(vol);
     const R YT = cap_strength(P.YT, P.E2, P.GYT, lc);
     const R YC = cap_strength(P.YC, P.E2, P.GYC, lc);
@@ -36,7 +48,14 @@ __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
     for (int k = 0; k < 4; ++k) x[6 + k] = (float)(R(1) - R(1) / r[k]);
     bool fb = (r[0] > R(1) || r[1] > R(1) || r[2] > R(1) || r[3] > R(1)) &&
               cdm_max_damage(P, lc, YT, YC, SL, r) > (R)dmg_thr;
-    if (__ballot(!fb) != 0) sur_forward_wave(pk, x, y);         // uniform across the wave
+    if (__ballot(!fb && !el) != 0) sur_forward_wave(pk, x, y);  // uniform across the wave
+    if (el) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) sg[k] = sel[k];
+        changed = false;
+        exact = 2;
+        return;
+    }
     R rs[4], ss[6];
     if (!fb) {
 #pragma unroll
@@ -722,8 +741,8 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                         if (changed) store_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * lidx), r);
                         acc[T_UEL] += (double)uel;
                         if (P.law == 2) {
-                            acc[T_AUX] += (double)exact;
-                            acc[T_SURN] += 1.0;
+                            acc[T_AUX] += exact == 1 ? 1.0 : 0.0;      // fallback after consulting the network
+                            acc[T_SURN] += exact != 2 ? 1.0 : 0.0;     // network consulted
                         }
                     }
                 }

@@ -66,8 +66,8 @@ struct DevGlobals {
     double half_int, mz0;            // opening half of the current interval; initial sum m d_z
     double ws_acc, wgs_acc;          // striker works up to the current striker level
     int64_t reset_passes, released, max_passes, active;
-    double fallback_gp;              // surrogate: GP updates that used the exact law
-    double sur_gp;                   // surrogate: GP updates of surrogate plies
+    double fallback_gp;              // surrogate: consulted GP updates that the exact law produced
+    double sur_gp;                   // surrogate: GP updates on which the network was consulted
     unsigned int pad1;
 };
 

@@ -94,44 +94,67 @@ __device__ __forceinline__ R cdm_max_damage(const PlyC<R> &P, R lc, R YT, R YC, 
     return rmax(d, damage_exp(r[2], SL, P.G12v, P.GSL, lc));
 }
 
+// Undamaged stress s = C0 e, and the screen: true when the point is provably
+// elastic for the law, i.e. its thresholds are all at 1 and upper bounds of
+// its loading functions (without roots) show that none can exceed them.  The
+// law then returns s and leaves the thresholds unchanged, exactly as its full
+// evaluation would.  Elements above vol_nocap have crack-band capped matrix
+// strengths: with CAPPED the same bounds then use the capped values (a cube
+// root, three caps and four divisions per point), without it such points are
+// not screened.
+template <bool CAPPED, typename R>
+__device__ __forceinline__ bool cdm_screen(const PlyC<R> &P, R vol, const R e[6], const R r[4], R s[6])
+{
+    s[0] = P.C11 * e[0] + P.C12 * e[1] + P.C13 * e[2];
+    s[1] = P.C12 * e[0] + P.C22 * e[1] + P.C23 * e[2];
+    s[2] = P.C13 * e[0] + P.C23 * e[1] + P.C33 * e[2];
+    s[3] = P.G23 * e[3]; s[4] = P.G13 * e[4]; s[5] = P.G12 * e[5];
+    // 1/Y_T, 1/S_L, 1/S_T and eta_L of the element
+    R iYT = P.iYT, iSL = P.iSL, iST = P.iST, etaL = P.etaL0;
+    if (vol > P.vol_nocap) {
+        if constexpr (!CAPPED) return false;
+        const R lc = cbrt(vol);
+        const R YT = cap_strength(P.YT, P.E2, P.GYT, lc);
+        const R YC = cap_strength(P.YC, P.E2, P.GYC, lc);
+        const R SL = cap_strength(P.SL, P.G12v, P.GSL, lc);
+        iYT = R(1) / YT;
+        iSL = R(1) / SL;
+        iST = R(1) / (P.kST * YC);
+        etaL = P.kEtaL * SL / YC;
+    }
+    // with CAPPED the bounds carry a relative margin, so that a point the
+    // screen passes stays below onset in the law's own rounding as well
+    constexpr R mg = CAPPED ? R(1.00001) : R(1);
+    const R s1 = s[1];
+    const R t2 = s[5] * s[5] + s[4] * s[4];              // tau_L^2
+    bool grow = rmax(e[0], R(0)) * P.kE1XT * mg > r[0] || rmax(-e[0], R(0)) * P.kE1XC * mg > r[1];
+    if (s1 >= R(0)) {
+        const R a = s1 * iYT;
+        grow |= (a * a + t2 * iSL * iSL) * mg > r[2] * r[2];
+    } else {
+        const R el = etaL * s1;                          // eta_L sigma22
+        const R qL = el > R(0) ? R(2) * (t2 + el * el) : t2;
+        grow |= qL * iSL * iSL * mg > r[2] * r[2];
+        const R bT = -s1 * P.kT * iST;
+        const R elc = el * P.ca0;
+        const R qL2 = R(2) * P.ca0 * P.ca0 * (t2 + elc * elc);
+        grow |= (bT * bT + qL2 * iSL * iSL) * mg > r[3] * r[3];
+    }
+    return !grow && r[0] <= R(1) && r[1] <= R(1) && r[2] <= R(1) && r[3] <= R(1);
+}
+
 // eps: material-frame Green strain (Voigt 11,22,33,23,13,12, engineering shear)
 // r: thresholds r1+, r1-, r2+, r2- (in/out).  Returns nominal PK2 stress.
 template <typename R>
 __device__ void cdm_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6], bool &changed)
 {
-    R s0 = P.C11 * e[0] + P.C12 * e[1] + P.C13 * e[2];
-    R s1 = P.C12 * e[0] + P.C22 * e[1] + P.C23 * e[2];
-    R s2 = P.C13 * e[0] + P.C23 * e[1] + P.C33 * e[2];
-    R s3 = P.G23 * e[3], s4 = P.G13 * e[4], s5 = P.G12 * e[5];
     changed = false;
-    if (P.law == 0) {
+    R sc[6];
+    const bool elastic = cdm_screen<false>(P, vol, e, r, sc);
+    const R s0 = sc[0], s1 = sc[1], s2 = sc[2], s3 = sc[3], s4 = sc[4], s5 = sc[5];
+    if (P.law == 0 || elastic) {
         sg[0] = s0; sg[1] = s1; sg[2] = s2; sg[3] = s3; sg[4] = s4; sg[5] = s5;
         return;
-    }
-    if (vol <= P.vol_nocap) {
-        // Screen: upper bounds of the loading functions without roots or
-        // divisions.  When none can exceed its threshold the thresholds keep
-        // their values, exactly as the full evaluation below would leave them.
-        const R t2 = s5 * s5 + s4 * s4;                  // tau_L^2
-        bool grow = rmax(e[0], R(0)) * P.kE1XT > r[0] || rmax(-e[0], R(0)) * P.kE1XC > r[1];
-        if (s1 >= R(0)) {
-            const R a = s1 * P.iYT;
-            grow |= a * a + t2 * P.iSL * P.iSL > r[2] * r[2];
-        } else {
-            const R el = P.etaL0 * s1;                   // eta_L sigma22
-            const R qL = el > R(0) ? R(2) * (t2 + el * el) : t2;
-            grow |= qL * P.iSL * P.iSL > r[2] * r[2];
-            const R bT = -s1 * P.kT * P.iST;
-            const R elc = el * P.ca0;
-            const R qL2 = R(2) * P.ca0 * P.ca0 * (t2 + elc * elc);
-            grow |= bT * bT + qL2 * P.iSL * P.iSL > r[3] * r[3];
-        }
-        if (!grow) {
-            if (r[0] <= R(1) && r[1] <= R(1) && r[2] <= R(1) && r[3] <= R(1)) {
-                sg[0] = s0; sg[1] = s1; sg[2] = s2; sg[3] = s3; sg[4] = s4; sg[5] = s5;
-                return;
-            }
-        }
     }
     const R lc = cbrt(vol);                              // crack-band length
     const R YT = cap_strength(P.YT, P.E2, P.GYT, lc);

@@ -133,7 +133,9 @@ def test_surrogate_path_matches_fp64_oracle():
     n_o, n_g = int((ro.max(axis=1) > 1).sum()), int((rg.max(axis=1) > 1).sum())
     assert n_o > 10 and abs(n_g - n_o) <= 0.02 * n_o + 1
     assert 0.0 <= info["fallback_fraction"] <= 1.0
-    print(f"[surrogate] fallback fraction {info['fallback_fraction']:.4f}, peak force {fg.max():.3f} "
+    assert info["sur_consulted"] > 0                            # the network is exercised
+    print(f"[surrogate] consulted {info['sur_consulted']:.0f} GP updates, "
+          f"fallback fraction {info['fallback_fraction']:.4f}, peak force {fg.max():.3f} "
           f"vs {fo.max():.3f}", flush=True)
 
 
@@ -152,4 +154,28 @@ def test_surrogate_with_zero_tolerance_is_the_exact_law():
     assert np.array_equal(a.array_get(pdn.ARR_DISP), b.array_get(pdn.ARR_DISP))
     assert np.array_equal(a.array_get(pdn.ARR_GP_R), b.array_get(pdn.ARR_GP_R))
     assert b.info()["fallback_fraction"] == 1.0
+    assert rel(a.contact_force()[1], b.contact_force()[1]) == 0.0
+
+
+def test_screened_points_never_reach_the_network():
+    """Points that the law's screen proves elastic take the law's answer without
+    the network.  A gentle impact that stays below damage onset, stepped with an
+    untrained network accepted everywhere (residual bar 1e9), must consult the
+    network on no point and step bit for bit like the plain law."""
+    _note("surrogate screen: elastic impact never consults the network")
+    cfg = W.tiny(12, 12, 4, 1, angles=[0, 90, 0, 90], law=W.LAW_CDM, lx=12e-3, ly=12e-3,
+                 ply_thickness=0.5e-3, v0=0.5, mass=0.02, R=4e-3, precision=W.PREC_MIXED)
+    cfg["impactor"]["gap"] = 1e-7
+    w = _noisy_weights(11)
+    a = pdn.Simulation(cfg)
+    b = pdn.Simulation(cfg)
+    for p in range(len(cfg["materials"])):
+        b.surrogate_set(p, w, 1.0, 1e9)
+    a.step(300)
+    b.step(300)
+    assert a.contact_force()[1].max() > 0                      # the striker is in contact
+    assert np.all(a.array_get(pdn.ARR_GP_R) == 1.0)            # and the plate undamaged
+    assert b.info()["sur_consulted"] == 0.0
+    assert np.array_equal(a.array_get(pdn.ARR_DISP), b.array_get(pdn.ARR_DISP))
+    assert np.array_equal(a.array_get(pdn.ARR_GP_R), b.array_get(pdn.ARR_GP_R))
     assert rel(a.contact_force()[1], b.contact_force()[1]) == 0.0
