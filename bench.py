@@ -125,6 +125,12 @@ def batched_leg(steps: int, warmup: int, stream) -> dict:
     import workloads as W
     cfgs = W.batch_cases_64()
     sims = [pdn.Simulation(c, stream=stream) for c in cfgs]
+    # algorithmic bytes of one step of every case (as for the headline kernel):
+    # d and v read and written in FP64, four FP32 thresholds per GP, one per pair
+    nbytes = 0
+    for s_ in sims:
+        i_ = s_.info()
+        nbytes += 96 * i_["n_nodes"] + 32 * i_["n_bulk"] + 8 * i_["n_pairs"]
     t0 = time.perf_counter()
     b = pdn.Batch(sims)
     setup = time.perf_counter() - t0
@@ -144,7 +150,12 @@ def batched_leg(steps: int, warmup: int, stream) -> dict:
             "cases": len(cfgs), "bulk_gauss_points": ne, "value": ne * steps / el, "unit": "GP-updates/s",
             "steps": steps, "warmup": warmup, "ms_per_step": 1e3 * el / steps,
             "tile": f"{info['tile'][0]}x{info['tile'][1]}", "blocks_per_launch": info["blocks"],
-            "create_and_autotune_s": setup}
+            "create_and_autotune_s": setup,
+            # over the whole step (element/node and books launches, graph replay):
+            # a lower bound on the element/node kernel's rate
+            "roofline": {"bound": "hbm", "achieved": nbytes / (el / steps) / 1e9, "peak": 8000.0,
+                         "unit": "GB/s", "frac": nbytes / (el / steps) / 8e12, "timing": "whole step",
+                         "algorithmic_bytes_per_step": nbytes}}
 
 
 def full_integration_leg(stream, pre, warmup, steps, plain_ms) -> dict:

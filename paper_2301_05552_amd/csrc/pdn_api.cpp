@@ -1191,7 +1191,10 @@ struct pdn_batch {
     // 3 x n element-pass arguments: steps of parity 0 and 1 (contact pass), and
     // a restart pass of the current state (no contact) for the autotuner
     void *eargs_d = nullptr;
+    // block offsets of the cases (n + 1), then per block its case and its
+    // tile within the case (eblocks each)
     int *estart_d = nullptr;
+    size_t estart_cap = 0;               // ints allocated at estart_d
     std::vector<int> estart;
     std::vector<unsigned char> eargs_h;
     int eblocks = 0;
@@ -1199,6 +1202,7 @@ struct pdn_batch {
     hipGraphExec_t exec = nullptr;       // PDN_BATCH_GRAPH_STEPS steps, built for (tile, sur, eblocks)
     int graph_tile = -1, graph_eblocks = 0;
     bool graph_sur = false;
+    const int *graph_estart = nullptr;   // block table the graph's launches read
 };
 
 #define PDN_BATCH_GRAPH_STEPS 8          // even: a replay returns every case to the same buffer parity
@@ -1295,16 +1299,40 @@ int upload_tables(pdn_batch *b)
     b->estart.assign(n + 1, 0);
     for (size_t i = 0; i < n; ++i) b->estart[i + 1] = b->estart[i] + b->cs[i]->nblocks;
     b->eblocks = b->estart[n];
+    // Dispatch order of the blocks.  The hardware deals blocks round-robin to
+    // the 8 XCDs, and xcd_tile hands each XCD a contiguous eighth of this list.
+    // Every eighth holds the same band of every case's tiles, so the XCDs get
+    // equal work although the cases differ in thickness (a block's time grows
+    // with its layers); within a band a case's tiles stay contiguous, so
+    // neighbouring tiles share an L2.
+    b->estart.resize(n + 1 + 2 * (size_t)b->eblocks);
+    int *bcase = b->estart.data() + n + 1, *btile = bcase + b->eblocks;
+    size_t k = 0;
+    for (int x = 0; x < 8; ++x)
+        for (size_t i = 0; i < n; ++i) {
+            const int nb = b->cs[i]->nblocks;
+            for (int t = (int)((int64_t)nb * x / 8); t < (int)((int64_t)nb * (x + 1) / 8); ++t) {
+                bcase[k] = (int)i;
+                btile[k] = t;
+                ++k;
+            }
+        }
+    if (k != (size_t)b->eblocks) return berr(b, PDN_EDEVICE, "block table: %zu of %d blocks", k, b->eblocks);
     b->sur = false;
     for (pdn_ctx *c : b->cs) b->sur = b->sur || c->use_sur;
     if (b->precision == PDN_MIXED) fill_eargs<float>(b);
     else fill_eargs<double>(b);
-    if (!b->eargs_d) {
-        BHIPCHK(b, hipMalloc(&b->eargs_d, b->eargs_h.size()));
-        BHIPCHK(b, hipMalloc((void **)&b->estart_d, (n + 1) * sizeof(int)));
+    if (!b->eargs_d) BHIPCHK(b, hipMalloc(&b->eargs_d, b->eargs_h.size()));
+    if (b->estart.size() > b->estart_cap) {                // the block count depends on the tile
+        BHIPCHK(b, hipStreamSynchronize(b->stream));
+        if (b->estart_d) BHIPCHK(b, hipFree(b->estart_d));
+        b->estart_d = nullptr;
+        BHIPCHK(b, hipMalloc((void **)&b->estart_d, b->estart.size() * sizeof(int)));
+        b->estart_cap = b->estart.size();
     }
     BHIPCHK(b, hipMemcpyAsync(b->eargs_d, b->eargs_h.data(), b->eargs_h.size(), hipMemcpyHostToDevice, b->stream));
-    BHIPCHK(b, hipMemcpyAsync(b->estart_d, b->estart.data(), (n + 1) * sizeof(int), hipMemcpyHostToDevice, b->stream));
+    BHIPCHK(b, hipMemcpyAsync(b->estart_d, b->estart.data(), b->estart.size() * sizeof(int), hipMemcpyHostToDevice,
+                              b->stream));
     BHIPCHK(b, hipStreamSynchronize(b->stream));          // host tables are reused
     return PDN_OK;
 }
@@ -1383,6 +1411,7 @@ int build_graph(pdn_batch *b)
     b->graph_tile = b->tile;
     b->graph_sur = b->sur;
     b->graph_eblocks = b->eblocks;
+    b->graph_estart = b->estart_d;
     return PDN_OK;
 }
 
@@ -1493,7 +1522,8 @@ int pdn_batch_step(pdn_batch *b, int64_t n)
         (void)hipStreamSynchronize(c->stream);
     }
     if ((rc = upload_tables(b))) return rc;
-    if (b->graph_tile != b->tile || b->graph_sur != b->sur || b->graph_eblocks != b->eblocks)
+    if (b->graph_tile != b->tile || b->graph_sur != b->sur || b->graph_eblocks != b->eblocks ||
+        b->graph_estart != b->estart_d)
         if ((rc = build_graph(b))) return rc;
     int64_t s = 0;
     for (; s + PDN_BATCH_GRAPH_STEPS <= n; s += PDN_BATCH_GRAPH_STEPS)

@@ -877,28 +877,18 @@ void k_elem_node(ElemArgs<R> A)
     elem_node_tile<R, TX, TY, SUR, NGP>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
-// case of global block b in a batch: the last c with start[c] <= b
-__device__ __forceinline__ int batch_case(const int *start, int ncase, int b)
-{
-    int lo = 0, hi = ncase - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (start[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
-
-// many plates in one launch: tiles of case c are blocks start[c] .. start[c+1)-1
-// (after the XCD remap, so that one case's neighbouring tiles share an L2)
+// many plates in one launch: case c has start[c+1] - start[c] tiles.  After
+// the ncase + 1 offsets, the table holds for each block (after the XCD remap)
+// its case and its tile within the case (gridDim.x entries each), in the
+// order the host chose: one lookup per block.
 template <typename R, int TX, int TY, bool SUR, int NGP = 1>
 __global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
 void k_elem_node_batch(const ElemArgs<R> *__restrict__ args, const int *__restrict__ start, int ncase)
 {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
-    const int c = batch_case(start, ncase, b);
-    const ElemArgs<R> A = args[c];
-    elem_node_tile<R, TX, TY, SUR, NGP>(A, b - start[c]);
+    const int *bcase = start + ncase + 1, *btile = bcase + gridDim.x;
+    const ElemArgs<R> A = args[bcase[b]];
+    elem_node_tile<R, TX, TY, SUR, NGP>(A, btile[b]);
 }
 
 #define PDN_BOOKS_THREADS 256
