@@ -379,16 +379,47 @@ __device__ __forceinline__ int books_stage_rows(int nblk) { return rmax(1, rmin(
 
 // Sum of acc over the workgroup, deterministic (fixed shuffle tree per wave,
 // waves in order); the NTM totals land in out[0], out[stride], ... from threads 0..NTM-1.
+// value of lane l' under a DPP lane pattern (both words of a double)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_update_dpp(0, w.x, CTRL, 0xF, 0xF, true);
+    r.y = __builtin_amdgcn_update_dpp(0, w.y, CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, r);
+}
+
+__device__ __forceinline__ double lane_f64(double v, int l)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    int2 r;
+    r.x = __builtin_amdgcn_readlane(w.x, l);
+    r.y = __builtin_amdgcn_readlane(w.y, l);
+    return __builtin_bit_cast(double, r);
+}
+
+// sum over the 64 lanes of a wave in a fixed order: pairs, quads, half rows
+// and rows of 16 lanes by DPP lane patterns (commutative steps, so every lane
+// of a row holds the same row sum), then the four row sums in order
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);                   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);                   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);                  // row_half_mirror
+    v += dpp_f64<0x140>(v);                  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
+}
+
 template <int NT, int NTM = PDN_NTERMS>
 __device__ void block_reduce_store(const double *acc, double *out, int stride, double *sh)
 {
-    // deterministic: fixed shuffle tree inside each wave, waves summed in order
+    // deterministic: fixed lane pattern inside each wave, waves summed in order
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int NW = NT / 64;
 #pragma unroll
     for (int k = 0; k < NTM; ++k) {
-        double v = acc[k];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        const double v = wave_sum(acc[k]);
         if (lane == 0) sh[k * NW + wave] = v;
     }
     __syncthreads();
@@ -852,7 +883,21 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             A.fside[3 * ci + 2] = carry[2];
         }
     }
-    block_reduce_store<NT>(acc, A.partials + tile, A.prow, red);
+    // Block partials: the element terms from every tile; the contact terms only
+    // from the tiles whose contact terms the books read (those around the
+    // candidate window, in a contact pass); the surrogate counters are zero
+    // unless the surrogate is built in.
+    if (A.contact && tx >= A.wt0 && tx < A.wt1 && ty >= A.wu0 && ty < A.wu1) {
+        block_reduce_store<NT>(acc, A.partials + tile, A.prow, red);
+    } else if constexpr (SUR) {
+        block_reduce_store<NT, T_FC>(acc, A.partials + tile, A.prow, red);
+    } else {
+        block_reduce_store<NT, T_AUX>(acc, A.partials + tile, A.prow, red);
+        if (t == 0) {
+            A.partials[tile + (int64_t)T_AUX * A.prow] = 0.0;
+            A.partials[tile + (int64_t)T_SURN * A.prow] = 0.0;
+        }
+    }
     // first stage of the books of this pass: the element terms of the
     // previous pass over a contiguous range of its tiles
     const int nblk = A.tiles_x * A.tiles_y, ns = books_stage_rows(nblk);
