@@ -36,7 +36,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gauss-point updates/s per explicit step; plain vs surrogate at \u22640.5% force error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_elem_node_plate1200x800x16_traffic.txt")
-KERNEL_SOURCES = ("paper_2301_05552_amd/csrc/pdn_kernels.hip", "paper_2301_05552_amd/csrc/pdn_internal.h")
+# every source the element/node kernel is compiled from: the counter summary
+# is used only while they are unchanged
+KERNEL_SOURCES = tuple(f"paper_2301_05552_amd/csrc/{f}" for f in (
+    "pdn_kernels.hip", "pdn_elem.h", "pdn_law.h", "pdn_mlp.h", "pdn_internal.h", "pdn_launch.h"))
 
 
 def log(msg):

@@ -33,3 +33,22 @@ def test_multi_gpu_request_exits(monkeypatch, capsys):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().out
+
+
+def test_kernel_hash_covers_every_source_of_the_element_kernel():
+    """The traffic summary is tied to the element/node kernel's sources: the
+    hash must cover every local file pdn_kernels.hip includes, transitively."""
+    import re
+    csrc = os.path.join(ROOT, "paper_2301_05552_amd", "csrc")
+    seen, todo = set(), ["pdn_kernels.hip"]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        with open(os.path.join(csrc, f)) as fh:
+            for m in re.finditer(r'^\s*#include\s+"([^"]+)"', fh.read(), re.M):
+                if os.path.exists(os.path.join(csrc, m.group(1))):
+                    todo.append(m.group(1))
+    hashed = {os.path.basename(p) for p in bench.KERNEL_SOURCES}
+    assert seen <= hashed, sorted(seen - hashed)
