@@ -377,9 +377,7 @@ __device__ __forceinline__ void store_xyz(double *p, const double (&v)[3])
 // stage rows of the books reduction: 64 or more tiles each, at most PDN_STAGE
 __device__ __forceinline__ int books_stage_rows(int nblk) { return rmax(1, rmin(PDN_STAGE, nblk / 64)); }
 
-// Sum of acc over the workgroup, deterministic (fixed shuffle tree per wave,
-// waves in order); the NTM totals land in out[0], out[stride], ... from threads 0..NTM-1.
-// value of lane l' under a DPP lane pattern (both words of a double)
+// a double moved between lanes by a DPP lane pattern (both words alike)
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v)
 {
@@ -390,6 +388,7 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __builtin_bit_cast(double, r);
 }
 
+// a double of lane l, uniform
 __device__ __forceinline__ double lane_f64(double v, int l)
 {
     const int2 w = __builtin_bit_cast(int2, v);
@@ -411,6 +410,8 @@ __device__ __forceinline__ double wave_sum(double v)
     return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
 }
 
+// Sum of acc over the workgroup, deterministic (fixed lane pattern per wave,
+// waves in order); the NTM totals land in out[0], out[stride], ... from threads 0..NTM-1.
 template <int NT, int NTM = PDN_NTERMS>
 __device__ void block_reduce_store(const double *acc, double *out, int stride, double *sh)
 {
