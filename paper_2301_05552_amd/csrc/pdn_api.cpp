@@ -209,6 +209,14 @@ PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1)
     P.Ksh = (R)ksh;
     P.tauI = (R)m.tauI; P.GIc = (R)m.GIc; P.GIIc = (R)m.GIIc; P.eta_bk = (R)m.eta_bk;
     P.GIo = (R)(m.KI > 0 ? m.tauI * m.tauI / (2 * m.KI) : 0.0);
+    // An undamaged pair below the smallest onset opening over all mode
+    // mixities stays undamaged: lambda <= lambda_o(B) for every B when
+    // Ksh |d_sh|^2 + KI <d3>^2 <= 2 GIo min(GIc, GIIc) / GIc (a relative margin
+    // of 1e-5 covers the rounding of the law's own evaluation).  It needs
+    // GIc > GIo (lambda_c > lambda_o); otherwise no pair is screened.
+    const double gio = m.KI > 0 ? m.tauI * m.tauI / (2 * m.KI) : 0.0;
+    P.den_onset = (R)(m.KI > 0 && m.GIc > gio && m.GIIc > 0
+                          ? 2.0 * gio * std::min(m.GIc, m.GIIc) / m.GIc * (1.0 - 1e-5) : -1.0);
     return P;
 }
 

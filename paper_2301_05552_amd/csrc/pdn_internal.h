@@ -40,6 +40,7 @@ struct PlyC {
     R vol_nocap;                                     // element volume below which no strength is capped
     // interface on top of this ply
     R KI, Ksh, tauI, GIc, GIIc, eta_bk, GIo;
+    R den_onset;                                     // screen of the cohesive law: below onset at any mixity
 };
 
 // Layer table: layer l joins node planes l and l+1.

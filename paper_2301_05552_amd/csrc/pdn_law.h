@@ -201,6 +201,16 @@ __device__ R czm_update(const PlyC<R> &P, R d1, R d2, R d3, R &rd, R tau[3], boo
     R sh2 = d1 * d1 + d2 * d2;
     R d3p = rmax(d3, R(0));
     R den = P.Ksh * sh2 + P.KI * d3p * d3p;
+    // screen: an undamaged pair whose opening is below onset at every mode
+    // mixity keeps D = 0, which is what the evaluation below gives for it
+    // (with D = 0 the tractions are K d exactly)
+    if (rd == R(0) && den <= P.den_onset) {
+        changed = false;
+        tau[0] = P.Ksh * d1;
+        tau[1] = P.Ksh * d2;
+        tau[2] = P.KI * d3;
+        return R(0);
+    }
     R B = den > R(0) ? P.Ksh * sh2 / den : R(0);
     R KB = (R(1) - B) * P.KI + B * P.Ksh;
     R lam = sqrt(den / KB);

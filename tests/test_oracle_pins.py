@@ -613,6 +613,34 @@ def test_czm_mixed_mode_bk_toughness(a, b):
     assert abs(work - Gc) <= 2e-4 * Gc
 
 
+def test_czm_no_onset_below_the_smallest_onset_opening():
+    """An undamaged pair with Ksh |d_sh|^2 + KI <d3>^2 <= 2 GIo min(GIc, GIIc) / GIc
+    (GIo = tau_I^2 / 2 KI) is below onset at every mode mixity: the law leaves it
+    undamaged with tractions K d (the bound the GPU's cohesive screen uses).
+    Just above the bound, the mixity with the smallest toughness starts to
+    damage, so the bound is the tightest of its form."""
+    m = W.material_cfrp(True, 0.5e-3)
+    KI = m["KI"]
+    Ksh = KI * (m["GIc"] / m["GIIc"]) * (m["tauII"] / m["tauI"]) ** 2
+    GIo = m["tauI"] ** 2 / (2 * KI)
+    bound = 2 * GIo * min(m["GIc"], m["GIIc"]) / m["GIc"]
+    rs = np.random.default_rng(17)
+    for _ in range(400):
+        n = rs.standard_normal(3)
+        n /= np.linalg.norm(n)
+        den1 = Ksh * (n[0] ** 2 + n[1] ** 2) + KI * max(n[2], 0.0) ** 2
+        if den1 <= 0:
+            continue
+        d = n * math.sqrt(bound * (1 - 1e-6) / den1)
+        tau, r, D = oracle.czm(m, d, 0.0)
+        assert r == 0.0 and D == 0.0
+        assert np.allclose(tau, [Ksh * d[0], Ksh * d[1], KI * d[2]], rtol=1e-14, atol=0)
+    # the mixity of smallest toughness (pure mode I here: GIc < GIIc) damages just above it
+    assert m["GIc"] < m["GIIc"]
+    tau, r, D = oracle.czm(m, [0.0, 0.0, math.sqrt(bound * 1.001 / KI)], 0.0)
+    assert r > 0.0
+
+
 def test_czm_compression_is_penalty_contact():
     m = W.material_cfrp(True, 0.5e-3)
     tau, r, D = oracle.czm(m, [0, 0, 1.0], 0.0)            # fully broken in tension
