@@ -520,11 +520,14 @@ __device__ void contact_books(const ElemArgs<R> &A, double *sh)
 template <typename R, int TX, int TY, bool SUR, int NGP>
 __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int tile)
 {
-    constexpr int NE = TX * TY, NCX = TX + 1, NCY = TY + 1, NC = NCX * NCY;
+    // element slots follow the node rows: element (a, b) is slot a + NCX b,
+    // the thread whose node is the element's corner 0 (the last slot of a row
+    // has no element), so that a wave's LDS accesses are consecutive words
+    constexpr int NCX = TX + 1, NCY = TY + 1, NC = NCX * NCY, NE = NCX * TY;
     constexpr int NT = PDN_TILE_THREADS(TX, TY);
     constexpr bool F32 = sizeof(R) == 4;
     __shared__ R Ubuf[F32 ? 2 : 1][3][F32 ? NC : 1];   // node planes k-1, k in FP32
-    __shared__ R Fs[2][4][3][NE];           // element corner forces: [bottom/top][corner][xyz]
+    __shared__ R Fs[2][4][3][NE];           // element corner forces: [bottom/top][corner][xyz][slot]
     __shared__ double D64[2][3][NC];        // FP64 displacement of planes k-1, k
     __shared__ double V64[2][3][NC];        // FP64 velocity of planes k-1, k (own slot)
     __shared__ double red[PDN_NTERMS * (NT / 64)];
@@ -540,9 +543,9 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     const int64_t plane = (int64_t)(nx + 1) * (ny + 1);
 
     // element role: one element column per thread; ewave: the thread's wave has some
-    const bool erole = t < NE;
+    const int ea = t % NCX, eb = t / NCX;
+    const bool erole = t < NE && ea < TX;
     const bool ewave = (t & ~63) < NE;
-    const int ea = t % TX, eb = t / TX;
     const int ie = e0x + ea, je = e0y + eb;
     const bool evalid = erole && ie < nx && je < ny;
     const bool eown = evalid && (ea < TX - 1 || lastx) && (eb < TY - 1 || lasty);
@@ -799,22 +802,22 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                 // one layer are summed in the element type, in this order
                 R fb[3] = {R(0), R(0), R(0)}, ft[3] = {R(0), R(0), R(0)};
                 if (np < TX && nq < TY) {
-                    const int e = np + TX * nq;
+                    const int e = np + NCX * nq;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][0][c][e]; ft[c] += Fs[1][0][c][e]; }
                 }
                 if (np >= 1 && nq < TY) {
-                    const int e = np - 1 + TX * nq;
+                    const int e = np - 1 + NCX * nq;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][1][c][e]; ft[c] += Fs[1][1][c][e]; }
                 }
                 if (np >= 1 && nq >= 1) {
-                    const int e = np - 1 + TX * (nq - 1);
+                    const int e = np - 1 + NCX * (nq - 1);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][2][c][e]; ft[c] += Fs[1][2][c][e]; }
                 }
                 if (np < TX && nq >= 1) {
-                    const int e = np + TX * (nq - 1);
+                    const int e = np + NCX * (nq - 1);
 #pragma unroll
                     for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][3][c][e]; ft[c] += Fs[1][3][c][e]; }
                 }
