@@ -7,6 +7,8 @@
 #include "pdn_law.h"
 #include "pdn_mlp.h"
 
+#include <type_traits>
+
 namespace pdn {
 
 // ---------------------------------------------------------------------------
@@ -526,14 +528,9 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     constexpr int NCX = TX + 1, NCY = TY + 1, NC = NCX * NCY, NE = NCX * TY;
     constexpr int NT = PDN_TILE_THREADS(TX, TY);
     constexpr bool F32 = sizeof(R) == 4;
-    __shared__ R Ubuf[F32 ? 2 : 1][3][F32 ? NC : 1];   // node planes k-1, k in FP32
+    __shared__ R U[2][3][NC];               // node planes k-1, k in the element type (slot k & 1)
     __shared__ R Fs[2][4][3][NE];           // element corner forces: [bottom/top][corner][xyz][slot]
-    __shared__ double D64[2][3][NC];        // FP64 displacement of planes k-1, k
-    __shared__ double V64[2][3][NC];        // FP64 velocity of planes k-1, k (own slot)
     __shared__ double red[PDN_NTERMS * (NT / 64)];
-    // element-type plane copy: the FP64 staging itself when R is double
-    R (*U)[3][NC] = F32 ? reinterpret_cast<R (*)[3][NC]>(&Ubuf[0][0][0])
-                        : reinterpret_cast<R (*)[3][NC]>(&D64[0][0][0]);
 
     const int t = threadIdx.x;
     const int tx = tile % A.tiles_x, ty = tile / A.tiles_x;
@@ -590,20 +587,23 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         load_xyz(A.d_in + 3 * nk, pd);
         load_xyz(A.v_in + 3 * nv, pv);
     };
-    auto stage_plane = [&](int k, const double (&pd)[3], const double (&pv)[3]) {
+    // FP64 displacement and velocity of the thread's own node in the last two
+    // staged planes, in registers: slot S of a call site is a compile-time
+    // parity (the loop is unrolled by two), so the arrays stay in registers
+    double sd[2][3] = {{0, 0, 0}, {0, 0, 0}}, sv[2][3] = {{0, 0, 0}, {0, 0, 0}};
+    auto stage_plane = [&](auto S, int k, const double (&pd)[3], const double (&pv)[3]) {
+        constexpr int s = decltype(S)::value;
         const int p = k & 1;
         if (nvalid) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                D64[p][c][t] = pd[c];
-                if (F32) U[p][c][t] = (R)pd[c];
-            }
-            if (nown) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) V64[p][c][t] = pv[c];
-            }
+            for (int c = 0; c < 3; ++c) U[p][c][t] = (R)pd[c];
         } else if (nrole) {
             U[p][0][t] = U[p][1][t] = U[p][2][t] = R(0);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            sd[s][c] = pd[c];
+            sv[s][c] = pv[c];
         }
     };
     // damage thresholds of the element in layer l, fetched one layer ahead
@@ -628,18 +628,18 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     // (read once; the loop then needs neither the flag nor the table)
     const int fix_lat = (A.clamp_lateral && (gi == 0 || gi == nx || gj == 0 || gj == ny)) ? 7 : 0;
     const int fix_bot = fix_lat | (nvalid ? (int)A.bc_bottom[col] : 0);
-    auto update_node = [&](int kp, const double f[3]) {
-        const int p = kp & 1;
+    auto update_node = [&](auto S, int kp, const double f[3]) {
+        constexpr int s = decltype(S)::value;
         const int64_t n = col + plane * kp;
         const int bits = kp == 0 ? fix_bot : fix_lat;
         const double m = mxy * cload(A.mz + kp);
         const double im = imxy * cload(A.imz + kp);
         const double dt = A.dt, g = A.grav;
-        acc[T_MZ] += m * D64[p][2][t];         // gravity work = -g (sum m d_z - its initial value)
+        acc[T_MZ] += m * sd[s][2];             // gravity work = -g (sum m d_z - its initial value)
         double dn[3], vn[3], vvn = 0.0, vf = 0.0, vnf = 0.0;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const double d = D64[p][c][t], v = V64[p][c][t];
+            const double d = sd[s][c], v = sv[s][c];
             const bool fx = (bits >> c) & 1;
             const double fe = c == 2 ? -m * g : 0.0;
             const double a = fx ? 0.0 : (fe - f[c]) * im;
@@ -732,11 +732,14 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     };
 
     // layer k-1 (between node planes k-1 and k), then the update of plane k-1
-    auto layer_step = [&](int k, double (&pd)[3], double (&pv)[3]) {
+    // S: register slot of plane k (plane k - 1 is in the other one)
+    auto layer_step = [&](auto S, int k, double (&pd)[3], double (&pv)[3]) {
+        constexpr int s = decltype(S)::value;
+        const std::integral_constant<int, 1 - s> S1{};
         const LayerInfo Lk = cload(A.layers + (k - 1));
         const int ltype = uni(Lk.type), lply = uni(Lk.ply), lidx = uni(Lk.index);
         const R lhz = (R)uni(Lk.hz), lihz = (R)uni(Lk.ihz);
-        stage_plane(k, pd, pv);
+        stage_plane(S, k, pd, pv);
         R r[4] = {rn[0], rn[1], rn[2], rn[3]};
         const R rdl = rdn;
         // thresholds first: the wait for them next layer then leaves the plane
@@ -830,13 +833,12 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             // one state and the summed tributary area
             const PlyC<R> P = cload(A.ply + lply);
             const int64_t pi = col + plane * lidx;
-            const int pb = (k - 1) & 1, pt = k & 1;
             R rd = rdl;                              // fetched one layer ahead
             R tau[3];
             bool changed;
-            const R d1 = (R)(D64[pt][0][t] - D64[pb][0][t]);
-            const R d2 = (R)(D64[pt][1][t] - D64[pb][1][t]);
-            const R d3 = (R)(D64[pt][2][t] - D64[pb][2][t]);
+            const R d1 = (R)(sd[s][0] - sd[1 - s][0]);
+            const R d2 = (R)(sd[s][1] - sd[1 - s][1]);
+            const R d3 = (R)(sd[s][2] - sd[1 - s][2]);
             czm_update(P, d1, d2, d3, rd, tau, changed);
             if (changed) A.rd[pi] = rd;
             const double ap = mxy;                   // (sum of adjacent widths / 2)(... / 2)
@@ -848,11 +850,13 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             }
             acc[T_UEL] += 0.5 * ap * (double)(tau[0] * d1 + tau[1] * d2 + tau[2] * d3);
         }
-        if (nown) update_node(k - 1, fin);
+        if (nown) update_node(S1, k - 1, fin);
     };
+    const std::integral_constant<int, 0> S0{};
+    const std::integral_constant<int, 1> S1{};
 
     fetch_plane(0, pdA, pvA);
-    stage_plane(0, pdA, pvA);
+    stage_plane(S0, 0, pdA, pvA);
     fetch_plane(1, pdB, pvB);
     fetch_plane(2, pdA, pvA);
     fetch_r(0);
@@ -861,11 +865,11 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     const int top = A.K - 1;
     int k = 1;
     for (; k + 1 < top; k += 2) {
-        layer_step(k, pdB, pvB);
-        layer_step(k + 1, pdA, pvA);
+        layer_step(S1, k, pdB, pvB);
+        layer_step(S0, k + 1, pdA, pvA);
     }
     if (k < top) {
-        layer_step(k, pdB, pvB);
+        layer_step(S1, k, pdB, pvB);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             pdB[c] = pdA[c];
@@ -876,9 +880,21 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     // window have contact work (the others would load the striker for nothing)
     if (A.contact && e0x < A.ci1 && e0x + TX >= A.ci0 && e0y < A.cj1 && e0y + TY >= A.cj0)
         contact_correct(pdB, pvB);
-    layer_step(top, pdB, pvB);
+    // the top call site stages into register slot 1: plane top - 1 must be in
+    // slot 0, where an even top finds it in slot 1
+    if ((top & 1) == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double a = sd[0][c], b = sv[0][c];
+            sd[0][c] = sd[1][c];
+            sv[0][c] = sv[1][c];
+            sd[1][c] = a;
+            sv[1][c] = b;
+        }
+    }
+    layer_step(S1, top, pdB, pvB);
     if (nown) {
-        update_node(A.K - 1, carry);
+        update_node(S1, A.K - 1, carry);
         // internal force of a top-plane candidate (the contact step's internal-work correction)
         if (gi >= A.ci0 && gi < A.ci1 && gj >= A.cj0 && gj < A.cj1) {
             const int64_t ci = (gi - A.ci0) + (int64_t)(A.ci1 - A.ci0) * (gj - A.cj0);
