@@ -242,12 +242,14 @@ typedef struct {
 int pdn_surrogate_train(const pdn_sur_train *opt, const pdn_material *m, double crack_band, float *weights,
                         pdn_sur_report *rep);
 /* Use a trained network on ply `ply` (-1: every ply with a damage law) of the
- * context.  A point keeps the exact law when a damage variable of its incoming
- * thresholds exceeds dmg_thresh (e.g. 0.05), or when the network's stress
- * differs from the nominal stress of its own new thresholds by more than
- * res_thresh (e.g. 1e-3) relative to |C0 strain|.  pdn_info reports the
- * fraction of updates that used the exact law.  ESTATE for a ply without a
- * damage law.  Legal mid-run. */
+ * context.  A point that the exact law's elastic screen passes (thresholds at
+ * 1 and strain provably inside every onset surface) takes the law's answer
+ * without consulting the network.  A consulted point keeps the exact law when
+ * a damage variable of its incoming thresholds exceeds dmg_thresh (e.g. 0.05),
+ * or when the network's stress differs from the nominal stress of its own new
+ * thresholds by more than res_thresh (e.g. 1e-3) relative to |C0 strain|.
+ * pdn_info reports the consulted updates and the fraction of them that used
+ * the exact law.  ESTATE for a ply without a damage law.  Legal mid-run. */
 int pdn_surrogate_set(pdn_ctx *ctx, int32_t ply, const float *weights, int64_t n, double dmg_thresh,
                       double res_thresh);
 /* Forward pass on n points: x is n x 10 inputs, y receives n x 10 outputs. */
