@@ -158,7 +158,7 @@ double stiffness_max(const pdn_material &m, double C[3][3])
 }
 
 template <typename R>
-PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1)
+PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1, double lc_min = 0.0, double lc_max = 0.0)
 {
     PlyC<R> P{};
     double C[3][3];
@@ -190,19 +190,32 @@ PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1)
         const double kst = std::cos(a0) * (std::sin(a0) + std::cos(a0) / std::tan(2 * a0));
         const double etat = -1.0 / std::tan(2 * a0);
         P.kE1XT = (R)(m.E1 / m.XT);
-        P.kE1XC = (R)(m.E1 / m.XC);
         P.iYT = (R)(1.0 / m.YT);
-        P.iYC = (R)(1.0 / m.YC);
         P.iSL = (R)(1.0 / m.SL);
-        P.iST = (R)(1.0 / (kst * m.YC));
-        P.etaL0 = (R)(-std::cos(2 * a0) / (std::cos(a0) * std::cos(a0)) * m.SL / m.YC);
         P.kT = (R)(std::cos(a0) * (std::sin(a0) + std::fabs(etat) * std::cos(a0)));
-        // largest crack band without a strength cap: l_c X^2 <= 1.8 E G for all three modes
-        const double l1 = 1.8 * m.E2 * m.GYT / (m.YT * m.YT);
-        const double l2 = 1.8 * m.E2 * m.GYC / (m.YC * m.YC);
-        const double l3 = 1.8 * m.G12 * m.GSL / (m.SL * m.SL);
-        const double lm = std::min({l1, l2, l3});
-        P.vol_nocap = (R)(lm * lm * lm * (1.0 - 1e-6));
+        // Screen constants for the crack bands lc_min .. lc_max of the ply's
+        // elements.  The crack band caps a strength at sqrt(1.8 E G / lc),
+        // which only lowers it as lc grows: the strengths capped at lc_max
+        // bound every element's loading functions from above.  eta_L =
+        // k SL / YC is taken at its largest magnitude over the range (at an
+        // end or where a cap sets in).  A relative margin of 1e-5 keeps a
+        // screened point below onset in the law's own rounding too.
+        auto capped = [](double X, double E, double G, double lc) {
+            const double lim = 1.8 * E * G / lc;
+            return lc > 0 && X * X > lim ? std::sqrt(lim) : X;
+        };
+        const double mg = 1.0 + 1e-5, lhi = lc_max * (1.0 + 1e-6), llo = lc_min * (1.0 - 1e-6);
+        const double kel = -std::cos(2 * a0) / (std::cos(a0) * std::cos(a0));
+        double rmax = 0.0;
+        for (double lc : {llo, lhi, 1.8 * m.G12 * m.GSL / (m.SL * m.SL), 1.8 * m.E2 * m.GYC / (m.YC * m.YC)})
+            if (lc >= llo && lc <= lhi)
+                rmax = std::max(rmax, capped(m.SL, m.G12, m.GSL, lc) / capped(m.YC, m.E2, m.GYC, lc));
+        P.scr_kXT = (R)(mg * m.E1 / m.XT);
+        P.scr_kXC = (R)(mg * m.E1 / m.XC);
+        P.scr_iYT = (R)(mg / capped(m.YT, m.E2, m.GYT, lhi));
+        P.scr_iSL = (R)(mg / capped(m.SL, m.G12, m.GSL, lhi));
+        P.scr_iST = (R)(mg / (kst * capped(m.YC, m.E2, m.GYC, lhi)));
+        P.scr_etaL = (R)(mg * kel * rmax);
     }
     P.KI = (R)m.KI;
     const double ksh = (m.tauI > 0 && m.GIIc > 0) ? m.KI * (m.GIc / m.GIIc) * (m.tauII / m.tauI) * (m.tauII / m.tauI) : m.KI;
@@ -286,14 +299,35 @@ int prepare(pdn_ctx *c)
     c->use_sur = false;
     for (int p = 0; p < c->P; ++p)
         if (c->mat[p].law == PDN_LAW_CDM_SURROGATE && c->ply_net[p] >= 0) c->use_sur = true;
+    // crack-band range of each ply's elements (for the screen constants)
+    std::vector<double> lcmin(c->P, 0.0), lcmax(c->P, 0.0);
+    {
+        double hxlo = 1e300, hxhi = 0, hylo = 1e300, hyhi = 0;
+        for (int i = 0; i < nx; ++i) { const double h = c->xs[i + 1] - c->xs[i]; hxlo = std::min(hxlo, h); hxhi = std::max(hxhi, h); }
+        for (int j = 0; j < ny; ++j) { const double h = c->ys[j + 1] - c->ys[j]; hylo = std::min(hylo, h); hyhi = std::max(hyhi, h); }
+        std::vector<double> hzlo(c->P, 1e300), hzhi(c->P, 0.0);
+        for (int l = 0; l < c->NL; ++l)
+            if (c->layers[l].type == 0) {
+                const int p = c->layers[l].ply;
+                hzlo[p] = std::min(hzlo[p], c->layers[l].hz);
+                hzhi[p] = std::max(hzhi[p], c->layers[l].hz);
+            }
+        for (int p = 0; p < c->P; ++p)
+            if (hzhi[p] > 0) {
+                lcmin[p] = std::cbrt(hxlo * hylo * hzlo[p]);
+                lcmax[p] = std::cbrt(hxhi * hyhi * hzhi[p]);
+            }
+    }
     if (c->precision == PDN_MIXED) {
         std::vector<PlyC<float>> pc;
-        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<float>(c->mat[p], c->ang[p], c->ply_net[p]));
+        for (int p = 0; p < c->P; ++p)
+            pc.push_back(make_ply<float>(c->mat[p], c->ang[p], c->ply_net[p], lcmin[p], lcmax[p]));
         HIPCHK(c, hipMemcpyAsync(c->ply, pc.data(), pc.size() * sizeof(pc[0]), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     } else {
         std::vector<PlyC<double>> pc;
-        for (int p = 0; p < c->P; ++p) pc.push_back(make_ply<double>(c->mat[p], c->ang[p], c->ply_net[p]));
+        for (int p = 0; p < c->P; ++p)
+            pc.push_back(make_ply<double>(c->mat[p], c->ang[p], c->ply_net[p], lcmin[p], lcmax[p]));
         HIPCHK(c, hipMemcpyAsync(c->ply, pc.data(), pc.size() * sizeof(pc[0]), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }

@@ -32,15 +32,15 @@ struct PlyC {
     R rho;
     int law;                                         // 0 elastic, 1 damage, 2 damage by the surrogate
     int sur;                                         // network of a surrogate ply
-    // screening constants (uncapped strengths): reciprocals and bounds
-    R kE1XT, kE1XC;                                  // E1/XT, E1/XC
-    R iYT, iYC, iSL, iST;                            // 1/YT, 1/YC, 1/SL, 1/ST
-    R etaL0;                                         // eta_L with uncapped strengths
+    // elastic screen, valid for every element of the ply: E1/XT, E1/XC, 1/YT,
+    // 1/SL, 1/ST with the strengths capped at the ply's largest crack band,
+    // eta_L of the largest magnitude over its crack-band range (with a margin)
+    R scr_kXT, scr_kXC, scr_iYT, scr_iSL, scr_iST, scr_etaL;
     R kT;                                            // ca0 (sa0 + |etaT| ca0): bound of tau_T^eff / -s22
-    R vol_nocap;                                     // element volume below which no strength is capped
     // interface on top of this ply
     R KI, Ksh, tauI, GIc, GIIc, eta_bk, GIo;
     R den_onset;                                     // screen of the cohesive law: below onset at any mixity
+    R kE1XT, iYT, iSL;                               // surrogate input scales: E1/XT, 1/YT, 1/SL (uncapped)
 };
 
 // Layer table: layer l joins node planes l and l+1.

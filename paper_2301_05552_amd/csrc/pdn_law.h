@@ -98,47 +98,30 @@ __device__ __forceinline__ R cdm_max_damage(const PlyC<R> &P, R lc, R YT, R YC, 
 // elastic for the law, i.e. its thresholds are all at 1 and upper bounds of
 // its loading functions (without roots) show that none can exceed them.  The
 // law then returns s and leaves the thresholds unchanged, exactly as its full
-// evaluation would.  Elements above vol_nocap have crack-band capped matrix
-// strengths: with CAPPED the same bounds then use the capped values (a cube
-// root, three caps and four divisions per point), without it such points are
-// not screened.
-template <bool CAPPED, typename R>
-__device__ __forceinline__ bool cdm_screen(const PlyC<R> &P, R vol, const R e[6], const R r[4], R s[6])
+// evaluation would.  The bounds use the ply's screen constants, which hold for
+// every element of the ply (strengths capped at its largest crack band, with
+// a rounding margin).
+template <typename R>
+__device__ __forceinline__ bool cdm_screen(const PlyC<R> &P, const R e[6], const R r[4], R s[6])
 {
     s[0] = P.C11 * e[0] + P.C12 * e[1] + P.C13 * e[2];
     s[1] = P.C12 * e[0] + P.C22 * e[1] + P.C23 * e[2];
     s[2] = P.C13 * e[0] + P.C23 * e[1] + P.C33 * e[2];
     s[3] = P.G23 * e[3]; s[4] = P.G13 * e[4]; s[5] = P.G12 * e[5];
-    // 1/Y_T, 1/S_L, 1/S_T and eta_L of the element
-    R iYT = P.iYT, iSL = P.iSL, iST = P.iST, etaL = P.etaL0;
-    if (vol > P.vol_nocap) {
-        if constexpr (!CAPPED) return false;
-        const R lc = cbrt(vol);
-        const R YT = cap_strength(P.YT, P.E2, P.GYT, lc);
-        const R YC = cap_strength(P.YC, P.E2, P.GYC, lc);
-        const R SL = cap_strength(P.SL, P.G12v, P.GSL, lc);
-        iYT = R(1) / YT;
-        iSL = R(1) / SL;
-        iST = R(1) / (P.kST * YC);
-        etaL = P.kEtaL * SL / YC;
-    }
-    // with CAPPED the bounds carry a relative margin, so that a point the
-    // screen passes stays below onset in the law's own rounding as well
-    constexpr R mg = CAPPED ? R(1.00001) : R(1);
     const R s1 = s[1];
     const R t2 = s[5] * s[5] + s[4] * s[4];              // tau_L^2
-    bool grow = rmax(e[0], R(0)) * P.kE1XT * mg > r[0] || rmax(-e[0], R(0)) * P.kE1XC * mg > r[1];
+    bool grow = rmax(e[0], R(0)) * P.scr_kXT > r[0] || rmax(-e[0], R(0)) * P.scr_kXC > r[1];
     if (s1 >= R(0)) {
-        const R a = s1 * iYT;
-        grow |= (a * a + t2 * iSL * iSL) * mg > r[2] * r[2];
+        const R a = s1 * P.scr_iYT;
+        grow |= a * a + t2 * P.scr_iSL * P.scr_iSL > r[2] * r[2];
     } else {
-        const R el = etaL * s1;                          // eta_L sigma22
+        const R el = P.scr_etaL * s1;                    // eta_L sigma22
         const R qL = el > R(0) ? R(2) * (t2 + el * el) : t2;
-        grow |= qL * iSL * iSL * mg > r[2] * r[2];
-        const R bT = -s1 * P.kT * iST;
+        grow |= qL * P.scr_iSL * P.scr_iSL > r[2] * r[2];
+        const R bT = -s1 * P.kT * P.scr_iST;
         const R elc = el * P.ca0;
         const R qL2 = R(2) * P.ca0 * P.ca0 * (t2 + elc * elc);
-        grow |= (bT * bT + qL2 * iSL * iSL) * mg > r[3] * r[3];
+        grow |= bT * bT + qL2 * P.scr_iSL * P.scr_iSL > r[3] * r[3];
     }
     return !grow && r[0] <= R(1) && r[1] <= R(1) && r[2] <= R(1) && r[3] <= R(1);
 }
@@ -150,7 +133,7 @@ __device__ void cdm_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
 {
     changed = false;
     R sc[6];
-    const bool elastic = cdm_screen<false>(P, vol, e, r, sc);
+    const bool elastic = cdm_screen(P, e, r, sc);
     const R s0 = sc[0], s1 = sc[1], s2 = sc[2], s3 = sc[3], s4 = sc[4], s5 = sc[5];
     if (P.law == 0 || elastic) {
         sg[0] = s0; sg[1] = s1; sg[2] = s2; sg[3] = s3; sg[4] = s4; sg[5] = s5;

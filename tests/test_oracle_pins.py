@@ -613,6 +613,64 @@ def test_czm_mixed_mode_bk_toughness(a, b):
     assert abs(work - Gc) <= 2e-4 * Gc
 
 
+def _screen_constants(m, lc_min, lc_max):
+    """The GPU screen's per-ply constants (strengths capped at the largest crack
+    band, eta_L of largest magnitude over the range, a 1e-5 margin)."""
+    def capped(X, E, G, lc):
+        lim = 1.8 * E * G / lc
+        return math.sqrt(lim) if X * X > lim else X
+    a0 = math.radians(m["alpha0_deg"])
+    kst = math.cos(a0) * (math.sin(a0) + math.cos(a0) / math.tan(2 * a0))
+    etat = -1.0 / math.tan(2 * a0)
+    kel = -math.cos(2 * a0) / math.cos(a0) ** 2
+    mg, lhi, llo = 1 + 1e-5, lc_max * (1 + 1e-6), lc_min * (1 - 1e-6)
+    cands = [llo, lhi, 1.8 * m["G12"] * m["GSL"] / m["SL"] ** 2, 1.8 * m["E2"] * m["GYC"] / m["YC"] ** 2]
+    rmax = max(capped(m["SL"], m["G12"], m["GSL"], lc) / capped(m["YC"], m["E2"], m["GYC"], lc)
+               for lc in cands if llo <= lc <= lhi)
+    return dict(kXT=mg * m["E1"] / m["XT"], kXC=mg * m["E1"] / m["XC"],
+                iYT=mg / capped(m["YT"], m["E2"], m["GYT"], lhi), iSL=mg / capped(m["SL"], m["G12"], m["GSL"], lhi),
+                iST=mg / (kst * capped(m["YC"], m["E2"], m["GYC"], lhi)), etaL=mg * kel * rmax,
+                kT=math.cos(a0) * (math.sin(a0) + abs(etat) * math.cos(a0)), ca0=math.cos(a0))
+
+
+@pytest.mark.parametrize("outer", [True, False])
+def test_elastic_screen_bounds_hold_over_the_crack_band_range(outer):
+    """The GPU's elastic screen passes a point only when the law leaves it
+    undamaged: with constants derived for the ply's largest crack band, every
+    screened strain stays below onset in the oracle's law at every crack band
+    of the range (where the caps lower the matrix strengths differently)."""
+    m = W.material_cfrp(outer, 0.25e-3)
+    S = np.array([[1 / m["E1"], -m["nu12"] / m["E1"], -m["nu13"] / m["E1"]],
+                  [-m["nu12"] / m["E1"], 1 / m["E2"], -m["nu23"] / m["E2"]],
+                  [-m["nu13"] / m["E1"], -m["nu23"] / m["E2"], 1 / m["E3"]]])
+    C = np.linalg.inv(S)
+    lc_min, lc_max = 0.3e-3, 1.6e-3                 # spans the onset of the caps (about 0.47 mm)
+    k = _screen_constants(m, lc_min, lc_max)
+    rs = np.random.default_rng(23)
+    screened = 0
+    for _ in range(3000):
+        e = rs.standard_normal(6) * np.array([4e-3, 6e-3, 4e-3, 8e-3, 8e-3, 8e-3]) * rs.uniform(0.05, 1.0)
+        s1 = C[1] @ e[:3]
+        t2 = (m["G12"] * e[5]) ** 2 + (m["G13"] * e[4]) ** 2
+        grow = max(e[0], 0) * k["kXT"] > 1 or max(-e[0], 0) * k["kXC"] > 1
+        if s1 >= 0:
+            grow |= (s1 * k["iYT"]) ** 2 + t2 * k["iSL"] ** 2 > 1
+        else:
+            el = k["etaL"] * s1
+            qL = 2 * (t2 + el * el) if el > 0 else t2
+            grow |= qL * k["iSL"] ** 2 > 1
+            bT = -s1 * k["kT"] * k["iST"]
+            qL2 = 2 * k["ca0"] ** 2 * (t2 + (el * k["ca0"]) ** 2)
+            grow |= bT * bT + qL2 * k["iSL"] ** 2 > 1
+        if grow:
+            continue
+        screened += 1
+        for lc in (lc_min, 0.47e-3, 0.8e-3, lc_max, rs.uniform(lc_min, lc_max)):
+            sig, r, dmg = oracle.cdm(m, lc, e, np.ones(4))
+            assert np.all(r == 1.0) and np.all(dmg == 0.0), (e, lc, r)
+    assert screened > 500
+
+
 def test_czm_no_onset_below_the_smallest_onset_opening():
     """An undamaged pair with Ksh |d_sh|^2 + KI <d3>^2 <= 2 GIo min(GIc, GIIc) / GIc
     (GIo = tau_I^2 / 2 KI) is below onset at every mode mixity: the law leaves it
