@@ -120,3 +120,29 @@ def test_autotune_keeps_state():
     assert np.array_equal(a.array_get(pdn.ARR_GP_R), b.array_get(pdn.ARR_GP_R))
     assert np.array_equal(a.contact_force()[1], b.contact_force()[1])
     assert a.autotune() == tile                     # remembered for this plate shape
+
+
+def test_batch_restores_its_tile_after_a_case_is_retiled():
+    """A case moved to another tile layout between batched calls is put back in
+    the batch's layout (block table and step graph rebuilt as needed); the
+    states stay bit for bit those of the cases stepped alone."""
+    _note("batch after a case changed tile")
+    cfgs = _cases(W.PREC_MIXED)
+    sims = [pdn.Simulation(c) for c in cfgs]
+    batch = pdn.Batch(sims)
+    tile = batch.info()["tile"]
+    refs = [pdn.Simulation(c, tile=tile) for c in cfgs]
+    batch.step(17)
+    for r in refs:
+        r.step(17)
+    other = (8, 8) if tile != (8, 8) else (15, 15)
+    sims[0].set_tile(*other)
+    sims[0].step(2)
+    refs[0].step(2)
+    batch.step(19)
+    for r in refs:
+        r.step(19)
+    assert batch.info()["tile"] == tile
+    for k, (s, r) in enumerate(zip(sims, refs)):
+        _same(s, r, f"case {k}")
+    batch.close()
