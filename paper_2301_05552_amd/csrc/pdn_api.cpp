@@ -216,6 +216,7 @@ PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1, double lc_
         P.scr_iSL = (R)(mg / capped(m.SL, m.G12, m.GSL, lhi));
         P.scr_iST = (R)(mg / (kst * capped(m.YC, m.E2, m.GYC, lhi)));
         P.scr_etaL = (R)(mg * kel * rmax);
+        P.scr_vmax = (R)(lc_max > 0 ? lc_max * lc_max * lc_max * (1.0 + 1e-6) : 0.0);
     }
     P.KI = (R)m.KI;
     const double ksh = (m.tauI > 0 && m.GIIc > 0) ? m.KI * (m.GIc / m.GIIc) * (m.tauII / m.tauI) * (m.tauII / m.tauI) : m.KI;

@@ -29,7 +29,7 @@ __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
                            const uint4 *__restrict__ pk, float dmg_thr, float res_thr, int &exact)
 {
     R sel[6];
-    const bool el = cdm_screen(P, e, r, sel);
+    const bool el = cdm_screen(P, vol, e, r, sel);
     if (__ballot(!el) == 0) {                                   // uniform across the wave
 #pragma unroll
         for (int k = 0; k < 6; ++k) sg[k] = sel[k];

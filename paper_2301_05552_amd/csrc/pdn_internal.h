@@ -36,6 +36,7 @@ struct PlyC {
     // 1/SL, 1/ST with the strengths capped at the ply's largest crack band,
     // eta_L of the largest magnitude over its crack-band range (with a margin)
     R scr_kXT, scr_kXC, scr_iYT, scr_iSL, scr_iST, scr_etaL;
+    R scr_vmax;                                      // largest element volume the constants hold for
     R kT;                                            // ca0 (sa0 + |etaT| ca0): bound of tau_T^eff / -s22
     // interface on top of this ply
     R KI, Ksh, tauI, GIc, GIIc, eta_bk, GIo;

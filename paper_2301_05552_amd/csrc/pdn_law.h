@@ -102,12 +102,13 @@ __device__ __forceinline__ R cdm_max_damage(const PlyC<R> &P, R lc, R YT, R YC, 
 // every element of the ply (strengths capped at its largest crack band, with
 // a rounding margin).
 template <typename R>
-__device__ __forceinline__ bool cdm_screen(const PlyC<R> &P, const R e[6], const R r[4], R s[6])
+__device__ __forceinline__ bool cdm_screen(const PlyC<R> &P, R vol, const R e[6], const R r[4], R s[6])
 {
     s[0] = P.C11 * e[0] + P.C12 * e[1] + P.C13 * e[2];
     s[1] = P.C12 * e[0] + P.C22 * e[1] + P.C23 * e[2];
     s[2] = P.C13 * e[0] + P.C23 * e[1] + P.C33 * e[2];
     s[3] = P.G23 * e[3]; s[4] = P.G13 * e[4]; s[5] = P.G12 * e[5];
+    if (vol > P.scr_vmax) return false;                  // beyond the elements the constants were made for
     const R s1 = s[1];
     const R t2 = s[5] * s[5] + s[4] * s[4];              // tau_L^2
     bool grow = rmax(e[0], R(0)) * P.scr_kXT > r[0] || rmax(-e[0], R(0)) * P.scr_kXC > r[1];
@@ -133,7 +134,7 @@ __device__ void cdm_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
 {
     changed = false;
     R sc[6];
-    const bool elastic = cdm_screen(P, e, r, sc);
+    const bool elastic = cdm_screen(P, vol, e, r, sc);
     const R s0 = sc[0], s1 = sc[1], s2 = sc[2], s3 = sc[3], s4 = sc[4], s5 = sc[5];
     if (P.law == 0 || elastic) {
         sg[0] = s0; sg[1] = s1; sg[2] = s2; sg[3] = s3; sg[4] = s4; sg[5] = s5;
