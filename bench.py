@@ -397,8 +397,8 @@ def main():
         copy_calibration(2 << 30)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(the multi-GPU decomposition is described, not built)"}))
+        print(json.dumps({"error": "the library steps a plate on one GPU; --gpus must be 1 "
+                                   "(a multi-GPU domain decomposition is not implemented)"}))
         sys.exit(2)
 
     log("importing torch")
