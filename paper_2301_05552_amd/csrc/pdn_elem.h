@@ -390,6 +390,12 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __builtin_bit_cast(double, r);
 }
 
+// a float of the lane to the left within a row of 16 lanes (0 in the row's first lane)
+__device__ __forceinline__ float row_left(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xF, 0xF, true));
+}
+
 // a double of lane l, uniform
 __device__ __forceinline__ double lane_f64(double v, int l)
 {
@@ -529,7 +535,12 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     constexpr int NT = PDN_TILE_THREADS(TX, TY);
     constexpr bool F32 = sizeof(R) == 4;
     __shared__ R U[2][3][NC];               // node planes k-1, k in the element type (slot k & 1)
-    __shared__ R Fs[2][4][3][NE];           // element corner forces: [bottom/top][corner][xyz][slot]
+    // With rows of 16 element slots (one DPP row, FP32) an element lane adds
+    // its left neighbour's corner forces by a lane move: the LDS then holds,
+    // per node column, the part of row b (corners 0 + 1) and of row b - 1
+    // (corners 3 + 2) of each face instead of the four corners.
+    constexpr bool RD = F32 && NCX == 16;
+    __shared__ R Fs[2][RD ? 2 : 4][3][NE];  // [bottom/top][corner or row part][xyz][slot]
     __shared__ double red[PDN_NTERMS * (NT / 64)];
 
     const int t = threadIdx.x;
@@ -784,7 +795,24 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                         }
                     }
                 }
-                if (erole) {
+                if constexpr (RD) {
+                    // every lane of the wave takes part in the lane moves
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        R f[8];
+                        inv8(cm[c], f);
+#pragma unroll
+                        for (int q = 0; q < 8; ++q) f[q] = evalid ? f[q] : R(0);
+                        // corners 1, 2 (bottom) and 5, 6 (top) of the element to the left
+                        const R l1 = row_left(f[1]), l2 = row_left(f[2]), l5 = row_left(f[5]), l6 = row_left(f[6]);
+                        if (t < NE) {
+                            Fs[0][0][c][t] = f[0] + l1;                // node (a, b), bottom face
+                            Fs[0][1][c][t] = f[3] + l2;                // node (a, b + 1), bottom face
+                            Fs[1][0][c][t] = f[4] + l5;                // node (a, b), top face
+                            Fs[1][1][c][t] = f[7] + l6;                // node (a, b + 1), top face
+                        }
+                    }
+                } else if (erole) {
                     R *F0 = &Fs[0][0][0][t];
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
@@ -802,27 +830,55 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
             if (nown) {
                 // node (np, nq) is corner 0 of element (np, nq), 1 of (np-1, nq),
                 // 2 of (np-1, nq-1) and 3 of (np, nq-1); the four corner forces of
-                // one layer are summed in the element type, in this order
+                // one layer are summed in the element type as (c0 + c1) + (c3 + c2),
+                // for every tile shape
                 R fb[3] = {R(0), R(0), R(0)}, ft[3] = {R(0), R(0), R(0)};
-                if (np < TX && nq < TY) {
-                    const int e = np + NCX * nq;
+                if constexpr (RD) {
+                    // rows nq (corners 0 + 1) and nq - 1 (corners 3 + 2), in this order
+                    if (nq < TY) {
+                        const int e = np + NCX * nq;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][0][c][e]; ft[c] += Fs[1][0][c][e]; }
-                }
-                if (np >= 1 && nq < TY) {
-                    const int e = np - 1 + NCX * nq;
+                        for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][0][c][e]; ft[c] += Fs[1][0][c][e]; }
+                    }
+                    if (nq >= 1) {
+                        const int e = np + NCX * (nq - 1);
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][1][c][e]; ft[c] += Fs[1][1][c][e]; }
-                }
-                if (np >= 1 && nq >= 1) {
-                    const int e = np - 1 + NCX * (nq - 1);
+                        for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][1][c][e]; ft[c] += Fs[1][1][c][e]; }
+                    }
+                } else {
+                    // the same sums from the four corners: row nq (corner 0, then
+                    // corner 1 of the element to the left), then row nq - 1
+                    // (corner 3, then corner 2 of the element to the left)
+                    if (nq < TY) {
+                        R pb[3] = {R(0), R(0), R(0)}, pt[3] = {R(0), R(0), R(0)};
+                        if (np < TX) {
+                            const int e = np + NCX * nq;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][2][c][e]; ft[c] += Fs[1][2][c][e]; }
-                }
-                if (np < TX && nq >= 1) {
-                    const int e = np + NCX * (nq - 1);
+                            for (int c = 0; c < 3; ++c) { pb[c] = Fs[0][0][c][e]; pt[c] = Fs[1][0][c][e]; }
+                        }
+                        if (np >= 1) {
+                            const int e = np - 1 + NCX * nq;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) { fb[c] += Fs[0][3][c][e]; ft[c] += Fs[1][3][c][e]; }
+                            for (int c = 0; c < 3; ++c) { pb[c] += Fs[0][1][c][e]; pt[c] += Fs[1][1][c][e]; }
+                        }
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) { fb[c] += pb[c]; ft[c] += pt[c]; }
+                    }
+                    if (nq >= 1) {
+                        R qb[3] = {R(0), R(0), R(0)}, qt[3] = {R(0), R(0), R(0)};
+                        if (np < TX) {
+                            const int e = np + NCX * (nq - 1);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) { qb[c] = Fs[0][3][c][e]; qt[c] = Fs[1][3][c][e]; }
+                        }
+                        if (np >= 1) {
+                            const int e = np - 1 + NCX * (nq - 1);
+#pragma unroll
+                            for (int c = 0; c < 3; ++c) { qb[c] += Fs[0][2][c][e]; qt[c] += Fs[1][2][c][e]; }
+                        }
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) { fb[c] += qb[c]; ft[c] += qt[c]; }
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { fin[c] = carry[c] + (double)fb[c]; carry[c] = (double)ft[c]; }
