@@ -795,7 +795,8 @@ int pdn_impactor_set(pdn_ctx *c, const pdn_impactor *imp)
 
 int pdn_step(pdn_ctx *c, int64_t n)
 {
-    if (!c || n < 0) return PDN_EINVAL;
+    if (!c) return PDN_EINVAL;
+    if (n < 0) return set_err(c, PDN_EINVAL, "negative step count %lld", (long long)n);
     if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
     if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "materials and striker must be set first");
     (void)hipSetDevice(c->device);
@@ -878,8 +879,9 @@ int pdn_contact_force(const pdn_ctx *c, double *t, double *force, double *disp, 
 
 int pdn_damage_field(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int64_t *n_out)
 {
-    if (!cc || kind < 0 || kind > 6) return PDN_EINVAL;
+    if (!cc) return PDN_EINVAL;
     pdn_ctx *c = const_cast<pdn_ctx *>(cc);
+    if (kind < 0 || kind > 6) return set_err(c, PDN_EINVAL, "unknown damage field %d", kind);
     const bool proj = kind >= PDN_DMG_PROJ_FIBRE;
     const int base = proj ? kind - 4 : kind;
     const int64_t ncol = (int64_t)c->nx * c->ny;
@@ -1496,14 +1498,17 @@ int pdn_batch_create(pdn_ctx *const *cases, int32_t n, pdn_batch **out)
     *out = nullptr;
     if (!cases || n < 1) return PDN_EINVAL;
     for (int32_t i = 0; i < n; ++i) {
+        // the reason goes to the first case's error message
         pdn_ctx *c = cases[i];
-        if (!c) return PDN_EINVAL;
+        if (!c) return set_err(cases[0], PDN_EINVAL, "case %d is null", i);
         for (int32_t j = 0; j < i; ++j)
-            if (cases[j] == c) return set_err(c, PDN_EINVAL, "a context appears twice in the batch");
-        if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
-        if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "materials and striker must be set first");
+            if (cases[j] == c) return set_err(cases[0], PDN_EINVAL, "case %d repeats case %d", i, j);
+        if (c->broken) return set_err(cases[0], PDN_EUNSTABLE, "case %d is unstable", i);
+        if (!all_set(c) || !c->have_imp)
+            return set_err(cases[0], PDN_ESTATE, "case %d: materials and striker must be set first", i);
         if (c->device != cases[0]->device || c->precision != cases[0]->precision || c->ngp != cases[0]->ngp)
-            return set_err(c, PDN_EINVAL, "batched cases must share device, precision and element integration");
+            return set_err(cases[0], PDN_EINVAL,
+                           "case %d: batched cases must share device, precision and element integration", i);
     }
     pdn_batch *b = new pdn_batch;
     b->cs.assign(cases, cases + n);

@@ -58,3 +58,39 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(pdn, "_lib", None)
     with pytest.raises(ImportError):
         pdn.lib()
+
+
+def _bad_descriptors():
+    import copy
+    import workloads as W
+    base = W.tiny(4, 3, 2, 1)
+    edits = [("nx", 0), ("ny", -1), ("n_plies", 0), ("elems_per_ply", 0), ("lx", 0.0), ("ly", -1e-3),
+             ("ply_thickness", 0.0), ("precision", 7), ("bc", 3), ("cfl_safety", 0.0), ("phi", 0.99),
+             ("hourglass_kappa", -0.1), ("integration", 4)]
+    for key, val in edits:
+        c = copy.deepcopy(base)
+        c["mesh"][key] = val
+        yield key, c, {}
+    yield "x_coords", copy.deepcopy(base), {"x_coords": [0.0, 1e-3, 1e-3, 3e-3, 4e-3]}
+    yield "y_coords", copy.deepcopy(base), {"y_coords": [0.0, 2e-3, 1e-3, 3e-3]}
+
+
+@pytest.mark.parametrize("key,cfg,kw", list(_bad_descriptors()), ids=[k for k, _, _ in _bad_descriptors()])
+def test_mesh_create_rejects_bad_descriptors_before_any_device_work(key, cfg, kw):
+    """pdn_mesh_create validates the descriptor (sizes, precision, boundary
+    condition, scheme, grid lines strictly increasing) before it touches a
+    device, so the rejection is the same with or without a GPU."""
+    if not os.path.exists(pdn.LIB_PATH):
+        pytest.skip("libpdn.so not built")
+    with pytest.raises(pdn.PdnError) as e:
+        pdn.Simulation(cfg, **kw)
+    assert e.value.code == -1, key
+
+
+def test_mesh_create_rejects_null_arguments():
+    if not os.path.exists(pdn.LIB_PATH):
+        pytest.skip("libpdn.so not built")
+    L = pdn.lib()
+    h = ctypes.c_void_p()
+    assert L.pdn_mesh_create(None, ctypes.byref(h)) == -1
+    assert L.pdn_mesh_create(ctypes.byref(pdn.MeshDesc()), None) == -1
