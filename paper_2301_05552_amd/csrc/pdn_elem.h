@@ -991,8 +991,13 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     }
 }
 
+// The surrogate build is held to 2 waves per SIMD (256 registers): left
+// alone, the network code takes 430 VGPRs and AGPRs and the whole kernel
+// runs at 1 wave per SIMD even where no point reaches the network.  The
+// spills this costs sit around the network evaluation; the plain build
+// (bound 1, the default) is unaffected.
 template <typename R, int TX, int TY, bool SUR, int NGP = 1>
-__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY)) __attribute__((amdgpu_waves_per_eu(SUR ? 2 : 1)))
 void k_elem_node(ElemArgs<R> A)
 {
     elem_node_tile<R, TX, TY, SUR, NGP>(A, xcd_tile(blockIdx.x, gridDim.x));
@@ -1003,7 +1008,7 @@ void k_elem_node(ElemArgs<R> A)
 // its case and its tile within the case (gridDim.x entries each), in the
 // order the host chose: one lookup per block.
 template <typename R, int TX, int TY, bool SUR, int NGP = 1>
-__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY)) __attribute__((amdgpu_waves_per_eu(SUR ? 2 : 1)))
 void k_elem_node_batch(const ElemArgs<R> *__restrict__ args, const int *__restrict__ start, int ncase)
 {
     const int b = xcd_tile(blockIdx.x, gridDim.x);
