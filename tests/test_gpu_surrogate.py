@@ -179,3 +179,28 @@ def test_screened_points_never_reach_the_network():
     assert np.array_equal(a.array_get(pdn.ARR_DISP), b.array_get(pdn.ARR_DISP))
     assert np.array_equal(a.array_get(pdn.ARR_GP_R), b.array_get(pdn.ARR_GP_R))
     assert rel(a.contact_force()[1], b.contact_force()[1]) == 0.0
+
+
+def test_surrogate_runs_and_training_are_reproducible():
+    """Training the same network twice gives the same weights bit for bit, and
+    a run that accepts network outputs (residual bar 1, far above the
+    network's error) repeats bit for bit: no part of the path depends on
+    timing or on memory left by earlier work."""
+    _note("surrogate reproducibility")
+    cfg = _cdm_case()
+    n1 = _trained_networks(cfg, steps=300)
+    n2 = _trained_networks(cfg, steps=300)
+    for a, b in zip(n1, n2):
+        assert np.array_equal(a, b)
+    out = []
+    for _ in range(2):
+        g = pdn.Simulation(cfg)
+        for p, w in enumerate(n1):
+            g.surrogate_set(p, w, 0.05, 1.0)
+        g.step(400)
+        out.append((g.array_get(pdn.ARR_DISP), g.array_get(pdn.ARR_GP_R), g.contact_force()[1], g.info()))
+        g.close()
+    (da, ra, fa, ia), (db, rb, fb, ib) = out
+    assert ia["sur_consulted"] > 0 and ia["fallback_fraction"] < 1.0      # network outputs were accepted
+    assert np.array_equal(da, db) and np.array_equal(ra, rb) and np.array_equal(fa, fb)
+    assert ia["fallback_fraction"] == ib["fallback_fraction"]
