@@ -63,7 +63,11 @@ enum { PDN_ARR_DISP = 0,    /* 3 * n_nodes: displacement at the last completed l
        PDN_ARR_MASS = 4 };  /* n_nodes: lumped mass (get only) */
 
 /* Plate description (Section 3.2 set-up): nx*ny element columns on lx*ly,
- * n_plies plies of ply_thickness each split into elems_per_ply hex8 layers. */
+ * n_plies plies of ply_thickness each split into elems_per_ply hex8 layers.
+ * The mesh is structured: every element is a box (an axis-aligned hexahedron)
+ * between grid lines x_i, y_j and the layer planes; the grid lines may be
+ * graded (x_coords, y_coords).  General (distorted) hexahedra are not
+ * accepted: there is no per-node coordinate input. */
 typedef struct {
     int32_t nx, ny, n_plies, elems_per_ply;
     double lx, ly, ply_thickness;
@@ -90,8 +94,14 @@ typedef struct {
 
 /* Ply material (Table 1 fields).  law = PDN_LAW_ELASTIC uses only the elastic
  * constants.  The interface fields describe the cohesive interface lying on
- * top of this ply.  Strengths whose crack-band softening would snap back at
- * the element size (l_c X^2 >= 2 E G) are lowered to l_c X^2 = 0.9 * 2 E G. */
+ * top of this ply.
+ * Snap-back reading: the crack-band softening of Section 2.3.1 needs
+ * l_c X^2 < 2 E G (l_c = cube root of the element volume); the paper does not
+ * say what happens beyond that size.  A matrix or shear strength X that
+ * violates it at an element's size is lowered for that element to
+ * l_c X^2 = 0.9 * 2 E G, which keeps the dissipated energy G / l_c; the call
+ * does not fail for it.  The fibre modes' bilinear law is not capped: a
+ * fibre law that is not ordered at the element size gives PDN_EINVAL. */
 typedef struct {
     double E1, E2, E3, nu12, nu13, nu23, G12, G13, G23, rho;
     int32_t law;
@@ -103,7 +113,10 @@ typedef struct {
 
 /* Rigid striker (Section 3.2): radius, mass, initial tip gap above the top
  * surface, impact velocity v0 or energy (energy > 0 gives v0 = sqrt(2E/m)),
- * impact point x0/y0 (NaN = plate centre).  Lateral motion is constrained. */
+ * impact point x0/y0 (NaN = plate centre).  Reading of Section 2.2.2 for a
+ * drop-weight striker guided along its axis: only the Z motion is
+ * integrated; the in-plane components of the contact force do no work on
+ * it (they are booked on the plate side only). */
 typedef struct {
     double radius, mass, v0, energy, gap, x0, y0;
 } pdn_impactor;
@@ -147,13 +160,23 @@ int pdn_impactor_set(pdn_ctx *ctx, const pdn_impactor *imp);
  * after the stream has drained.  PDN_ERANGE if contact reached the edge of the
  * contact search window; PDN_EUNSTABLE on non-finite state. */
 int pdn_step(pdn_ctx *ctx, int64_t n);
-/* Contact-force history, one entry per step: time, contact force on the plate
- * along -Z, striker displacement along -Z. Any of t/force/imp_disp may be NULL. */
+/* Contact-force history (the force-time and force-displacement outputs of
+ * Section 3, Figs. 6-8; the peak forces of Tables 2 and 4), one entry per
+ * step: time, contact force on the plate along -Z (the sum of the PDN
+ * reactions of Eq. 3 over the active set), striker displacement along -Z.
+ * Any of t/force/imp_disp may be NULL.  PDN_ERANGE with *n_out = steps when
+ * cap is smaller. */
 int pdn_contact_force(const pdn_ctx *ctx, double *t, double *force, double *imp_disp,
                       int64_t cap, int64_t *n_out);
-/* Damage field: per bulk element (FIBRE/MATRIX/SHEAR: max of the mode pair),
- * per cohesive element (COHESIVE: max over its 4 nodal points), or projected
- * nx*ny maps (PROJ_*: max over the thickness). */
+/* Damage field (the damage maps of Fig. 9 and the projected delamination
+ * area of Table 4): per bulk element (FIBRE/MATRIX/SHEAR: the larger damage
+ * variable of the mode pair of Section 2.3.1, largest over the element's
+ * points), per cohesive element (COHESIVE: interface damage D of
+ * Section 2.3.2 at its current opening, largest over its 4 nodal points), or
+ * projected nx*ny maps (PROJ_FIBRE, PROJ_MATRIX, PROJ_COHESIVE: largest over
+ * the thickness of FIBRE, MATRIX and COHESIVE), i fastest.  Before the first
+ * step every value is 0.  PDN_EINVAL for an unknown kind, PDN_ERANGE with
+ * *n_out = size when cap is smaller. */
 int pdn_damage_field(const pdn_ctx *ctx, int32_t kind, double *out, int64_t cap, int64_t *n_out);
 int pdn_energies(const pdn_ctx *ctx, pdn_energy *out);
 int pdn_info_get(const pdn_ctx *ctx, pdn_info *out);

@@ -1244,7 +1244,7 @@ int64_t orc_damage_field(const orc_sim *s, int32_t kind, double *out, int64_t ca
 {
     int64_t ncol = (int64_t)s->nx * s->ny;
     int proj = kind >= ORC_DMG_PROJ_FIBRE;
-    int base = proj ? kind - 4 : kind;
+    int base = proj ? (kind == ORC_DMG_PROJ_COHESIVE ? ORC_DMG_COHESIVE : kind - 4) : kind;
     int64_t n = proj ? ncol : (base == ORC_DMG_COHESIVE ? s->nc : s->ne);
     if (cap < n) return -n;
     if (proj) for (int64_t i = 0; i < n; ++i) out[i] = 0;

@@ -883,7 +883,7 @@ int pdn_damage_field(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, 
     pdn_ctx *c = const_cast<pdn_ctx *>(cc);
     if (kind < 0 || kind > 6) return set_err(c, PDN_EINVAL, "unknown damage field %d", kind);
     const bool proj = kind >= PDN_DMG_PROJ_FIBRE;
-    const int base = proj ? kind - 4 : kind;
+    const int base = proj ? (kind == PDN_DMG_PROJ_COHESIVE ? PDN_DMG_COHESIVE : kind - 4) : kind;
     const int64_t ncol = (int64_t)c->nx * c->ny;
     const int64_t nelem = base == PDN_DMG_COHESIVE ? c->nce : c->ne;
     const int64_t n = proj ? ncol : nelem;
@@ -1135,13 +1135,26 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     if (h.magic != kMagic || h.nn != c->nn || h.ne != c->ne || h.npairs != c->npairs || h.ncand != ncand ||
         h.precision != c->precision || h.ngp != c->ngp)
         return set_err(c, PDN_EINVAL, "checkpoint does not match this context");
+    // the blob must be exactly what pdn_state_save writes for this context and
+    // history length; nothing is read or changed before this holds
+    const size_t rs = rsize(c);
+    const size_t fixed = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) +
+                         4 * c->ngp * c->ne * rs + c->npairs * rs + ncand * (1 + 6 * sizeof(double));
+    if (h.hist_n < 0 || (uint64_t)h.hist_n > ((uint64_t)INT64_MAX - fixed) / (3 * sizeof(double)))
+        return set_err(c, PDN_EINVAL, "checkpoint history length %lld is invalid", (long long)h.hist_n);
+    const size_t need = fixed + 3 * (size_t)h.hist_n * sizeof(double);
+    if ((uint64_t)n != (uint64_t)need)
+        return set_err(c, PDN_EINVAL, "checkpoint has %lld bytes, this context's checkpoint with %lld steps has %zu",
+                       (long long)n, (long long)h.hist_n, need);
+    DevGlobals g;
+    std::memcpy(&g, p, sizeof g); p += sizeof g;
+    if (g.step != h.hist_n) return set_err(c, PDN_EINVAL, "checkpoint step count does not match its history");
     (void)hipSetDevice(c->device);
     int rc;
     if (!c->ready && (rc = prepare(c))) return rc;
     if ((rc = ensure_history(c, h.hist_n + 1))) return rc;
-    std::memcpy(&c->gl, p, sizeof(DevGlobals)); p += sizeof(DevGlobals);
+    c->gl = g;
     c->gl.hist_cap = c->hist_cap;
-    const size_t rs = rsize(c);
     auto h2d = [&](void *dst, size_t bytes) -> int {
         if (bytes == 0) return PDN_OK;
         HIPCHK(c, hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, c->stream));

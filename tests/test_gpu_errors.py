@@ -77,6 +77,14 @@ def test_rejected_arguments_leave_the_state_unchanged():
     other.step(2)
     assert _code(s.state_load, other.state_save()) == EINVAL            # another plate's checkpoint
     other.close()
+    blob = ref.state_save()
+    assert _code(s.state_load, blob[:-1]) == EINVAL                     # one byte short
+    assert _code(s.state_load, blob + b"\0") == EINVAL                  # one byte long
+    hdr = bytearray(blob)
+    hdr[5 * 8:6 * 8] = (-1).to_bytes(8, "little", signed=True)          # negative history length
+    assert _code(s.state_load, bytes(hdr)) == EINVAL
+    hdr[5 * 8:6 * 8] = (1 << 60).to_bytes(8, "little", signed=True)     # huge history length
+    assert _code(s.state_load, bytes(hdr)) == EINVAL
     assert _code(s.set_tile, 7, 3) == EINVAL                            # no such tile
     # output buffers that are too small: ERANGE and the size needed
     n = C.c_int64()

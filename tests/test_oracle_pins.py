@@ -567,6 +567,137 @@ def test_cdm_closed_strain_cycle_returns_no_energy():
 
 
 # ---------------------------------------------------------------------------
+# matrix compression with shear: the fracture-plane criteria (LaRC reading)
+# ---------------------------------------------------------------------------
+
+def _mohr_coulomb_plane(m):
+    """Friction coefficient eta_T and transverse shear strength S_T of the
+    fracture plane, found numerically from their definition: under uniaxial
+    transverse compression Y_C the Mohr-Coulomb effective shear
+    tau_T + eta_T sigma_n on a plane at angle a (sigma_n = -Y_C cos^2 a,
+    tau_T = Y_C sin a cos a) is largest on the fracture plane a0 of Table 1,
+    and its value there is S_T.  The longitudinal coefficient follows from
+    the same friction per unit strength: eta_L / S_L = eta_T / S_T."""
+    from scipy.optimize import brentq, minimize_scalar
+    a0 = math.radians(m["alpha0_deg"])
+
+    def argmax(eta):
+        r = minimize_scalar(lambda a: -(math.sin(a) * math.cos(a) - eta * math.cos(a) ** 2),
+                            bounds=(0.0, 0.5 * math.pi), method="bounded",
+                            options=dict(xatol=1e-14))
+        return r.x
+
+    eta_t = brentq(lambda e: argmax(e) - a0, 1e-6, 10.0, xtol=1e-15)
+    s_t = m["YC"] * (math.sin(a0) * math.cos(a0) - eta_t * math.cos(a0) ** 2)
+    return eta_t, s_t, eta_t * m["SL"] / s_t
+
+
+def _sigma_to_strain(m, s22, t12, t13=0.0):
+    """Strain whose effective (undamaged) stress is sigma22 = s22, tau12 = t12,
+    tau13 = t13, all other components zero."""
+    sv = np.zeros(6)
+    sv[1], sv[4], sv[5] = s22, t13, t12
+    return _compliance(m) @ sv
+
+
+def _onset_shear(m, s22, hi):
+    """In-plane shear stress at which the matrix threshold r2+ first grows at
+    a fixed transverse stress s22 (bisection on the law's own verdict)."""
+    lo = 0.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        _, r, _ = oracle.cdm(m, LC3, _sigma_to_strain(m, s22, mid), np.ones(4))
+        if r[2] > 1.0:
+            hi = mid
+        else:
+            lo = mid
+        if hi - lo <= 1e-15 * hi:
+            break
+    _, r, _ = oracle.cdm(m, LC3, _sigma_to_strain(m, s22, hi), np.ones(4))
+    assert r[3] == 1.0            # the tensile/shear criterion, not the compressive one, set in
+    return hi
+
+
+@pytest.mark.parametrize("outer", [True, False])
+def test_cdm_compression_shear_onset_line(outer):
+    """Under transverse compression the matrix shear criterion is of the
+    Mohr-Coulomb kind: damage sets in where tau_L = S_L - eta_L sigma22,
+    with eta_L fixed by the fracture plane (Table 1's alpha0).  The onset
+    shear stress is continuous at sigma22 = 0 (where both branches give S_L)
+    and grows with compression."""
+    m = W.material_cfrp(outer, 0.5e-3)
+    _, _, eta_l = _mohr_coulomb_plane(m)
+    assert eta_l > 0
+    S_L = m["SL"]
+    assert abs(_onset_shear(m, 1e-9 * S_L, 2 * S_L) - S_L) <= 1e-9 * S_L
+    assert abs(_onset_shear(m, -1e-9 * S_L, 2 * S_L) - S_L) <= 1e-9 * S_L
+    prev = S_L
+    for f in (0.1, 0.25, 0.45):
+        s22 = -f * m["YC"]
+        tau = _onset_shear(m, s22, 3 * S_L)
+        assert abs(tau - (S_L - eta_l * s22)) <= 1e-9 * S_L, (f, tau)
+        assert tau > prev
+        prev = tau
+    # at a fixed shear stress the tensile-branch loading function falls as
+    # compression grows (r2+ reached on the path is smaller)
+    rs = []
+    for f in (0.0, 0.1, 0.3):
+        _, r, _ = oracle.cdm(m, LC3, _sigma_to_strain(m, -f * m["YC"], 1.3 * S_L), np.ones(4))
+        rs.append(r[2])
+    assert rs[0] > rs[1] > rs[2]
+
+
+def _fracture_plane_phi(m, s22, t12):
+    """Compressive matrix loading function from the tractions on the fracture
+    plane, computed with the stress tensor: the plane through the fibre axis
+    (material 1) whose normal is tilted by alpha0 from direction 2 towards 3
+    carries the normal traction sigma_n and the shear traction, whose
+    transverse and longitudinal components are tau_T and tau_L at the angle
+    theta = atan2(tau_L, tau_T); Mohr-Coulomb friction reduces each component
+    by eta sigma_n along it."""
+    eta_t, s_t, eta_l = _mohr_coulomb_plane(m)
+    a0 = math.radians(m["alpha0_deg"])
+    sig = np.array([[0.0, t12, 0.0], [t12, s22, 0.0], [0.0, 0.0, 0.0]])
+    n = np.array([0.0, math.cos(a0), math.sin(a0)])
+    e_l = np.array([1.0, 0.0, 0.0])
+    e_t = np.cross(n, e_l)
+    e_t *= np.sign(e_t @ (sig @ n)) if abs(e_t @ (sig @ n)) > 0 else 1.0
+    tr = sig @ n
+    s_n = n @ tr
+    tau_t, tau_l = e_t @ tr, abs(e_l @ tr)
+    th = math.atan2(tau_l, tau_t)
+    te = max(tau_t + eta_t * s_n * math.cos(th), 0.0)
+    le = max(tau_l + eta_l * s_n * math.sin(th), 0.0)
+    return math.hypot(te / s_t, le / m["SL"])
+
+
+@pytest.mark.parametrize("outer", [True, False])
+@pytest.mark.parametrize("f22,f12", [(1.1, 0.0), (1.2, 0.6), (1.1, 0.3), (0.9, 1.3), (0.8, 1.5)])
+def test_cdm_compressive_matrix_criterion_off_axis(outer, f22, f12):
+    """The compressive matrix threshold r2- after one update from the
+    undamaged state equals the fracture-plane loading function computed from
+    the stress tensor's tractions (points with both normal and longitudinal
+    shear stress, beyond onset so that r2- = phi2-)."""
+    m = W.material_cfrp(outer, 0.5e-3)
+    s22, t12 = -f22 * m["YC"], f12 * m["SL"]
+    want = _fracture_plane_phi(m, s22, t12)
+    assert want > 1.02
+    _, r, _ = oracle.cdm(m, LC3, _sigma_to_strain(m, s22, t12), np.ones(4))
+    assert abs(r[3] - want) <= 1e-9 * want, (r, want)
+    assert r[2] >= r[3]
+
+
+def test_cdm_uniaxial_compression_fracture_plane_is_alpha0():
+    """Under pure transverse compression the fracture-plane loading function
+    reaches 1 exactly at Y_C (the plane's strength S_T reproduces Y_C), and
+    the oracle's threshold agrees beyond it."""
+    m = W.material_cfrp(True, 0.5e-3)
+    assert abs(_fracture_plane_phi(m, -m["YC"], 0.0) - 1.0) <= 1e-12
+    _, r, _ = oracle.cdm(m, LC3, _sigma_to_strain(m, -1.3 * m["YC"], 0.0), np.ones(4))
+    assert abs(r[3] - _fracture_plane_phi(m, -1.3 * m["YC"], 0.0)) <= 1e-9
+
+
+# ---------------------------------------------------------------------------
 # cohesive law (Algorithm 5 reading)
 # ---------------------------------------------------------------------------
 
@@ -717,6 +848,115 @@ def test_czm_t800_equal_penalties_table1():
     tau1, _, _ = oracle.czm(m, [1e-9, 0, 0], 0.0)
     tau3, _, _ = oracle.czm(m, [0, 0, 1e-9], 0.0)
     assert abs(tau1[0] / tau3[2] - 1.0) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# stable step of an interface node pair, projected damage maps
+# ---------------------------------------------------------------------------
+
+def _interface_column(safety):
+    """One element column of two plies (0 and 90 degrees, so an interface lies
+    between them), free, no gravity, with a soft elastic bulk so that the
+    interface penalty K_I of the paper's set sets the stable step."""
+    t = 0.25e-3
+    mats = []
+    for _ in range(2):
+        m = dict(W.material_isotropic(1.0e8, 0.3, 1590.0))
+        c = W.material_cfrp(True, t)
+        m.update({k: c[k] for k in ("KI", "tauI", "tauII", "GIc", "GIIc", "eta_bk")})
+        mats.append(m)
+    mesh = W._mesh(1, 1, 2, 1, 1e-3, 1e-3, t, [0.0, 90.0], cohesive=1, bc=W.BC_FREE,
+                   gravity=0.0, cfl_safety=safety)
+    return dict(mesh=mesh, materials=mats, impactor=W.impactor(4e-3, 1.0, v0=0.0, gap=1.0))
+
+
+def _interface_mode_growth(safety, steps, rel_amp=1e-3):
+    """Largest displacement over the second half of the run divided by that
+    over the first half, after an opening of the interface pairs (plus a
+    little noise in every degree of freedom) far below onset."""
+    o = oracle.Oracle(_interface_column(safety))
+    nplane = 4
+    m = o.get(oracle.MASS)
+    d = np.zeros((o.nn, 3))
+    amp = rel_amp * o.cfg["materials"][0]["tauI"] / o.cfg["materials"][0]["KI"]
+    d[: 2 * nplane, 2] = -amp * m[2 * nplane:].sum() / m.sum()             # opening mode with
+    d[2 * nplane:, 2] = amp * m[: 2 * nplane].sum() / m.sum()              # no net momentum
+    d += 1e-3 * amp * np.random.default_rng(5).standard_normal(d.shape)
+    o.set(oracle.DISP, d.reshape(-1))
+    peak = np.zeros(steps)
+    for k in range(steps):
+        o.step(1)
+        peak[k] = np.abs(o.get(oracle.DISP)).max()
+    return peak[steps // 2:].max() / peak[: steps // 2].max(), o.get(oracle.COH_R_IP), o
+
+
+def test_cohesive_pair_stable_step():
+    """The interface penalty between two lumped masses is a two-mass spring of
+    circular frequency sqrt(K_I A_p / m_eff); central differences are stable
+    below 2 / omega and grow geometrically above it (a factor of about 1.33
+    per step at 1.01 times the limit).  With the oracle's step at 0.99 of its
+    limit the oscillation keeps its amplitude over 400 steps; at 1.01 it grows.
+    The opening stays far below onset in both runs, so the pair is linear."""
+    g_lo, r_lo, o = _interface_mode_growth(0.99, 400)
+    assert o.nc == 1
+    assert g_lo < 1.02 and (r_lo == 0).all(), g_lo
+    g_hi, r_hi, _ = _interface_mode_growth(1.01, 80, rel_amp=1e-12)
+    assert g_hi > 1e4 and (r_hi == 0).all(), g_hi
+    # the bulk stays far below its own limit: the pair mode alone decides
+    c_bulk = 1.0e8 * 0.7 / (1.3 * 0.4)
+    assert o.dt < 0.1 * 0.25e-3 * math.sqrt(1590.0 / c_bulk)
+
+
+def test_projected_damage_maps_take_the_max_over_thickness():
+    """Damage maps (Fig. 9): per element (i fastest, then j, then layer) and
+    projected onto the plate (max over the thickness).  Thresholds are set by
+    hand in chosen elements of chosen layers, so the projected map has a
+    known value and place; interface pairs likewise for the cohesive map."""
+    cfg = W.tiny(5, 3, 4, 1, angles=[0, 90, 0, 90], cohesive=1, law=W.LAW_CDM, lx=5e-3, ly=3e-3,
+                 ply_thickness=0.25e-3, v0=0.0)
+    cfg["impactor"]["gap"] = 1.0
+    o = oracle.Oracle(cfg)
+    nx, ny, L = 5, 3, 4
+    r = np.ones((L, ny, nx, 4))
+    hot = {(0, 0): (2, 3.0), (4, 2): (0, 9.0), (2, 1): (3, 1.7), (1, 2): (1, 5.0)}
+    for (i, j), (layer, val) in hot.items():
+        r[layer, j, i, 2] = val                      # r2+ (matrix tension, drives shear)
+    r[3, 2, 4, 2] = 2.0                              # below the column's max (layer 0: 9.0)
+    o.set(oracle.GP_R, r.reshape(-1))
+    per = o.damage_field(oracle.DMG_MATRIX).reshape(L, ny, nx)
+    proj = o.damage_field(oracle.DMG_PROJ_MATRIX).reshape(ny, nx)
+    shear = o.damage_field(oracle.DMG_SHEAR).reshape(L, ny, nx)
+    # each damaged element carries the law's own damage for its threshold
+    for (i, j), (layer, val) in hot.items():
+        rr = np.ones(4)
+        rr[2] = val
+        _, _, dmg = oracle.cdm(cfg["materials"][layer], (5e-3 / 5 * 3e-3 / 3 * 0.25e-3) ** (1 / 3),
+                               np.zeros(6), rr)
+        assert per[layer, j, i] == dmg[2] > 0
+        assert shear[layer, j, i] == dmg[4] > 0
+        assert proj[j, i] == per[layer, j, i]
+    assert per[3, 2, 4] < per[0, 2, 4]
+    mask = np.zeros((ny, nx), bool)
+    for (i, j) in hot:
+        mask[j, i] = True
+    assert (proj[~mask] == 0).all() and (per.sum(axis=0)[~mask] == 0).all()
+    assert (o.damage_field(oracle.DMG_PROJ_FIBRE) == 0).all()
+    # cohesive: one interface pair damaged (threshold 0.6) in the second
+    # interface; it is a corner of the <= 4 interface elements around it
+    assert o.nc == 3 * nx * ny
+    rd = np.zeros((3, ny, nx, 4))
+    for a, (di, dj) in enumerate(((0, 0), (1, 0), (1, 1), (0, 1))):   # corner a of element (i, j)
+        i, j = 2 - di, 1 - dj
+        rd[1, j, i, a] = 0.6                                          # node (2, 1) of interface 1
+    o.set(oracle.COH_R_IP, rd.reshape(-1))
+    coh = o.damage_field(oracle.DMG_COHESIVE).reshape(3, ny, nx)
+    pc = o.damage_field(oracle.DMG_PROJ_COHESIVE).reshape(ny, nx)
+    _, _, D = oracle.czm(cfg["materials"][1], [0.0, 0.0, 0.0], 0.6)
+    assert D > 0.6
+    want = np.zeros((ny, nx))
+    want[0:2, 1:3] = D
+    assert np.array_equal(pc, want)
+    assert np.array_equal(coh[1], want) and (coh[0] == 0).all() and (coh[2] == 0).all()
 
 
 # ---------------------------------------------------------------------------
