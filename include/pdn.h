@@ -285,6 +285,25 @@ int pdn_surrogate_grad(int32_t device, void *stream, const float *weights, const
  * 10 inputs, 10 exact outputs; increments of a path consecutive). */
 int pdn_surrogate_data(int32_t device, void *stream, const pdn_material *m, double crack_band, uint64_t seed,
                        int64_t p0, int64_t n_paths, int32_t increments, float *records);
+/* The gradient of pdn_surrogate_grad without any allocation, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  weights (PDN_SUR_NPARAM), x and t (n x 10
+ * each), grad (PDN_SUR_NPARAM) and loss (one double, may be NULL) are DEVICE
+ * pointers on `device`; the caller owns them.  The packed network, the
+ * interleaved records and the per-workgroup partials live in one fixed
+ * device array of the library (about 6.3 MB per device, held until the
+ * process ends), so n is limited to PDN_SUR_GRAD_NOALLOC_MAX points: larger
+ * n, n < 1 or a NULL pointer give PDN_EINVAL with the reason in
+ * pdn_global_last_error().  The call only enqueues work on `stream` (NULL =
+ * null stream) and returns: grad and loss are ready when the stream reaches
+ * that point.  Its results equal those of pdn_surrogate_grad bit for bit.
+ * Every call on a device shares that device's array: calls that overlap in
+ * time on one device (other streams, other host threads) race and must be
+ * serialised by the caller.  The first call on a device looks up the array's
+ * address; make it before any graph capture. */
+#define PDN_SUR_GRAD_NOALLOC_MAX 16384
+int pdn_surrogate_grad_noalloc(int32_t device, void *stream, const float *weights, const float *x, const float *t,
+                               int64_t n, float *grad, double *loss);
 const char *pdn_global_last_error(void);
 
 #ifdef __cplusplus

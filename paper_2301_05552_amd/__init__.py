@@ -111,6 +111,7 @@ def lib():
                                    P(C.c_double)],
             "pdn_surrogate_data": [C.c_int32, vp, P(Material), C.c_double, C.c_uint64, i64, i64, C.c_int32,
                                    P(C.c_float)],
+            "pdn_surrogate_grad_noalloc": [C.c_int32, vp, vp, vp, vp, i64, vp, vp],
             "pdn_global_last_error": [],
         }
         for name, args in sig.items():
@@ -135,6 +136,7 @@ def _fp(a):
 
 
 SUR_NPARAM = 9674
+SUR_GRAD_NOALLOC_MAX = 16384      # points; pdn_surrogate_grad_noalloc's fixed scratch
 SUR_SEED = 0x5EED5EED
 
 
@@ -189,6 +191,13 @@ def surrogate_grad(w, x, t, device=0, stream=None):
     loss = C.c_double()
     _gchk(lib().pdn_surrogate_grad(device, stream, _fp(w), _fp(x), _fp(t), x.shape[0], _fp(g), C.byref(loss)))
     return g, loss.value
+
+
+def surrogate_grad_noalloc(w_ptr: int, x_ptr: int, t_ptr: int, n: int, grad_ptr: int, loss_ptr: int | None,
+                           device=0, stream=None):
+    """pdn_surrogate_grad_noalloc on device pointers (e.g. tensor.data_ptr());
+    only enqueues the work on the stream."""
+    _gchk(lib().pdn_surrogate_grad_noalloc(device, stream, w_ptr, x_ptr, t_ptr, n, grad_ptr, loss_ptr))
 
 
 def surrogate_data(mat: dict, crack_band: float, p0: int, n_paths: int, increments=32, seed=SUR_SEED,

@@ -1814,6 +1814,31 @@ int pdn_surrogate_grad(int32_t device, void *stream, const float *weights, const
     return PDN_OK;
 }
 
+int pdn_surrogate_grad_noalloc(int32_t device, void *stream, const float *weights, const float *x, const float *t,
+                               int64_t n, float *grad, double *loss)
+{
+    if (!weights || !x || !t || !grad || n < 1)
+        return gerr(PDN_EINVAL, "surrogate grad (no allocation): invalid argument");
+    if (n > PDN_SUR_GRAD_NOALLOC_MAX)
+        return gerr(PDN_EINVAL, "surrogate grad (no allocation): %lld points exceed the fixed scratch's %d",
+                    (long long)n, PDN_SUR_GRAD_NOALLOC_MAX);
+    const int nwg = pdn::sur_grad_blocks(n, 1);
+    if (nwg > PDN_SUR_NOALLOC_PARTS) return gerr(PDN_EINVAL, "surrogate grad (no allocation): scratch layout");
+    GHIPCHK(hipSetDevice(device));
+    void *scr = nullptr;
+    GHIPCHK(pdn::sur_noalloc_scratch(device, &scr));
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)scr;
+    void *pk = base;
+    float *rec = (float *)(base + PDN_SUR_NOALLOC_OFF_REC);
+    float *part = (float *)(base + PDN_SUR_NOALLOC_OFF_PART);
+    GHIPCHK(pdn::launch_sur_pack(weights, pk, s));
+    GHIPCHK(pdn::launch_sur_interleave(x, t, n, rec, s));
+    GHIPCHK(pdn::launch_sur_grad(pk, rec, n, 0, n, 1, 0, 0, (float)(1.0 / ((double)n * SUR_NOUT)), part, s));
+    GHIPCHK(pdn::launch_sur_grad_reduce(part, nwg, (double)n * SUR_NOUT, grad, loss, s));
+    return PDN_OK;
+}
+
 int pdn_surrogate_train(const pdn_sur_train *o, const pdn_material *m, double crack_band, float *weights,
                         pdn_sur_report *rep)
 {

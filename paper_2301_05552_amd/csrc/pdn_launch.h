@@ -1,10 +1,21 @@
 // pdn_launch.h -- host-side launchers of the libpdn kernels (internal).
 #pragma once
+#include "pdn.h"
 #include "pdn_internal.h"
+#include "pdn_mlp.h"
 
 #define PDN_MAX2(a, b) ((a) > (b) ? (a) : (b))
 // threads of an element-tile workgroup: one per element column and one per node column
 #define PDN_TILE_THREADS(TX, TY) ((PDN_MAX2((TX) * (TY), ((TX) + 1) * ((TY) + 1)) + 63) / 64 * 64)
+
+// scratch of pdn_surrogate_grad_noalloc (per device): packed network, then the
+// records of up to PDN_SUR_GRAD_NOALLOC_MAX points, then one partial gradient
+// per 128-point training workgroup
+#define PDN_SUR_NOALLOC_OFF_REC SUR_PACK_BYTES
+#define PDN_SUR_NOALLOC_OFF_PART (PDN_SUR_NOALLOC_OFF_REC + PDN_SUR_GRAD_NOALLOC_MAX * 20 * 4)
+#define PDN_SUR_NOALLOC_PARTS (PDN_SUR_GRAD_NOALLOC_MAX / 128)
+#define PDN_SUR_NOALLOC_SCRATCH_BYTES (PDN_SUR_NOALLOC_OFF_PART + PDN_SUR_NOALLOC_PARTS * (PDN_SUR_NPARAM + 1) * 4)
+#define PDN_SUR_NOALLOC_MAX_DEVICES 64
 
 enum { PDN_TILE_16x16 = 0, PDN_TILE_32x8 = 1, PDN_TILE_8x8 = 2, PDN_TILE_15x15 = 3, PDN_TILE_31x15 = 4,
        PDN_TILE_COUNT = 5 };
@@ -61,5 +72,10 @@ hipError_t launch_sur_adam(const float *partials, int nparts, float *w, float *m
                            float b2, float eps, float bc1, float bc2, float *loss_out, hipStream_t s);
 hipError_t launch_sur_eval(const void *pk, const float *x, int64_t n, float *y, hipStream_t s);
 int sur_loss_blocks(int64_t n);
+hipError_t launch_sur_interleave(const float *x, const float *t, int64_t n, float *rec, hipStream_t s);
+hipError_t launch_sur_grad_reduce(const float *part, int nparts, double count, float *grad, double *loss,
+                                  hipStream_t s);
+// device address of the fixed scratch array on `device` (must be the current device)
+hipError_t sur_noalloc_scratch(int device, void **out);
 hipError_t launch_sur_loss(const void *pk, const float *data, int64_t i0, int64_t n, double *partials, hipStream_t s);
 }  // namespace pdn

@@ -14,6 +14,8 @@
 #include "pdn_law.h"
 #include "pdn_mlp.h"
 
+#include <mutex>
+
 namespace pdn {
 
 #define SUR_REC 20                          // record: 10 inputs, 10 targets
@@ -486,6 +488,48 @@ hipError_t launch_sur_eval(const void *pk, const float *x, int64_t n, float *y, 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// gradient without allocation: a fixed device array holds the packed network,
+// the interleaved records and the workgroup partials
+// ---------------------------------------------------------------------------
+__global__ void k_sur_interleave(const float *__restrict__ x, const float *__restrict__ t, int64_t n,
+                                 float *__restrict__ rec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * SUR_REC) return;
+    const int64_t p = i / SUR_REC;
+    const int k = (int)(i - p * SUR_REC);
+    rec[i] = k < SUR_NIN ? x[p * SUR_NIN + k] : t[p * SUR_NOUT + (k - SUR_NIN)];
+}
+
+// parameter p: the partials of the nparts workgroups summed in workgroup order
+// in FP64 (the order and precision of the host reduction of pdn_surrogate_grad)
+__global__ void k_sur_grad_reduce(const float *__restrict__ part, int nparts, double count,
+                                  float *__restrict__ grad, double *__restrict__ loss)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > SUR_NPARAM) return;
+    double g = 0.0;
+    for (int b = 0; b < nparts; ++b) g += (double)part[(size_t)b * (SUR_NPARAM + 1) + p];
+    if (p < SUR_NPARAM) grad[p] = (float)g;
+    else if (loss) *loss = g / count;
+}
+
+hipError_t launch_sur_interleave(const float *x, const float *t, int64_t n, float *rec, hipStream_t s)
+{
+    const int64_t nb = (n * SUR_REC + 255) / 256;
+    hipLaunchKernelGGL(k_sur_interleave, dim3((unsigned)nb), dim3(256), 0, s, x, t, n, rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_sur_grad_reduce(const float *part, int nparts, double count, float *grad, double *loss,
+                                  hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sur_grad_reduce, dim3((SUR_NPARAM + 1 + 255) / 256), dim3(256), 0, s, part, nparts, count,
+                       grad, loss);
+    return hipGetLastError();
+}
+
 int sur_loss_blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 hipError_t launch_sur_loss(const void *pk, const float *data, int64_t i0, int64_t n, double *partials, hipStream_t s)
@@ -495,4 +539,33 @@ hipError_t launch_sur_loss(const void *pk, const float *data, int64_t i0, int64_
     return hipGetLastError();
 }
 
+}  // namespace pdn
+
+// Scratch of pdn_surrogate_grad_noalloc: one copy per device, held until the
+// process ends.  Host code never passes this name to a kernel (on the host it
+// is only a stand-in for the symbol); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[PDN_SUR_NOALLOC_SCRATCH_BYTES];
+
+namespace pdn {
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[PDN_SUR_NOALLOC_MAX_DEVICES];
+}  // namespace
+
+hipError_t sur_noalloc_scratch(int device, void **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= PDN_SUR_NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // device must be current
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
 }  // namespace pdn
