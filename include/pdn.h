@@ -60,7 +60,9 @@ enum { PDN_ARR_DISP = 0,    /* 3 * n_nodes: displacement at the last completed l
        PDN_ARR_VEL = 1,     /* 3 * n_nodes: velocity (TW velocity = CD half-step velocity) */
        PDN_ARR_GP_R = 2,    /* 4 * n_bulk: damage thresholds r1+, r1-, r2+, r2- per element */
        PDN_ARR_COH_R = 3,   /* n_pairs: cohesive damage threshold per interface node pair */
-       PDN_ARR_MASS = 4 };  /* n_nodes: lumped mass (get only) */
+       PDN_ARR_MASS = 4,    /* n_nodes: lumped mass (get only) */
+       PDN_ARR_GP_EP = 5 }; /* 3 * n_bulk: plastic state per element: plastic gamma12, gamma13 and
+                               accumulated plastic shear (zeros, and set rejected, without plasticity) */
 
 /* Plate description (Section 3.2 set-up): nx*ny element columns on lx*ly,
  * n_plies plies of ply_thickness each split into elems_per_ply hex8 layers.
@@ -109,6 +111,15 @@ typedef struct {
     double GXT, GXC, GYT, GYC, GSL;
     double fXT, fGT, fXC, fGC;
     double KI, tauI, tauII, GIc, GIIc, eta_bk;
+    /* Matrix shear plasticity (Algorithm 4, first two lines; Table 1's S_p,
+     * K_p), law PDN_LAW_CDM only; Sp = 0 turns it off.  Reading: linear
+     * isotropic hardening of the longitudinal shear tau_L = |(tau12, tau13)|
+     * in effective stress, yield when tau_L > Sp + Kp G12 abar (abar the
+     * accumulated plastic shear), radial return; the damage criteria act on
+     * the stress of the elastic strains.  Needs G13 = G12, the one-point
+     * element, the 15x15 or 16x16 tile, no surrogate plies and no batch;
+     * otherwise PDN_EINVAL. */
+    double Sp, Kp;
 } pdn_material;
 
 /* Rigid striker (Section 3.2): radius, mass, initial tip gap above the top
@@ -194,6 +205,12 @@ int pdn_set_tile(pdn_ctx *ctx, int32_t tile_x, int32_t tile_y);
  * the step, over the last pdn_step call, from HIP events (0 if not timed). */
 int pdn_kernel_times(const pdn_ctx *ctx, double *elem_node_ms, double *books_ms);
 int pdn_set_timing(pdn_ctx *ctx, int32_t on);
+/* Measurement hook (not a step of the method): copy `bytes` (a multiple of
+ * 16, 16-byte aligned device pointers) from src to dst on `device` with the
+ * library's streaming-copy kernel, enqueued on `stream`.  The HBM bandwidth
+ * it reaches is the practical ceiling the element/node kernel's roofline is
+ * read against.  PDN_EINVAL on bad sizes or alignment. */
+int pdn_stream_copy(int32_t device, void *stream, const void *src, void *dst, int64_t bytes);
 /* Autotuner: time one element/node pass per supported tile shape that fits
  * the device, keep the fastest (remembered per plate shape for the process)
  * and report it.  The timed passes recompute the current predictor, so the

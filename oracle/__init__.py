@@ -22,7 +22,7 @@ _SRC = os.path.join(_HERE, "pdn_oracle.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 _lib = None
 
-DISP, VEL, GP_R, COH_R_IP, COH_R_BY_BOTTOM_NODE, MASS, COORDS, FINT, ACTIVE, FIX, FCONTACT = range(11)
+DISP, VEL, GP_R, COH_R_IP, COH_R_BY_BOTTOM_NODE, MASS, COORDS, FINT, ACTIVE, FIX, FCONTACT, GP_EP = range(12)
 DMG_FIBRE, DMG_MATRIX, DMG_SHEAR, DMG_COHESIVE, DMG_PROJ_FIBRE, DMG_PROJ_MATRIX, \
     DMG_PROJ_COHESIVE = range(7)
 
@@ -51,7 +51,7 @@ class MeshDesc(C.Structure):
 
 _MAT_FIELDS = ["E1", "E2", "E3", "nu12", "nu13", "nu23", "G12", "G13", "G23", "rho", "law",
                "XT", "XC", "YT", "YC", "SL", "alpha0_deg", "GXT", "GXC", "GYT", "GYC", "GSL",
-               "fXT", "fGT", "fXC", "fGC", "KI", "tauI", "tauII", "GIc", "GIIc", "eta_bk"]
+               "fXT", "fGT", "fXC", "fGC", "KI", "tauI", "tauII", "GIc", "GIIc", "eta_bk", "Sp", "Kp"]
 
 
 class Material(C.Structure):
@@ -88,6 +88,7 @@ def lib():
         L.orc_set_material.argtypes = [C.c_void_p, C.c_int32, P(Material)]
         L.orc_set_impactor.argtypes = [C.c_void_p, P(Impactor)]
         L.orc_set_threads.argtypes = [C.c_void_p, C.c_int32]
+        L.orc_set_assembly_order.argtypes = [C.c_void_p, C.c_int32]
         L.orc_step.argtypes = [C.c_void_p, C.c_int64]
         L.orc_dt.restype = C.c_double
         L.orc_dt.argtypes = [C.c_void_p]
@@ -107,6 +108,7 @@ def lib():
         L.orc_hex8_force_elastic_full.argtypes = [dp, dp, P(Material), C.c_double, dp]
         L.orc_hex8_mass.argtypes = [dp, C.c_double, dp]
         L.orc_cdm.argtypes = [P(Material), C.c_double, dp, dp, dp, dp]
+        L.orc_cdm_plastic.argtypes = [P(Material), C.c_double, dp, dp, dp, dp, dp]
         L.orc_czm.restype = C.c_double
         L.orc_czm.argtypes = [P(Material), dp, dp, dp]
         L.orc_rk4.argtypes = [RHS, C.c_void_p, C.c_double, dp, C.c_int, C.c_double]
@@ -121,7 +123,8 @@ def _dp(a: np.ndarray):
 
 
 def material(m: dict) -> Material:
-    return Material(**{f: (int(m[f]) if f == "law" else float(m[f])) for f in _MAT_FIELDS})
+    return Material(**{f: (int(m[f]) if f == "law" else float(m.get(f, 0.0) if f in ("Sp", "Kp") else m[f]))
+                       for f in _MAT_FIELDS})
 
 
 def mesh_desc(mesh: dict, node_coords: np.ndarray | None = None):
@@ -186,6 +189,10 @@ class Oracle:
         if rc != 0:
             raise OracleError(lib().orc_error(self.h).decode())
 
+    def set_assembly_order(self, reverse: bool):
+        """Sum nodal forces in descending element order (sensitivity runs)."""
+        self._chk(lib().orc_set_assembly_order(self.h, int(reverse)))
+
     def set_impactor(self, imp: dict):
         self._chk(lib().orc_set_impactor(self.h, C.byref(Impactor(**imp))))
 
@@ -200,7 +207,7 @@ class Oracle:
         ngp = 8 if self.cfg["mesh"].get("integration", 1) == 8 else 1
         size = {DISP: 3 * self.nn, VEL: 3 * self.nn, FINT: 3 * self.nn, GP_R: 4 * ngp * self.ne,
                 COH_R_IP: 4 * self.nc, COH_R_BY_BOTTOM_NODE: self.nn, MASS: self.nn,
-                COORDS: 3 * self.nn, ACTIVE: self.nn, FCONTACT: 3 * self.nn}[kind]
+                COORDS: 3 * self.nn, ACTIVE: self.nn, FCONTACT: 3 * self.nn, GP_EP: 3 * ngp * self.ne}[kind]
         out = np.zeros(max(size, 1))
         self._chk(lib().orc_get(self.h, kind, _dp(out), out.size))
         return out[:size]
@@ -279,6 +286,17 @@ def cdm(mat: dict, lc: float, eps, r):
     sig, dmg = np.zeros(6), np.zeros(5)
     lib().orc_cdm(C.byref(material(mat)), lc, _dp(e), _dp(rr), _dp(sig), _dp(dmg))
     return sig, rr, dmg
+
+
+def cdm_plastic(mat: dict, lc: float, eps, r, ep):
+    """The intralaminar law with the plastic state (Algorithm 4 from its first
+    line); returns (sigma, r_new, ep_new, damage[5])."""
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    rr = np.ascontiguousarray(r, dtype=np.float64).copy()
+    pp = np.ascontiguousarray(ep, dtype=np.float64).copy()
+    sig, dmg = np.zeros(6), np.zeros(5)
+    lib().orc_cdm_plastic(C.byref(material(mat)), lc, _dp(e), _dp(rr), _dp(pp), _dp(sig), _dp(dmg))
+    return sig, rr, pp, dmg
 
 
 def czm(mat: dict, delta, rd: float):

@@ -54,6 +54,7 @@ struct orc_sim {
     int have_imp;
     orc_impactor imp;
     int nthreads;
+    int reverse_assembly;          /* sensitivity runs: nodal sums in descending element order */
     /* state at level n */
     int64_t step;                  /* completed steps */
     int needs_init;
@@ -62,6 +63,7 @@ struct orc_sim {
     double *fc, *fc_prev;          /* contact force found in the last step / the one before */
     double *v_prev;                /* v at level n-1 */
     double *r;                     /* 4 per Gauss point: 4 ne ngp */
+    double *ep;                    /* 3 per Gauss point: plastic gamma12, gamma13, accumulated */
     double *rd;                    /* 4 nc */
     unsigned char *active;         /* nn */
     double *ework;                 /* per-element scratch: 24 forces */
@@ -358,6 +360,40 @@ void orc_cdm(const orc_material *m, double lc, const double eps[6], double r[4],
     if (dmg) { dmg[0] = d1p; dmg[1] = d1m; dmg[2] = d2p; dmg[3] = d2m; dmg[4] = d6; }
 }
 
+/* Algorithm 4, first line (reading): plasticity of the longitudinal shear in
+ * effective stress.  The shear plane through the fibre is isotropic
+ * (G13 = G12), so the yield function is on tau_L = |(tau12, tau13)|:
+ *   F = tau_L - (S_p + H abar),  H = K_p G12 (linear isotropic hardening on
+ * the accumulated plastic shear abar).  Where F > 0, the radial return along
+ * the trial stress direction n: dl = F / (G12 + H), gamma_p += dl n,
+ * abar += dl.  ep = {gamma12_p, gamma13_p, abar}. */
+static void plastic_return(const orc_material *m, const double eps[6], double ep[3])
+{
+    double G = m->G12, H = m->Kp * m->G12;
+    double t12 = G * (eps[5] - ep[0]), t13 = G * (eps[4] - ep[1]);
+    double tL = sqrt(t12 * t12 + t13 * t13);
+    double F = tL - (m->Sp + H * ep[2]);
+    if (!(F > 0)) return;
+    double dl = F / (G + H);
+    ep[0] += dl * t12 / tL;
+    ep[1] += dl * t13 / tL;
+    ep[2] += dl;
+}
+
+void orc_cdm_plastic(const orc_material *m, double lc, const double eps[6], double r[4], double ep[3],
+                     double sig[6], double dmg[5])
+{
+    /* Algorithm 4: plastic strains, effective elastic strains, then the
+     * damage law on the elastic strains */
+    double ee[6] = {eps[0], eps[1], eps[2], eps[3], eps[4], eps[5]};
+    if (m->law != 0 && m->Sp > 0) {
+        plastic_return(m, eps, ep);
+        ee[5] = eps[5] - ep[0];
+        ee[4] = eps[4] - ep[1];
+    }
+    orc_cdm(m, lc, ee, r, sig, dmg);
+}
+
 double orc_czm(const orc_material *m, const double dl[3], double *rd, double tau[3])
 {
     /* Algorithm 5 with Turon-2018 variables; reading: shear penalty
@@ -395,7 +431,7 @@ double orc_czm(const orc_material *m, const double dl[3], double *rd, double tau
  * material frame, law (thresholds r, updated), back to the global frame and
  * the nominal stress Pn = F S.  Returns the secant energy density S:E/2. */
 static double point_response(const double H[3][3], const orc_material *m, double angle_deg, double lc,
-                             double *r, double Pn[3][3])
+                             double *r, double *ep, double Pn[3][3])
 {
     /* the Green strain E = (F^T F - I)/2 is evaluated as (H + H^T + H^T H)/2,
      * the same tensor without the cancellation of 1 + small - 1 */
@@ -427,8 +463,13 @@ static double point_response(const double H[3][3], const orc_material *m, double
         }
     double eps[6] = {Em[0][0], Em[1][1], Em[2][2], 2 * Em[1][2], 2 * Em[0][2], 2 * Em[0][1]};
     double sg[6];
-    double rloc[4] = {1, 1, 1, 1};
-    orc_cdm(m, lc, eps, r ? r : rloc, sg, NULL);
+    double rloc[4] = {1, 1, 1, 1}, eploc[3] = {0, 0, 0};
+    double *epp = ep ? ep : eploc;
+    orc_cdm_plastic(m, lc, eps, r ? r : rloc, epp, sg, NULL);
+    if (m->law != 0 && m->Sp > 0) {           /* recoverable energy: the elastic strains */
+        eps[5] -= epp[0];
+        eps[4] -= epp[1];
+    }
     double Sm[3][3] = {{sg[0], sg[5], sg[4]}, {sg[5], sg[1], sg[3]}, {sg[4], sg[3], sg[2]}};
     double S[3][3];
     for (int i = 0; i < 3; ++i)
@@ -456,7 +497,7 @@ static double point_response(const double H[3][3], const orc_material *m, double
 
 static double hex8_force(const double *b, double V, const double *gam, const double *u,
                          const orc_material *m, double angle_deg, double kappa, double lc,
-                         double *r, double f[24])
+                         double *r, double *ep, double f[24])
 {
     /* one point: H = sum_a u_a (x) b_a with the mean gradients b */
     double H[3][3], Pn[3][3];
@@ -466,7 +507,7 @@ static double hex8_force(const double *b, double V, const double *gam, const dou
             for (int a = 0; a < 8; ++a) s += u[3 * a + i] * b[3 * a + J];
             H[i][J] = s;
         }
-    double wd = point_response(H, m, angle_deg, lc, r, Pn);
+    double wd = point_response(H, m, angle_deg, lc, r, ep, Pn);
     for (int a = 0; a < 8; ++a)
         for (int i = 0; i < 3; ++i) {
             double t = 0;
@@ -500,7 +541,7 @@ static double hex8_force(const double *b, double V, const double *gam, const dou
  * H = sum_a u_a (x) dN_a/dX, the law with the point's own thresholds
  * r[4 g .. 4 g + 3], and f_a += det J Pn dN_a/dX.  No hourglass control. */
 static double hex8_force_full(const double X[24], const double *u, const orc_material *m, double angle_deg,
-                              double lc, double *r, double f[24])
+                              double lc, double *r, double *ep, double f[24])
 {
     const double gp = 1.0 / sqrt(3.0);
     double energy = 0;
@@ -528,7 +569,7 @@ static double hex8_force_full(const double X[24], const double *u, const orc_mat
                 for (int a = 0; a < 8; ++a) t += u[3 * a + i] * B[a][I];
                 H[i][I] = t;
             }
-        energy += dJ * point_response(H, m, angle_deg, lc, r ? r + 4 * g : NULL, Pn);
+        energy += dJ * point_response(H, m, angle_deg, lc, r ? r + 4 * g : NULL, ep ? ep + 3 * g : NULL, Pn);
         for (int a = 0; a < 8; ++a)
             for (int i = 0; i < 3; ++i) {
                 double t = 0;
@@ -546,7 +587,7 @@ double orc_hex8_force_elastic(const double X[24], const double u[24], const orc_
     orc_hex8_geometry(X, b, &V, gam);
     orc_material me = *m;
     me.law = 0;
-    return hex8_force(b, V, gam, u, &me, angle_deg, kappa, cbrt(V), NULL, f);
+    return hex8_force(b, V, gam, u, &me, angle_deg, kappa, cbrt(V), NULL, NULL, f);
 }
 
 double orc_hex8_force_elastic_full(const double X[24], const double u[24], const orc_material *m,
@@ -556,7 +597,7 @@ double orc_hex8_force_elastic_full(const double X[24], const double u[24], const
     orc_hex8_geometry(X, b, &V, NULL);
     orc_material me = *m;
     me.law = 0;
-    return hex8_force_full(X, u, &me, angle_deg, cbrt(V), NULL, f);
+    return hex8_force_full(X, u, &me, angle_deg, cbrt(V), NULL, NULL, f);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -748,6 +789,7 @@ orc_sim *orc_create(const orc_mesh_desc *d)
     s->fc_prev = (double *)calloc(3 * nn, sizeof(double));
     s->v_prev = (double *)calloc(3 * nn, sizeof(double));
     s->r = (double *)calloc(4 * s->ngp * (ne ? ne : 1), sizeof(double));
+    s->ep = (double *)calloc(3 * s->ngp * (ne ? ne : 1), sizeof(double));
     s->rd = (double *)calloc(4 * (nc ? nc : 1), sizeof(double));
     s->active = (unsigned char *)calloc(nn, 1);
     s->ework = (double *)calloc(24 * (ne ? ne : 1), sizeof(double));
@@ -762,10 +804,16 @@ void orc_destroy(orc_sim *s)
     if (!s) return;
     void *p[] = {s->bulk_layer_of, s->X, s->conn, s->eply, s->cconn, s->cply, s->fix, s->top,
                  s->mass, s->eb, s->evol, s->egam, s->elc_band, s->carea, s->d, s->v, s->a,
-                 s->fint, s->fint_prev, s->fc, s->fc_prev, s->v_prev, s->r, s->rd, s->active,
+                 s->fint, s->fint_prev, s->fc, s->fc_prev, s->v_prev, s->r, s->ep, s->rd, s->active,
                  s->ework, s->cwork, s->hist};
     for (size_t i = 0; i < sizeof p / sizeof p[0]; ++i) free(p[i]);
     free(s);
+}
+
+int orc_set_assembly_order(orc_sim *s, int32_t reverse)
+{
+    s->reverse_assembly = reverse != 0;
+    return 0;
 }
 
 int orc_set_threads(orc_sim *s, int32_t n)
@@ -801,6 +849,9 @@ int orc_set_material(orc_sim *s, int32_t ply, const orc_material *m)
     double lcmax = 0;
     for (int64_t e = 0; e < s->ne; ++e)
         if ((ply < 0 || s->eply[e] == ply) && s->elc_band[e] > lcmax) lcmax = s->elc_band[e];
+    if (m->Sp < 0 || m->Kp < 0) return fail(s, "plasticity needs S_p >= 0 and K_p >= 0");
+    if (m->Sp > 0 && m->law != 0 && m->G13 != m->G12)
+        return fail(s, "longitudinal shear plasticity needs an isotropic shear plane (G13 = G12)");
     if (m->law != 0) {
         double ls[2] = {m->XT, m->XC}, gs[2] = {m->GXT, m->GXC}, fx[2] = {m->fXT, m->fXC}, fg[2] = {m->fGT, m->fGC};
         for (int k = 0; k < 2; ++k) {
@@ -915,10 +966,10 @@ static void internal_force(orc_sim *s)
             for (int a = 0; a < 8; ++a)
                 for (int i = 0; i < 3; ++i) Xe[3 * a + i] = s->X[3 * s->conn[8 * e + a] + i];
             uel += hex8_force_full(Xe, ue, &s->mat[p], s->ang[p], s->elc_band[e], &s->r[32 * e],
-                                   &s->ework[24 * e]);
+                                   &s->ep[24 * e], &s->ework[24 * e]);
         } else {
             uel += hex8_force(&s->eb[24 * e], s->evol[e], &s->egam[32 * e], ue, &s->mat[p], s->ang[p],
-                              s->kappa, s->elc_band[e], &s->r[4 * e], &s->ework[24 * e]);
+                              s->kappa, s->elc_band[e], &s->r[4 * e], &s->ep[3 * e], &s->ework[24 * e]);
         }
     }
 #ifdef _OPENMP
@@ -940,12 +991,17 @@ static void internal_force(orc_sim *s)
             uel += 0.5 * A * (tau[0] * dl[0] + tau[1] * dl[1] + tau[2] * dl[2]);
         }
     }
-    /* assembly in ascending element order */
+    /* assembly in ascending element order (descending for a sensitivity run:
+     * the same sums in another order, to measure how the problem amplifies
+     * rounding) */
     for (int64_t n = 0; n < 3 * s->nn; ++n) s->fint[n] = 0;
-    for (int64_t e = 0; e < ne; ++e)
+    for (int64_t k = 0; k < ne; ++k) {
+        int64_t e = s->reverse_assembly ? ne - 1 - k : k;
         for (int a = 0; a < 8; ++a)
             for (int i = 0; i < 3; ++i) s->fint[3 * s->conn[8 * e + a] + i] += s->ework[24 * e + 3 * a + i];
-    for (int64_t e = 0; e < nc; ++e) {
+    }
+    for (int64_t k = 0; k < nc; ++k) {
+        int64_t e = s->reverse_assembly ? nc - 1 - k : k;
         for (int a = 0; a < 4; ++a)
             for (int i = 0; i < 3; ++i) {
                 s->fint[3 * s->cconn[8 * e + a] + i] += s->cwork[24 * e + 3 * a + i];
@@ -1154,6 +1210,7 @@ int orc_get(const orc_sim *s, int32_t kind, double *out, int64_t cap)
     case ORC_FINT: n = 3 * s->nn; if (cap < n) return -1; memcpy(out, s->fint, n * 8); return 0;
     case ORC_FCONTACT: n = 3 * s->nn; if (cap < n) return -1; memcpy(out, s->fc, n * 8); return 0;
     case ORC_GP_R: n = 4 * s->ngp * s->ne; if (cap < n) return -1; memcpy(out, s->r, n * 8); return 0;
+    case ORC_GP_EP: n = 3 * s->ngp * s->ne; if (cap < n) return -1; memcpy(out, s->ep, n * 8); return 0;
     case ORC_COH_R_IP: n = 4 * s->nc; if (cap < n) return -1; memcpy(out, s->rd, n * 8); return 0;
     case ORC_MASS: n = s->nn; if (cap < n) return -1; memcpy(out, s->mass, n * 8); return 0;
     case ORC_COORDS: n = 3 * s->nn; if (cap < n) return -1; memcpy(out, s->X, n * 8); return 0;
@@ -1177,6 +1234,7 @@ int orc_set(orc_sim *s, int32_t kind, const double *in, int64_t n)
     case ORC_DISP: if (n != 3 * s->nn) return -1; memcpy(s->d, in, n * 8); break;
     case ORC_VEL: if (n != 3 * s->nn) return -1; memcpy(s->v, in, n * 8); break;
     case ORC_GP_R: if (n != 4 * s->ngp * s->ne) return -1; memcpy(s->r, in, n * 8); break;
+    case ORC_GP_EP: if (n != 3 * s->ngp * s->ne) return -1; memcpy(s->ep, in, n * 8); break;
     case ORC_COH_R_IP: if (n != 4 * s->nc) return -1; memcpy(s->rd, in, n * 8); break;
     case ORC_COH_R_BY_BOTTOM_NODE:
         if (n != s->nn) return -1;

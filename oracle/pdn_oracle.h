@@ -13,8 +13,8 @@
  *   - Section 2.2: Tchamwa-Wielgosz explicit scheme (phi = 1 is central
  *     difference) with lumped mass; rigid striker integrated by RK4 (the
  *     printed k3/4 weight is read as k3/3);
- *   - Section 2.3.1, Algorithm 4: intralaminar continuum damage (elastic-damage
- *     reading, no shear plasticity);
+ *   - Section 2.3.1, Algorithm 4: intralaminar continuum damage with
+ *     plasticity of the longitudinal shear (Table 1's S_p, K_p);
  *   - Section 2.3.2, Algorithm 5: Turon cohesive law on zero-thickness
  *     interface elements with nodal (Newton-Cotes) integration;
  *   - critical time step of Section 2.3.1 / 2.3.2.
@@ -51,6 +51,8 @@ typedef struct {
     double GXT, GXC, GYT, GYC, GSL;
     double fXT, fGT, fXC, fGC;
     double KI, tauI, tauII, GIc, GIIc, eta_bk;   /* interface above this ply */
+    double Sp, Kp;                    /* longitudinal shear plasticity: yield stress, hardening
+                                         modulus / G12 (Sp = 0: none) */
 } orc_material;
 
 typedef struct {
@@ -67,7 +69,8 @@ typedef struct {
 enum { ORC_DISP = 0, ORC_VEL = 1, ORC_GP_R = 2, ORC_COH_R_IP = 3,
        ORC_COH_R_BY_BOTTOM_NODE = 4, ORC_MASS = 5, ORC_COORDS = 6,
        ORC_FINT = 7, ORC_ACTIVE = 8, ORC_FIX = 9 /* set only: 3*n_nodes 0/1 */,
-       ORC_FCONTACT = 10 /* contact force found in the last step */ };
+       ORC_FCONTACT = 10 /* contact force found in the last step */,
+       ORC_GP_EP = 11 /* 3 per Gauss point: plastic gamma12, gamma13, accumulated plastic shear */ };
 
 enum { ORC_DMG_FIBRE = 0, ORC_DMG_MATRIX = 1, ORC_DMG_SHEAR = 2, ORC_DMG_COHESIVE = 3,
        ORC_DMG_PROJ_FIBRE = 4, ORC_DMG_PROJ_MATRIX = 5, ORC_DMG_PROJ_COHESIVE = 6 };
@@ -80,6 +83,8 @@ const char *orc_error(const orc_sim *s);
 int  orc_set_material(orc_sim *s, int32_t ply, const orc_material *m);
 int  orc_set_impactor(orc_sim *s, const orc_impactor *imp);
 int  orc_set_threads(orc_sim *s, int32_t n);
+/* sensitivity runs: 1 = sum nodal forces in descending element order */
+int  orc_set_assembly_order(orc_sim *s, int32_t reverse);
 int  orc_step(orc_sim *s, int64_t n);
 double orc_dt(orc_sim *s);
 int  orc_get(const orc_sim *s, int32_t kind, double *out, int64_t cap);
@@ -106,6 +111,10 @@ void orc_hex8_mass(const double X[24], double rho, double m[8]);
 /* intralaminar law: eps Voigt (eng. shear), r[4] in/out, lc crack band; sigma out, dmg[5] */
 void orc_cdm(const orc_material *m, double lc, const double eps[6], double r[4],
              double sig[6], double dmg[5]);
+/* the same with the plastic state ep[3] (in/out: plastic gamma12, gamma13,
+ * accumulated plastic shear) of Algorithm 4's first two lines */
+void orc_cdm_plastic(const orc_material *m, double lc, const double eps[6], double r[4], double ep[3],
+                     double sig[6], double dmg[5]);
 /* cohesive law: delta[3] (shear1, shear2, normal), rd in/out; tau[3]; returns D */
 double orc_czm(const orc_material *m, const double delta[3], double *rd, double tau[3]);
 /* classical RK4 on y' = f(t, y) */

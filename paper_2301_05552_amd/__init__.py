@@ -21,7 +21,7 @@ FP64, MIXED = 0, 1
 BC_CLAMPED_EDGES, BC_ASTM_WINDOW, BC_FREE = 0, 1, 2
 LAW_ELASTIC, LAW_CDM, LAW_CDM_SURROGATE = 0, 1, 2
 DMG_FIBRE, DMG_MATRIX, DMG_SHEAR, DMG_COHESIVE, DMG_PROJ_FIBRE, DMG_PROJ_MATRIX, DMG_PROJ_COHESIVE = range(7)
-ARR_DISP, ARR_VEL, ARR_GP_R, ARR_COH_R, ARR_MASS = range(5)
+ARR_DISP, ARR_VEL, ARR_GP_R, ARR_COH_R, ARR_MASS, ARR_GP_EP = range(6)
 
 EXPORTS = ["pdn_mesh_create", "pdn_material_set", "pdn_impactor_set", "pdn_step", "pdn_contact_force",
            "pdn_damage_field", "pdn_energies", "pdn_info_get", "pdn_array_get", "pdn_array_set",
@@ -48,7 +48,7 @@ class MeshDesc(C.Structure):
 
 _MAT = ["E1", "E2", "E3", "nu12", "nu13", "nu23", "G12", "G13", "G23", "rho", "law",
         "XT", "XC", "YT", "YC", "SL", "alpha0_deg", "GXT", "GXC", "GYT", "GYC", "GSL",
-        "fXT", "fGT", "fXC", "fGC", "KI", "tauI", "tauII", "GIc", "GIIc", "eta_bk"]
+        "fXT", "fGT", "fXC", "fGC", "KI", "tauI", "tauII", "GIc", "GIIc", "eta_bk", "Sp", "Kp"]
 
 
 class Material(C.Structure):
@@ -112,6 +112,7 @@ def lib():
             "pdn_surrogate_data": [C.c_int32, vp, P(Material), C.c_double, C.c_uint64, i64, i64, C.c_int32,
                                    P(C.c_float)],
             "pdn_surrogate_grad_noalloc": [C.c_int32, vp, vp, vp, vp, i64, vp, vp],
+            "pdn_stream_copy": [C.c_int32, vp, vp, vp, i64],
             "pdn_global_last_error": [],
         }
         for name, args in sig.items():
@@ -158,7 +159,8 @@ def _gchk(rc):
 
 
 def _material(m: dict) -> Material:
-    return Material(**{f: (int(m[f]) if f == "law" else float(m[f])) for f, _ in Material._fields_})
+    return Material(**{f: (int(m[f]) if f == "law" else float(m.get(f, 0.0) if f in ("Sp", "Kp") else m[f]))
+                       for f, _ in Material._fields_})
 
 
 def surrogate_train(mat: dict, crack_band: float, *, n_paths=10_000_000, increments=32, seed=SUR_SEED,
@@ -198,6 +200,13 @@ def surrogate_grad_noalloc(w_ptr: int, x_ptr: int, t_ptr: int, n: int, grad_ptr:
     """pdn_surrogate_grad_noalloc on device pointers (e.g. tensor.data_ptr());
     only enqueues the work on the stream."""
     _gchk(lib().pdn_surrogate_grad_noalloc(device, stream, w_ptr, x_ptr, t_ptr, n, grad_ptr, loss_ptr))
+
+
+def stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, device=0, stream=None):
+    """pdn_stream_copy on device pointers (enqueued on the stream)."""
+    rc = lib().pdn_stream_copy(device, stream, src_ptr, dst_ptr, nbytes)
+    if rc != 0:
+        raise PdnError(rc, "pdn_stream_copy: bad size, alignment or device")
 
 
 def surrogate_data(mat: dict, crack_band: float, p0: int, n_paths: int, increments=32, seed=SUR_SEED,

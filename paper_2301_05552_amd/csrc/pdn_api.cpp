@@ -81,6 +81,8 @@ struct pdn_ctx {
     uint4 *sur_d = nullptr;
     int n_nets = 0;
     bool use_sur = false;             // some ply evaluates a network (kernel variant)
+    bool plastic = false;             // some ply has shear plasticity (kernel variant, state ep)
+    void *ep = nullptr;               // 4 per bulk GP when plastic: gamma12_p, gamma13_p, abar, -
     int ngp = 1;                      // Gauss points of a bulk element: 1 (hourglass control) or 8
     std::vector<int> ply_net;
     double sur_dmg = 0.05, sur_res = 1e-3;
@@ -231,8 +233,13 @@ PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1, double lc_
     const double gio = m.KI > 0 ? m.tauI * m.tauI / (2 * m.KI) : 0.0;
     P.den_onset = (R)(m.KI > 0 && m.GIc > gio && m.GIIc > 0
                           ? 2.0 * gio * std::min(m.GIc, m.GIIc) / m.GIc * (1.0 - 1e-5) : -1.0);
+    P.plas = (P.law == 1 && m.Sp > 0) ? 1 : 0;
+    P.Sp = (R)m.Sp;
+    P.Hp = (R)(m.Kp * m.G12);
     return P;
 }
+
+bool ply_plastic(const pdn_material &m) { return m.law == PDN_LAW_CDM && m.Sp > 0; }
 
 bool all_set(const pdn_ctx *c)
 {
@@ -300,6 +307,20 @@ int prepare(pdn_ctx *c)
     c->use_sur = false;
     for (int p = 0; p < c->P; ++p)
         if (c->mat[p].law == PDN_LAW_CDM_SURROGATE && c->ply_net[p] >= 0) c->use_sur = true;
+    c->plastic = false;
+    for (int p = 0; p < c->P; ++p)
+        if (ply_plastic(c->mat[p])) c->plastic = true;
+    if (c->plastic) {
+        if (c->use_sur) return set_err(c, PDN_EINVAL, "shear plasticity and surrogate plies are not built together");
+        if (!pdn::tile_has_full(c->tile))
+            return set_err(c, PDN_EINVAL, "shear plasticity is built for the 15x15 and 16x16 tiles");
+        if (!c->ep) {                 // plastic state, zero at the start (Algorithm 4)
+            const size_t bytes = 4 * (size_t)std::max<int64_t>(1, c->ne) * rsize(c);
+            if ((rc = dalloc(c, &c->ep, bytes))) return rc;
+            HIPCHK(c, hipMemsetAsync(c->ep, 0, bytes, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+    }
     // crack-band range of each ply's elements (for the screen constants)
     std::vector<double> lcmin(c->P, 0.0), lcmax(c->P, 0.0);
     {
@@ -373,6 +394,7 @@ ElemArgs<R> elem_args(pdn_ctx *c, int in, int out, int contact)
     a.kappa = (R)c->kappa;
     a.d_in = c->d[in]; a.v_in = c->v[in]; a.d_out = c->d[out]; a.v_out = c->v[out];
     a.r = (R *)c->r; a.rd = (R *)c->rd;
+    a.ep = c->plastic ? (R *)c->ep : nullptr;
     a.hx = (const R *)c->hx; a.hy = (const R *)c->hy;
     a.ihx = (const R *)c->ihx; a.ihy = (const R *)c->ihy;
     a.mx = c->mx_d; a.my = c->my_d; a.mz = c->mz_d;
@@ -489,7 +511,7 @@ void free_all(pdn_ctx *c)
                   c->mx_d, c->my_d, c->mz_d, c->imx_d, c->imy_d, c->imz_d, c->cand_d,
                   c->layers_d, c->bulk_layer_d, c->coh_layer_d, c->bcb_d,
                   c->active_d, c->vprev_d, c->fcprev_d, c->fside_d, c->partials_d, c->gl_d, c->hist_d, c->dmg_d,
-                  c->sur_d};
+                  c->sur_d, c->ep};
     for (void *p : ps)
         if (p) (void)hipFree(p);
 }
@@ -746,6 +768,13 @@ int pdn_material_set(pdn_ctx *c, int32_t ply, const pdn_material *m)
         }
     }
     if (c->cohesive && m->KI < 0) return set_err(c, PDN_EINVAL, "interface penalty must be positive");
+    if (!(m->Sp >= 0 && m->Kp >= 0)) return set_err(c, PDN_EINVAL, "plasticity needs Sp >= 0 and Kp >= 0");
+    if (m->Sp > 0 && m->law == PDN_LAW_CDM_SURROGATE)
+        return set_err(c, PDN_EINVAL, "shear plasticity is built for the exact damage law, not the surrogate");
+    if (ply_plastic(*m) && m->G13 != m->G12)
+        return set_err(c, PDN_EINVAL, "shear plasticity needs an isotropic longitudinal shear plane (G13 = G12)");
+    if (ply_plastic(*m) && c->ngp != 1)
+        return set_err(c, PDN_EINVAL, "shear plasticity is built for the one-point element");
     for (int p = 0; p < c->P; ++p)
         if (ply < 0 || p == ply) { c->mat[p] = *m; c->mat_set[p] = 1; }
     c->ready = false;
@@ -981,6 +1010,7 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
     case PDN_ARR_GP_R: n = 4 * c->ngp * c->ne; break;
     case PDN_ARR_COH_R: n = c->npairs; break;
     case PDN_ARR_MASS: n = c->nn; break;
+    case PDN_ARR_GP_EP: n = 3 * c->ne; break;
     default: return set_err(c, PDN_EINVAL, "unknown array kind %d", kind);
     }
     if (n_out) *n_out = n;
@@ -1001,6 +1031,25 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
         const double *src = kind == PDN_ARR_DISP ? c->d[c->cur] : c->v[c->cur];
         HIPCHK(c, hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        return PDN_OK;
+    }
+    if (kind == PDN_ARR_GP_EP) {     // 4 per GP on the device, 3 per GP out
+        if (!c->ep) {
+            for (int64_t i = 0; i < n; ++i) out[i] = 0.0;
+            return PDN_OK;
+        }
+        std::vector<double> all(4 * c->ne);
+        if (c->precision == PDN_MIXED) {
+            std::vector<float> tmp(4 * c->ne);
+            HIPCHK(c, hipMemcpyAsync(tmp.data(), c->ep, tmp.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            for (size_t i = 0; i < tmp.size(); ++i) all[i] = tmp[i];
+        } else {
+            HIPCHK(c, hipMemcpyAsync(all.data(), c->ep, all.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+        for (int64_t e = 0; e < c->ne; ++e)
+            for (int q = 0; q < 3; ++q) out[3 * e + q] = all[4 * e + q];
         return PDN_OK;
     }
     const void *src = kind == PDN_ARR_GP_R ? c->r : c->rd;
@@ -1025,6 +1074,10 @@ int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
     case PDN_ARR_DISP: case PDN_ARR_VEL: need = 3 * c->nn; break;
     case PDN_ARR_GP_R: need = 4 * c->ngp * c->ne; break;
     case PDN_ARR_COH_R: need = c->npairs; break;
+    case PDN_ARR_GP_EP:
+        need = 3 * c->ne;
+        if (!c->ep) return set_err(c, PDN_EINVAL, "no plastic state: no ply has shear plasticity (or no step yet)");
+        break;
     default: return set_err(c, PDN_EINVAL, "array kind %d cannot be set", kind);
     }
     if (n != need) return set_err(c, PDN_EINVAL, "array needs %lld values, got %lld", (long long)need, (long long)n);
@@ -1048,6 +1101,20 @@ int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
         double *dst = kind == PDN_ARR_DISP ? c->d[c->cur] : c->v[c->cur];
         HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else if (kind == PDN_ARR_GP_EP) {
+        if (c->precision == PDN_MIXED) {
+            std::vector<float> tmp(4 * c->ne, 0.0f);
+            for (int64_t e = 0; e < c->ne; ++e)
+                for (int q = 0; q < 3; ++q) tmp[4 * e + q] = (float)in[3 * e + q];
+            HIPCHK(c, hipMemcpyAsync(c->ep, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        } else {
+            std::vector<double> tmp(4 * c->ne, 0.0);
+            for (int64_t e = 0; e < c->ne; ++e)
+                for (int q = 0; q < 3; ++q) tmp[4 * e + q] = in[3 * e + q];
+            HIPCHK(c, hipMemcpyAsync(c->ep, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
     } else {
         void *dst = kind == PDN_ARR_GP_R ? c->r : c->rd;
         if (c->precision == PDN_MIXED) {
@@ -1092,8 +1159,9 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     const size_t rs = rsize(c);
     const int64_t ncand = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
     const int64_t hn = c->gl.step;
+    const size_t eps_bytes = c->plastic ? 4 * c->ne * rs : 0;
     const size_t need = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) +
-                        4 * c->ngp * c->ne * rs +
+                        4 * c->ngp * c->ne * rs + eps_bytes +
                         c->npairs * rs + ncand * (1 + 6 * sizeof(double)) + 3 * hn * sizeof(double);
     if (n_out) *n_out = (int64_t)need;
     if (cap < (int64_t)need || !buf) return set_err(c, PDN_ERANGE, "checkpoint needs %zu bytes", need);
@@ -1102,7 +1170,7 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     if (!rc) rc = materialize(c);
     if (rc) return rc;
     char *p = (char *)buf;
-    BlobHeader h{kMagic, c->nn, c->ne, c->npairs, ncand, hn, c->precision, 0, c->ngp, 0};
+    BlobHeader h{kMagic, c->nn, c->ne, c->npairs, ncand, hn, c->precision, 0, c->ngp, c->plastic ? 1 : 0};
     std::memcpy(p, &h, sizeof h); p += sizeof h;
     std::memcpy(p, &c->gl, sizeof(DevGlobals)); p += sizeof(DevGlobals);
     auto d2h = [&](const void *src, size_t bytes) -> int {
@@ -1114,6 +1182,7 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     if ((rc = d2h(c->d[c->cur], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = d2h(c->v[c->cur], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = d2h(c->r, 4 * c->ngp * c->ne * rs))) return rc;
+    if (eps_bytes && (rc = d2h(c->ep, eps_bytes))) return rc;
     if ((rc = d2h(c->rd, c->npairs * rs))) return rc;
     if ((rc = d2h(c->active_d + (size_t)(1 - c->cur) * ncand, ncand))) return rc;   // read by the next step
     if ((rc = d2h(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
@@ -1132,14 +1201,17 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     BlobHeader h;
     std::memcpy(&h, p, sizeof h); p += sizeof h;
     const int64_t ncand = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
+    bool plas = false;
+    for (int p = 0; p < c->P; ++p) plas = plas || ply_plastic(c->mat[p]);
     if (h.magic != kMagic || h.nn != c->nn || h.ne != c->ne || h.npairs != c->npairs || h.ncand != ncand ||
-        h.precision != c->precision || h.ngp != c->ngp)
+        h.precision != c->precision || h.ngp != c->ngp || h.pad != (plas ? 1 : 0))
         return set_err(c, PDN_EINVAL, "checkpoint does not match this context");
     // the blob must be exactly what pdn_state_save writes for this context and
     // history length; nothing is read or changed before this holds
     const size_t rs = rsize(c);
+    const size_t eps_bytes = plas ? 4 * c->ne * rs : 0;
     const size_t fixed = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) +
-                         4 * c->ngp * c->ne * rs + c->npairs * rs + ncand * (1 + 6 * sizeof(double));
+                         4 * c->ngp * c->ne * rs + eps_bytes + c->npairs * rs + ncand * (1 + 6 * sizeof(double));
     if (h.hist_n < 0 || (uint64_t)h.hist_n > ((uint64_t)INT64_MAX - fixed) / (3 * sizeof(double)))
         return set_err(c, PDN_EINVAL, "checkpoint history length %lld is invalid", (long long)h.hist_n);
     const size_t need = fixed + 3 * (size_t)h.hist_n * sizeof(double);
@@ -1165,6 +1237,7 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     if ((rc = h2d(c->d[0], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = h2d(c->v[0], 3 * c->nn * sizeof(double)))) return rc;
     if ((rc = h2d(c->r, 4 * c->ngp * c->ne * rs))) return rc;
+    if (eps_bytes && (rc = h2d(c->ep, eps_bytes))) return rc;
     if ((rc = h2d(c->rd, c->npairs * rs))) return rc;
     if ((rc = h2d(c->active_d + ncand, ncand))) return rc;            // cur = 0: the next step reads set 1
     if ((rc = h2d(c->vprev_d, 3 * ncand * sizeof(double)))) return rc;
@@ -1483,7 +1556,9 @@ int pdn_autotune(pdn_ctx *c, int32_t *tile_x, int32_t *tile_y)
     if (c->broken) return set_err(c, PDN_EUNSTABLE, "context is unstable");
     if (!all_set(c) || !c->have_imp) return set_err(c, PDN_ESTATE, "materials and striker must be set first");
     (void)hipSetDevice(c->device);
-    const std::string key = "1|" + shape_key(c);
+    bool plas = false;
+    for (int p = 0; p < c->P; ++p) plas = plas || ply_plastic(c->mat[p]);
+    const std::string key = std::string(plas ? "1p|" : "1|") + shape_key(c);
     auto it = tune_cache().find(key);
     int best = -1, rc;
     if (it != tune_cache().end()) {
@@ -1491,7 +1566,7 @@ int pdn_autotune(pdn_ctx *c, int32_t *tile_x, int32_t *tile_y)
     } else {
         float best_ms = 0;
         for (int t : kTileOrder) {
-            if (!tile_fits(c, t) || (c->ngp == 8 && !pdn::tile_has_full(t))) continue;
+            if (!tile_fits(c, t) || ((c->ngp == 8 || plas) && !pdn::tile_has_full(t))) continue;
             float ms = 0;
             if ((rc = use_tile(c, t)) || (rc = time_single(c, 3, &ms))) return rc;
             if (best < 0 || ms < best_ms) { best = t; best_ms = ms; }
@@ -1522,6 +1597,9 @@ int pdn_batch_create(pdn_ctx *const *cases, int32_t n, pdn_batch **out)
         if (c->device != cases[0]->device || c->precision != cases[0]->precision || c->ngp != cases[0]->ngp)
             return set_err(cases[0], PDN_EINVAL,
                            "case %d: batched cases must share device, precision and element integration", i);
+        for (int p = 0; p < c->P; ++p)
+            if (ply_plastic(c->mat[p]))
+                return set_err(cases[0], PDN_EINVAL, "case %d: shear plasticity is not built for batches", i);
     }
     pdn_batch *b = new pdn_batch;
     b->cs.assign(cases, cases + n);
@@ -1934,6 +2012,9 @@ int pdn_surrogate_set(pdn_ctx *c, int32_t ply, const float *weights, int64_t n, 
     for (int p = 0; p < c->P; ++p)
         if ((ply < 0 || p == ply) && (!c->mat_set[p] || c->mat[p].law == PDN_LAW_ELASTIC))
             return set_err(c, PDN_ESTATE, "ply %d has no damage law to replace", p);
+    for (int p = 0; p < c->P; ++p)
+        if (c->mat_set[p] && c->mat[p].Sp > 0)
+            return set_err(c, PDN_EINVAL, "surrogate plies and shear plasticity are not built together (ply %d)", p);
     (void)hipSetDevice(c->device);
     // grow the network table by one
     uint4 *nd = nullptr;

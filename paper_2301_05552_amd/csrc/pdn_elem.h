@@ -164,9 +164,10 @@ __device__ __forceinline__ void store_state<float>(float *r, int64_t e, const fl
 // (= F - I, row-major), ply frame, law (thresholds r), back to the global
 // frame, nominal stress Pn = F S (row-major).  Returns S:E in the ply frame
 // (twice the secant energy density).
-template <typename R, bool SUR>
+template <typename R, bool SUR, bool PLAS = false>
 __device__ __forceinline__ R box_point(const R G[9], const PlyC<R> &P, R vol, R r[4], bool &changed, R Pn[9],
-                                       const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact)
+                                       const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact,
+                                       R *ep = nullptr, bool *pchanged = nullptr)
 {
     const R G00 = G[0], G01 = G[1], G02 = G[2], G10 = G[3], G11 = G[4], G12 = G[5];
     const R G20 = G[6], G21 = G[7], G22 = G[8];
@@ -188,6 +189,11 @@ __device__ __forceinline__ R box_point(const R G[9], const PlyC<R> &P, R vol, R 
     e[5] = R(2) * (-cs * E00 + (cc - ss) * E01 + cs * E11);
     R sg[6];
     exact = 0;
+    if constexpr (PLAS) {
+        // plastic strains first; e becomes the elastic strain (its energy is
+        // the recoverable one returned below)
+        *pchanged = P.plas ? plastic_return(P, e, ep) : false;
+    }
     if constexpr (SUR) {
         if (P.law == 2)
             sur_update(P, vol, e, r, sg, changed, sur_pk + (int64_t)P.sur * (SUR_PACK_BYTES / 16), sur_dmg, sur_res,
@@ -219,12 +225,13 @@ __device__ __forceinline__ R box_point(const R G[9], const PlyC<R> &P, R vol, R 
 }
 
 // One point with hourglass control.  Returns the force coefficients on the
-// corner basis (forces = inv8 of each).
-template <typename R, bool SUR>
+// corner basis (forces = inv8 of each).  PLAS: ep is the point's plastic state.
+template <typename R, bool SUR, bool PLAS = false>
 __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
                               R ihx, R ihy, R ihz, const PlyC<R> &P, R kappa, R r[4], bool &changed,
                               Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel,
-                              const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact)
+                              const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact,
+                              R *ep = nullptr, bool *pchanged = nullptr)
 {
     Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
     const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
@@ -233,7 +240,7 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
                     sz.xi * gx, sz.eta * gy, sz.zeta * gz};
     const R vol = hx * hy * hz;
     R Pn[9];
-    const R w = box_point<R, SUR>(G, P, vol, r, changed, Pn, sur_pk, sur_dmg, sur_res, exact);
+    const R w = box_point<R, SUR, PLAS>(G, P, vol, r, changed, Pn, sur_pk, sur_dmg, sur_res, exact, ep, pchanged);
     const R ax = R(0.25) * hy * hz, ay = R(0.25) * hx * hz, az = R(0.25) * hx * hy;
     // hourglass: k = kappa Cmax V sum b^2 / 3, q = s/8, force coefficient k s / 64
     const R khg = kappa * P.cmax * vol * (ihx * ihx + ihy * ihy + ihz * ihz) * R(1.0 / 6.0);
@@ -524,8 +531,9 @@ __device__ void contact_books(const ElemArgs<R> &A, double *sh)
 
 // one workgroup's tile of one plate; block partials go to A.partials[tile].
 // SUR: plies with law 2 use the surrogate network (a separate instantiation,
-// so that the plain path keeps its register budget)
-template <typename R, int TX, int TY, bool SUR, int NGP>
+// so that the plain path keeps its register budget); PLAS: plies with shear
+// plasticity carry their plastic state (another instantiation, one point)
+template <typename R, int TX, int TY, bool SUR, int NGP, bool PLAS = false>
 __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int tile)
 {
     // element slots follow the node rows: element (a, b) is slot a + NCX b,
@@ -625,12 +633,14 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     // Values of lanes without an element or node pair, or of an elastic ply,
     // are not used.
     R rdn = R(0);
+    R epn[4] = {R(0), R(0), R(0), R(0)};   // plastic state of the element in layer l (PLAS)
     auto fetch_r = [&](int l) {
         const LayerInfo Lr = cload(A.layers + rmin(l, A.NL - 1));
         const int lt = uni(Lr.type), li = uni(Lr.index);
         const int64_t eidx = lt == 0 ? iv + (int64_t)nx * (jv + (int64_t)ny * li) : 0;
         const int64_t pidx = lt == 0 ? 0 : (nvalid ? col : 0) + plane * li;
         if constexpr (NGP == 1) load_state(A.r, eidx, rn);
+        if constexpr (PLAS) load_state(A.ep, eidx, epn);
         rdn = A.rd[pidx];
     };
 
@@ -752,6 +762,7 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         const R lhz = (R)uni(Lk.hz), lihz = (R)uni(Lk.ihz);
         stage_plane(S, k, pd, pv);
         R r[4] = {rn[0], rn[1], rn[2], rn[3]};
+        R ep[4] = {epn[0], epn[1], epn[2], epn[3]};
         const R rdl = rdn;
         // thresholds first: the wait for them next layer then leaves the plane
         // loads (issued after them) in flight
@@ -784,10 +795,15 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                                           cm[1], cm[2], uel);
                     if (eown) acc[T_UEL] += (double)uel;
                 } else {
-                    hex_box_force<R, SUR>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.kappa, r, changed,
-                                          cm[0], cm[1], cm[2], uel, A.mlp, A.sur_dmg, A.sur_res, exact);
+                    bool pchanged = false;
+                    hex_box_force<R, SUR, PLAS>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.kappa, r,
+                                                changed, cm[0], cm[1], cm[2], uel, A.mlp, A.sur_dmg, A.sur_res,
+                                                exact, ep, &pchanged);
                     if (eown) {
                         if (changed) store_state(A.r, ie + (int64_t)nx * (je + (int64_t)ny * lidx), r);
+                        if constexpr (PLAS) {
+                            if (pchanged) store_state(A.ep, ie + (int64_t)nx * (je + (int64_t)ny * lidx), ep);
+                        }
                         acc[T_UEL] += (double)uel;
                         if (P.law == 2) {
                             acc[T_AUX] += exact == 1 ? 1.0 : 0.0;      // fallback after consulting the network
@@ -996,11 +1012,11 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
 // runs at 1 wave per SIMD even where no point reaches the network.  The
 // spills this costs sit around the network evaluation; the plain build
 // (bound 1, the default) is unaffected.
-template <typename R, int TX, int TY, bool SUR, int NGP = 1>
+template <typename R, int TX, int TY, bool SUR, int NGP = 1, bool PLAS = false>
 __global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY)) __attribute__((amdgpu_waves_per_eu(SUR ? 2 : 1)))
 void k_elem_node(ElemArgs<R> A)
 {
-    elem_node_tile<R, TX, TY, SUR, NGP>(A, xcd_tile(blockIdx.x, gridDim.x));
+    elem_node_tile<R, TX, TY, SUR, NGP, PLAS>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // many plates in one launch: case c has start[c+1] - start[c] tiles.  After
@@ -1037,11 +1053,11 @@ __global__ __launch_bounds__(PDN_BOOKS_THREADS) void k_books_batch(const ElemArg
 // ---------------------------------------------------------------------------
 // launchers of one variant
 // ---------------------------------------------------------------------------
-template <typename R, int TX, int TY, bool SUR, int NGP = 1>
+template <typename R, int TX, int TY, bool SUR, int NGP = 1, bool PLAS = false>
 static hipError_t launch_en(const ElemArgs<R> &a, hipStream_t s)
 {
     const int nb = a.tiles_x * a.tiles_y;
-    hipLaunchKernelGGL((k_elem_node<R, TX, TY, SUR, NGP>), dim3(nb), dim3(PDN_TILE_THREADS(TX, TY)), 0, s, a);
+    hipLaunchKernelGGL((k_elem_node<R, TX, TY, SUR, NGP, PLAS>), dim3(nb), dim3(PDN_TILE_THREADS(TX, TY)), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1099,6 +1115,17 @@ static hipError_t launch_elem_node_batch_v(const ElemArgs<R> *args, const int *s
     case PDN_TILE_8x8: return launch_enb<R, 8, 8, SUR>(args, start, ncase, nblocks, s);
     case PDN_TILE_15x15: return launch_enb<R, 15, 15, SUR>(args, start, ncase, nblocks, s);
     case PDN_TILE_31x15: return launch_enb<R, 31, 15, SUR>(args, start, ncase, nblocks, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// shear plasticity (one point): the tiles it is built for
+template <typename R>
+static hipError_t launch_elem_node_plas_v(const ElemArgs<R> &a, int tile, hipStream_t s)
+{
+    switch (tile) {
+    case PDN_TILE_16x16: return launch_en<R, 16, 16, false, 1, true>(a, s);
+    case PDN_TILE_15x15: return launch_en<R, 15, 15, false, 1, true>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -42,6 +42,10 @@ struct PlyC {
     R KI, Ksh, tauI, GIc, GIIc, eta_bk, GIo;
     R den_onset;                                     // screen of the cohesive law: below onset at any mixity
     R kE1XT, iYT, iSL;                               // surrogate input scales: E1/XT, 1/YT, 1/SL (uncapped)
+    // longitudinal shear plasticity: yield stress, plastic modulus Kp G12;
+    // plas = 1 on a ply with the exact damage law and Sp > 0
+    R Sp, Hp;
+    int plas;
 };
 
 // Layer table: layer l joins node planes l and l+1.
@@ -86,6 +90,8 @@ struct ElemArgs {
     const double *d_in, *v_in;       // state at level n (AoS xyz)
     double *d_out, *v_out;           // predictor for level n+1
     R *r;                            // 4 per bulk GP
+    R *ep;                           // 4 per bulk GP (plastic gamma12, gamma13, accumulated, unused);
+                                     // null unless a ply is plastic (then the plastic kernel runs)
     R *rd;                           // 1 per cohesive node pair
     const R *hx, *hy;                // element sizes (nx, ny)
     const R *ihx, *ihy;              // their reciprocals

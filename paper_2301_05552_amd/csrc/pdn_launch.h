@@ -26,6 +26,9 @@ namespace pdn {
 // ngp: Gauss points of a bulk element (1 with hourglass control, or 8)
 template <typename R>
 hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, int ngp, hipStream_t s);
+// shear plasticity (one point, a.ep non-null): built for the 15x15 and 16x16 tiles
+template <typename R>
+hipError_t launch_elem_node_plas(const ElemArgs<R> &a, int tile, hipStream_t s);
 // full integration (ngp 8): built for the 15x15 and 16x16 tiles
 template <typename R>
 hipError_t launch_elem_node_full(const ElemArgs<R> &a, int tile, hipStream_t s);

@@ -127,6 +127,35 @@ __device__ __forceinline__ bool cdm_screen(const PlyC<R> &P, R vol, const R e[6]
     return !grow && r[0] <= R(1) && r[1] <= R(1) && r[2] <= R(1) && r[3] <= R(1);
 }
 
+// Algorithm 4, first two lines: the plastic strains of the longitudinal shear
+// (linear isotropic hardening in effective stress: yield when tau_L >
+// Sp + Hp abar, tau_L = |(tau12, tau13)|, G13 = G12; radial return), then the
+// elastic strains e - e_p in place.  ep = {gamma12_p, gamma13_p, abar, -}.
+// The flow test has a rounding allowance, and the elastic strains are formed
+// from the updated plastic strains: evaluating the point again from its
+// updated state then gives the same answer bit for bit (a rim element is
+// evaluated by two workgroups, one of which may read the updated state).
+// Returns true when the plastic state changed.
+template <typename R>
+__device__ __forceinline__ bool plastic_return(const PlyC<R> &P, R e[6], R ep[4])
+{
+    const R G = P.G12;
+    const R t12 = G * (e[5] - ep[0]), t13 = G * (e[4] - ep[1]);
+    const R tL = sqrt(t12 * t12 + t13 * t13);
+    const R Y = P.Sp + P.Hp * ep[2];
+    const R F = tL - Y;
+    const bool flow = F > (sizeof(R) == 4 ? R(1e-5) : R(1e-12)) * Y;
+    if (flow) {
+        const R dl = F / (G + P.Hp);
+        ep[0] += dl * t12 / tL;
+        ep[1] += dl * t13 / tL;
+        ep[2] += dl;
+    }
+    e[5] = e[5] - ep[0];
+    e[4] = e[4] - ep[1];
+    return flow;
+}
+
 // eps: material-frame Green strain (Voigt 11,22,33,23,13,12, engineering shear)
 // r: thresholds r1+, r1-, r2+, r2- (in/out).  Returns nominal PK2 stress.
 template <typename R>

@@ -698,6 +698,194 @@ def test_cdm_uniaxial_compression_fracture_plane_is_alpha0():
 
 
 # ---------------------------------------------------------------------------
+# longitudinal shear plasticity (Algorithm 4, first two lines; Table 1 S_p, K_p)
+# ---------------------------------------------------------------------------
+
+def _plastic_mat(outer=True):
+    m = W.material_cfrp(outer, 0.5e-3, plastic=True)
+    assert m["Sp"] == 62.0e6 and m["Kp"] == 0.1936 and m["G13"] == m["G12"]
+    return m
+
+
+def _shear_path(m, gammas, direction=(1.0, 0.0)):
+    """Strain path of longitudinal shear gamma along (gamma12, gamma13) =
+    gamma * direction; returns tau_L along the direction, the states."""
+    r, ep = np.ones(4), np.zeros(3)
+    taus, eps_p, rs = [], [], []
+    c, s_ = direction
+    for g in gammas:
+        e = np.zeros(6)
+        e[5], e[4] = c * g, s_ * g
+        sig, r, ep, _ = oracle.cdm_plastic(m, LC3, e, r, ep)
+        taus.append(c * sig[5] + s_ * sig[4])
+        eps_p.append(ep.copy())
+        rs.append(r.copy())
+    return np.array(taus), np.array(eps_p), np.array(rs)
+
+
+def test_plastic_shear_yields_at_Sp_and_hardens_linearly():
+    """Monotone in-plane shear below damage onset: elastic slope G12 up to the
+    yield stress S_p, then tau = S_p + H gamma_p with gamma_p growing as
+    (G12 gamma - S_p) / (G12 + H), H = K_p G12 (linear isotropic hardening),
+    i.e. the tangent G12 H / (G12 + H); the accumulated plastic shear equals
+    gamma_p on a monotone path; no damage."""
+    m = _plastic_mat()
+    G, H, Sp = m["G12"], m["Kp"] * m["G12"], m["Sp"]
+    g_top = (0.9 * m["SL"] - Sp) / H + 0.9 * m["SL"] / G         # tau reaches 0.9 S_L
+    gam = np.linspace(0.0, g_top, 801)[1:]
+    tau, ep, rs = _shear_path(m, gam)
+    el = gam <= Sp / G
+    assert el.sum() > 50 and (~el).sum() > 50
+    assert np.allclose(tau[el], G * gam[el], rtol=1e-13, atol=0)
+    assert (ep[el] == 0).all()
+    want = Sp + (G * gam[~el] - Sp) * H / (G + H)
+    assert np.abs(tau[~el] - want).max() <= 1e-11 * Sp
+    gp = (G * gam[~el] - Sp) / (G + H)
+    assert np.abs(ep[~el, 0] - gp).max() <= 1e-12 * gp.max()
+    assert np.abs(ep[~el, 2] - ep[~el, 0]).max() <= 1e-15 * gp.max()
+    assert (ep[:, 1] == 0).all() and (rs == 1).all()
+    assert tau.max() < m["SL"]
+
+
+def test_plastic_unloading_keeps_plastic_strain_and_reverse_yield_is_isotropic():
+    """Load past yield, unload: the slope is G12, no further plastic strain,
+    and the stress vanishes at gamma = gamma_p (the plastic strain is kept).
+    Reverse loading yields at -(S_p + H abar) (isotropic hardening)."""
+    m = _plastic_mat()
+    G, H, Sp = m["G12"], m["Kp"] * m["G12"], m["Sp"]
+    g1 = 0.02
+    up = np.linspace(0.0, g1, 401)[1:]
+    tau_up, ep_up, _ = _shear_path(m, up)
+    gp1, t1 = ep_up[-1, 0], tau_up[-1]
+    assert gp1 > 0 and abs(t1 - (Sp + H * gp1)) <= 1e-11 * Sp
+    r, ep = np.ones(4), ep_up[-1].copy()
+    # unload to zero stress (gamma = gamma_p) and on to just before reverse yield
+    g_rev = gp1 - (Sp + H * gp1) / G
+    down = np.linspace(g1, g_rev * 0.999 + gp1 * 0.001, 400)
+    for g in down:
+        e = np.zeros(6)
+        e[5] = g
+        sig, r, ep2, _ = oracle.cdm_plastic(m, LC3, e, r, ep)
+        assert np.array_equal(ep2, ep)                           # elastic unloading
+        assert abs(sig[5] - G * (g - gp1)) <= 1e-9 * Sp
+    e = np.zeros(6)
+    e[5] = gp1
+    sig, _, _, _ = oracle.cdm_plastic(m, LC3, e, r, ep)
+    assert abs(sig[5]) <= 1e-9 * Sp                              # zero stress at gamma = gamma_p
+    # reverse: yields at -(S_p + H abar)
+    e[5] = g_rev * 1.001 - gp1 * 0.001
+    sig, _, ep3, _ = oracle.cdm_plastic(m, LC3, e, r, ep)
+    assert ep3[0] < gp1 and ep3[2] > ep[2]
+    assert abs(sig[5] + (Sp + H * ep3[2])) <= 1e-9 * Sp
+
+
+def test_plastic_dissipation_of_a_load_unload_cycle():
+    """Loading to gamma_1 and unloading to zero stress dissipates
+    S_p gamma_p + H gamma_p^2 / 2 per unit volume (the work of the yield
+    stress on the plastic strain); the elastic energy is recovered."""
+    m = _plastic_mat()
+    G, H, Sp = m["G12"], m["Kp"] * m["G12"], m["Sp"]
+    g1 = 0.025
+    up = np.linspace(0.0, g1, 20001)
+    tau_up, ep_up, _ = _shear_path(m, up)
+    gp = ep_up[-1, 0]
+    down = np.linspace(g1, gp, 2001)
+    r, ep = np.ones(4), ep_up[-1].copy()
+    tau_dn = []
+    for g in down:
+        e = np.zeros(6)
+        e[5] = g
+        sig, r, ep, _ = oracle.cdm_plastic(m, LC3, e, r, ep)
+        tau_dn.append(sig[5])
+    work = np.trapezoid(tau_up, up) + np.trapezoid(np.array(tau_dn), down)
+    want = Sp * gp + 0.5 * H * gp * gp
+    assert abs(work - want) <= 1e-6 * want
+
+
+def test_plastic_shear_plane_is_isotropic():
+    """G13 = G12: longitudinal shear along any direction of the (12, 13)
+    plane follows the same tau_L - gamma_L curve, and the plastic strain is
+    along the loading direction."""
+    m = _plastic_mat()
+    gam = np.linspace(0.0, 0.03, 301)[1:]
+    t0, ep0, _ = _shear_path(m, gam)
+    for beta in (0.4, 1.1, 2.5):
+        d = (math.cos(beta), math.sin(beta))
+        t, ep, _ = _shear_path(m, gam, d)
+        assert np.abs(t - t0).max() <= 1e-12 * m["Sp"]
+        assert np.abs(ep[:, 0] - d[0] * ep0[:, 0]).max() <= 1e-14 and np.abs(ep[:, 1] - d[1] * ep0[:, 0]).max() <= 1e-14
+        assert np.abs(ep[:, 2] - ep0[:, 2]).max() <= 1e-14
+
+
+def test_plastic_strain_comes_before_the_damage_criteria():
+    """Algorithm 4's order: plastic strains, elastic strains, effective stress,
+    criteria.  Under pure shear the shear criterion sees the effective stress
+    of the elastic strain, so damage sets in at the total strain
+    S_L / G12 + (S_L - S_p) / H (the hardening has lifted the stress to S_L),
+    not at S_L / G12."""
+    m = _plastic_mat()
+    G, H, Sp, SL = m["G12"], m["Kp"] * m["G12"], m["Sp"], m["SL"]
+    want = SL / G + (SL - Sp) / H
+    lo, hi = 0.5 * want, 1.5 * want
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        n = 64
+        tau, ep, rs = _shear_path(m, np.linspace(0.0, mid, n + 1)[1:])
+        if rs[-1, 2] > 1.0:
+            hi = mid
+        else:
+            lo = mid
+        if hi - lo <= 1e-13 * want:
+            break
+    assert abs(hi - want) <= 1e-9 * want
+
+
+def test_plasticity_off_is_the_elastic_damage_law():
+    """With S_p = 0 the law is the elastic-damage law exactly, and with
+    plasticity on, strains below yield give the same answers bit for bit."""
+    m0 = W.material_cfrp(True, 0.5e-3)
+    mp = _plastic_mat()
+    rs = np.random.default_rng(31)
+    for _ in range(300):
+        e = rs.standard_normal(6) * np.array([4e-3, 6e-3, 4e-3, 8e-3, 8e-3, 8e-3]) * rs.uniform(0.05, 2.0)
+        r0 = 1.0 + rs.uniform(0.0, 0.5, 4) * (rs.uniform() < 0.5)
+        a = oracle.cdm(m0, LC3, e, r0)
+        b = oracle.cdm_plastic(m0, LC3, e, r0, np.zeros(3))
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and (b[2] == 0).all()
+        tL = m0["G12"] * math.hypot(e[4], e[5])
+        if tL < mp["Sp"]:
+            c = oracle.cdm_plastic(mp, LC3, e, r0, np.zeros(3))
+            assert np.array_equal(a[0], c[0]) and (c[2] == 0).all()
+
+
+def test_plastic_plate_energy_identity():
+    """A small laminate struck hard enough to yield in shear: the energy
+    identity closes to 1e-6 of the impact energy, the plastic strains are
+    non-zero, and the dissipated work W_int - U_el (U_el: energy of the elastic
+    strains) is non-negative and grows."""
+    cfg = W.tiny(8, 8, 4, 1, angles=[0, 45, -45, 90], law=W.LAW_CDM, lx=8e-3, ly=8e-3,
+                 ply_thickness=0.25e-3, v0=12.0, mass=0.05, R=3e-3, plastic=True)
+    o = oracle.Oracle(cfg)
+    dis = []
+    for _ in range(6):
+        o.step(100)
+        e = o.energies()
+        assert abs(e["residual"]) <= 1e-6 * e["ke0"]
+        dis.append(e["w_int"] - e["u_el"])
+    ep = o.get(oracle.GP_EP).reshape(-1, 3)
+    assert ep[:, 2].max() > 0
+    assert min(dis) >= -1e-9 * o.energies()["ke0"]
+    assert dis[-1] > dis[0]
+
+
+def test_plasticity_needs_an_isotropic_shear_plane():
+    cfg = W.tiny(2, 2, 1, 1, law=W.LAW_CDM, plastic=True)
+    cfg["materials"][0]["G13"] = 0.9 * cfg["materials"][0]["G12"]
+    with pytest.raises(oracle.OracleError):
+        oracle.Oracle(cfg)
+
+
+# ---------------------------------------------------------------------------
 # cohesive law (Algorithm 5 reading)
 # ---------------------------------------------------------------------------
 

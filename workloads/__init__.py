@@ -83,16 +83,23 @@ def material_isotropic(E: float, nu: float, rho: float) -> dict:
                 XT=0.0, XC=0.0, YT=0.0, YC=0.0, SL=0.0, alpha0_deg=53.0,
                 GXT=0.0, GXC=0.0, GYT=0.0, GYC=0.0, GSL=0.0,
                 fXT=0.0, fGT=0.0, fXC=0.0, fGC=0.0,
-                KI=0.0, tauI=0.0, tauII=0.0, GIc=0.0, GIIc=0.0, eta_bk=1.0)
+                KI=0.0, tauI=0.0, tauII=0.0, GIc=0.0, GIIc=0.0, eta_bk=1.0, Sp=0.0, Kp=0.0)
 
 
-def material_cfrp(outer: bool, ply_thickness: float, law: int = LAW_CDM) -> dict:
+# Table 1, Hexply AS4/8552, matrix plasticity: yield stress S_p (MPa) and the
+# hardening K_p (printed in N/mm; read as the plastic modulus over G12)
+AS4_SP = 62.0e6
+AS4_KP = 0.1936
+
+
+def material_cfrp(outer: bool, ply_thickness: float, law: int = LAW_CDM, plastic: bool = False) -> dict:
     """Carbon/epoxy ply: workload elastic constants + Table 1 AS4/8552 damage data.
 
     ``outer`` selects the outer-ply in-situ strengths (Y_T = 74.2, S_L = 94.4 MPa)
     instead of the embedded-ply ones (Y_T = 117.5, S_L = 120.8 MPa).  The
     interface penalty is K_I = 50 E2 / t_ply (Section 2.3.2's lower bound), since
-    Table 1's AS4 value violates that bound.
+    Table 1's AS4 value violates that bound.  ``plastic`` adds Table 1's
+    longitudinal shear plasticity (S_p, K_p); off, the law is elastic-damage.
     """
     E2 = 8.0e9
     nu23 = 0.45
@@ -105,12 +112,13 @@ def material_cfrp(outer: bool, ply_thickness: float, law: int = LAW_CDM) -> dict
              GXT=81.5e3, GXC=106.3e3, GYT=280.0, GYC=1313.0, GSL=790.0,
              fXT=0.1, fGT=0.6, fXC=0.1, fGC=0.9,
              KI=50.0 * E2 / ply_thickness, tauI=74.2e6, tauII=94.36e6,
-             GIc=280.0, GIIc=790.0, eta_bk=1.45)
+             GIc=280.0, GIIc=790.0, eta_bk=1.45,
+             Sp=(AS4_SP if plastic else 0.0), Kp=(AS4_KP if plastic else 0.0))
     return m
 
 
-def ply_materials(n_plies: int, ply_thickness: float, law: int = LAW_CDM) -> list:
-    return [material_cfrp(p == 0 or p == n_plies - 1, ply_thickness, law)
+def ply_materials(n_plies: int, ply_thickness: float, law: int = LAW_CDM, plastic: bool = False) -> list:
+    return [material_cfrp(p == 0 or p == n_plies - 1, ply_thickness, law, plastic)
             for p in range(n_plies)]
 
 
@@ -177,6 +185,22 @@ def plate_qi8_1200x800x16(precision=PREC_MIXED) -> dict:
         steps=20000)
 
 
+def plate_qi8_150x100x16_cut(precision=PREC_FP64) -> dict:
+    """A 150 x 100-column cut of the 1200 x 800 x 16 plate at its element size
+    (0.125 x 0.125 x 0.25 mm, 18.75 x 12.5 mm), with its 6 cohesive
+    interfaces, its striker (R = 8 mm, 5.5 kg at 25 J) and its support type:
+    the window and the corner clamp discs scaled with the plate (window
+    125/150 x 75/100 of the cut, clamp radius 5 mm x 18.75/150)."""
+    c = plate_qi8_1200x800x16(precision)
+    c["name"] = "cdm-czm-qi8-150x100x16-cut"
+    m = c["mesh"]
+    f = 150.0 / 1200.0
+    m.update(nx=150, ny=100, lx=0.150 * f, ly=0.100 * f, window_lx=0.125 * f, window_ly=0.075 * f,
+             clamp_radius=5.0e-3 * f)
+    c["steps"] = 2000
+    return c
+
+
 def plate_qi8_1200x800x16_surrogate(precision=PREC_MIXED) -> dict:
     c = plate_qi8_1200x800x16(precision)
     c["name"] = "surrogate-qi8-1200x800x16"
@@ -195,7 +219,7 @@ AS4_PLY = 0.181e-3
 AS4_CLUSTERS = [45, 0, -45, 90, 90, -45, 0, 45]
 
 
-def material_as4_8552(outer: bool, t_lam: float, law: int = LAW_CDM) -> dict:
+def material_as4_8552(outer: bool, t_lam: float, law: int = LAW_CDM, plastic: bool = False) -> dict:
     """Table 1, Hexply AS4/8552 column, in SI.  ``outer`` selects the outer
     cluster's in-situ strengths (Y_T = 74.2, S_L = 94.4 MPa) instead of the
     embedded ones (Y_T = 117.5, S_L = 120.8 MPa; the same for 4- and 8-ply
@@ -211,13 +235,15 @@ def material_as4_8552(outer: bool, t_lam: float, law: int = LAW_CDM) -> dict:
                 GXT=81.5e3, GXC=106.3e3, GYT=280.0, GYC=1313.0, GSL=790.0,
                 fXT=0.1, fGT=0.6, fXC=0.1, fGC=0.9,
                 KI=50.0 * E2 / t_lam, tauI=74.2e6, tauII=94.36e6,
-                GIc=280.0, GIIc=790.0, eta_bk=1.45)
+                GIc=280.0, GIIc=790.0, eta_bk=1.45,
+                Sp=(AS4_SP if plastic else 0.0), Kp=(AS4_KP if plastic else 0.0))
 
 
 def coupon_as4(level: int = 0, precision=PREC_MIXED, phi: float = 1.033) -> dict:
     """The AS4/8552 coupon at refinement level 0 (183 x 131, one element per
     cluster) or 1 (366 x 262, two), with the dissipative Tchamwa-Wielgosz
-    member phi = 1.033 of Section 2.2.1 by default."""
+    member phi = 1.033 of Section 2.2.1 by default, and Table 1's matrix
+    shear plasticity."""
     nx, ny, epc = ((183, 131, 1), (366, 262, 2))[level]
     t = 4 * AS4_PLY
     return dict(
@@ -225,7 +251,7 @@ def coupon_as4(level: int = 0, precision=PREC_MIXED, phi: float = 1.033) -> dict
         mesh=_mesh(nx, ny, 8, epc, 0.150, 0.100, t, AS4_CLUSTERS, cohesive=1,
                    bc=BC_ASTM_WINDOW, window_lx=0.125, window_ly=0.075,
                    clamp_radius=5.0e-3, precision=precision, phi=phi),
-        materials=[material_as4_8552(p in (0, 7), t) for p in range(8)],
+        materials=[material_as4_8552(p in (0, 7), t, plastic=True) for p in range(8)],
         impactor=impactor(8.0e-3, 5.0, v0=2.78),
         t_end=5.0e-3)
 
@@ -276,14 +302,14 @@ def scaled(cfg: dict, nx: int, ny: int, lx: float = None, ly: float = None,
 def tiny(nx=4, ny=4, n_plies=2, elems_per_ply=1, *, angles=None, cohesive=0,
          law=LAW_ELASTIC, precision=PREC_FP64, lx=8.0e-3, ly=8.0e-3,
          ply_thickness=1.0e-3, bc=BC_CLAMPED_EDGES, energy=0.0, v0=3.0,
-         mass=0.05, R=4.0e-3, gravity=9.81, isotropic=False) -> dict:
+         mass=0.05, R=4.0e-3, gravity=9.81, isotropic=False, plastic=False) -> dict:
     """Small mesh for brute-force and parity cases."""
     if angles is None:
         angles = [0.0 if p % 2 == 0 else 90.0 for p in range(n_plies)]
     if isotropic:
         mats = [material_isotropic(70.0e9, 0.3, 2700.0) for _ in range(n_plies)]
     else:
-        mats = ply_materials(n_plies, ply_thickness, law)
+        mats = ply_materials(n_plies, ply_thickness, law, plastic)
     return dict(
         name=f"tiny-{nx}x{ny}x{n_plies * elems_per_ply}",
         mesh=_mesh(nx, ny, n_plies, elems_per_ply, lx, ly, ply_thickness, angles,
