@@ -103,20 +103,166 @@ def copy_calibration(nbytes: int):
                       "copy_ms": ms, "copy_GBs": 2 * n * 8 / (ms * 1e-3) / 1e9}), flush=True)
 
 
-def cpu_baseline(steps: int, threads: int) -> dict:
+def _cpu_topology() -> dict:
+    """CPU model, logical CPUs this process may run on, and the physical cores
+    among them (lscpu's CORE,SOCKET pairs)."""
+    import subprocess
+    allowed = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else list(range(os.cpu_count()))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    cores = set()
+    try:
+        out = subprocess.run(["lscpu", "-p=CPU,CORE,SOCKET"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("#"):
+                continue
+            cpu, core, sock = (int(v) if v else 0 for v in line.split(","))
+            if cpu in allowed:
+                cores.add((sock, core))
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    return {"cpu_model": model, "logical_cpus": len(allowed), "physical_cores": len(cores) or len(allowed)}
+
+
+def _oracle_rate(threads: int, budget_s: float, max_steps: int) -> dict:
     import oracle
     import workloads as W
-    cfg = W.scaled(W.plate_qi8_1200x800x16(W.PREC_FP64), 150, 100, lx=150 * 0.125e-3, ly=100 * 0.125e-3)
-    cfg["mesh"]["bc"] = W.BC_CLAMPED_EDGES
+    cfg = W.plate_qi8_150x100x16_cut(W.PREC_FP64)
     o = oracle.Oracle(cfg, threads=threads)
     o.step(2)                                  # set-up outside the timed region
     t0 = time.perf_counter()
+    o.step(3)
+    per = (time.perf_counter() - t0) / 3
+    steps = int(max(5, min(max_steps, budget_s / max(per, 1e-9))))
+    t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    gps = o.ne * steps / dt
-    return {"value": gps, "unit": "GP-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} steps of a 150x100x16 (+6 interfaces) cut of the workload laminate, "
-                      f"same element size, {o.ne} bulk GPs, FP64, {threads} OpenMP threads"}
+    return {"value": o.ne * steps / dt, "unit": "GP-updates/s", "threads": threads, "steps": steps,
+            "wall_s": dt, "bulk_gps": o.ne}
+
+
+def cpu_baseline(max_steps: int, budget_s: float = 10.0) -> dict:
+    """The FP64 oracle on this host's CPUs, at one thread and at every
+    physical core it may use, on a bounded sample of the benchmark workload:
+    its 150 x 100-column cut (same laminate, element size, interfaces, striker
+    and support type), timed for about budget_s seconds each."""
+    topo = _cpu_topology()
+    one = _oracle_rate(1, budget_s, max_steps)
+    nall = max(1, topo["physical_cores"])
+    allc = _oracle_rate(nall, budget_s, max_steps)
+    return {"value": allc["value"], "unit": "GP-updates/s", "cores": nall, "kind": "oracle",
+            "sample": f"{allc['steps']} steps of the 150x100x16 (+6 interfaces) cut of the benchmark plate "
+                      f"(same element size, window supports scaled to the cut, 25 J striker), {allc['bulk_gps']} "
+                      f"bulk GPs, FP64, {nall} OpenMP threads; {one['steps']} steps at 1 thread",
+            "threads_1": one, "threads_all": allc, **topo}
+
+
+def copy_ceiling(stream, nbytes: int = 2 << 30, reps: int = 10) -> dict:
+    """HBM bandwidth of the library's streaming-copy kernel (pdn_stream_copy)
+    on a buffer far larger than the caches, timed with HIP events on the
+    library's stream."""
+    import torch
+    import paper_2301_05552_amd as pdn
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        pdn.stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream=stream.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        pdn.stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream=stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    assert bool((dst == 1).all())
+    del src, dst
+    return {"copy_GBs": 2 * nbytes / (ms * 1e-3) / 1e9, "copy_ms": ms, "copy_bytes_each_way": nbytes}
+
+
+def _timed(sim, steps):
+    import torch
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    sim.set_timing(False)
+    en_ms, bk_ms = sim.kernel_times()
+    return 1e3 * el / steps, en_ms, bk_ms
+
+
+def _window(sim, steps, precision, what) -> dict:
+    import paper_2301_05552_amd as pdn
+    ms, en_ms, bk_ms = _timed(sim, steps)
+    info = sim.info()
+    nbytes = algorithmic_bytes(info, precision)
+    ach = nbytes / (en_ms * 1e-3) / 1e9
+    dm = sim.damage_field(pdn.DMG_MATRIX)
+    _, f, _ = sim.contact_force()
+    return {"window": what, "steps": steps, "at_step": info["steps"], "ms_per_step": ms,
+            "value": info["n_bulk"] / (ms * 1e-3), "unit": "GP-updates/s", "kernel_ms": en_ms,
+            "books_kernel_ms": bk_ms, "matrix_damaged_gps": int((dm > 0).sum()),
+            "contact_force_N": float(f[-1]) if len(f) else 0.0,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
+
+
+def damaged_windows(sim, steps: int, total_steps: int, seed_steps: int) -> dict:
+    """The headline plate later in its run and with softened points: (1) the
+    last `steps` steps of the workload's 20,000 (damage under the striker);
+    (2) every Gauss point's thresholds set above onset (r = 1 + U(0, 0.5),
+    seeded), so that every point takes the law's softening arithmetic and no
+    point passes the elastic screen, then `seed_steps` untimed steps and
+    `steps` timed ones."""
+    import workloads as W
+    import paper_2301_05552_amd as pdn
+    out = {}
+    left = total_steps - sim.info()["steps"] - steps
+    while left > 0:
+        k = min(5000, left)
+        sim.step(k)
+        left -= k
+        log(f"late window: {sim.info()['steps']} steps")
+    prec = 1 if sim.info()["precision"] == 1 else 0
+    out["late"] = _window(sim, steps, prec, f"last {steps} of {total_steps} steps")
+    n = sim.info()["n_bulk"]
+    r = 1.0 + W.rng(0xDA3A9E).uniform(0.0, 0.5, 4 * n)
+    r[0::4] = np.maximum(r[0::4], r[1::4])             # r1+ >= r1-, r2+ >= r2- as the law keeps them
+    r[2::4] = np.maximum(r[2::4], r[3::4])
+    sim.array_set(pdn.ARR_GP_R, r)
+    del r
+    sim.step(seed_steps)
+    out["all_softened"] = _window(sim, steps, prec, "every Gauss point above onset (seeded thresholds)")
+    return out
+
+
+def fp64_leg(stream, pre, warmup, steps) -> dict:
+    """The headline plate in FP64 mode (the paper's own arithmetic: element
+    arithmetic and damage state in FP64 too), 16 x 16 tiles; roofline with the
+    FP64-mode algorithmic bytes (64 B per GP, 16 B per pair)."""
+    import paper_2301_05552_amd as pdn
+    import workloads as W
+    cfg = W.plate_qi8_1200x800x16(W.PREC_FP64)
+    sim = pdn.Simulation(cfg, stream=stream, tile=(16, 16))
+    sim.step(pre + warmup)
+    ms, en_ms, bk_ms = _timed(sim, steps)
+    info = sim.info()
+    sim.close()
+    nbytes = algorithmic_bytes(info, 0)
+    ach = nbytes / (en_ms * 1e-3) / 1e9
+    return {"workload": "as the headline plate, FP64 mode", "tile": "16x16", "steps": steps, "ms_per_step": ms,
+            "value": info["n_bulk"] / (ms * 1e-3), "unit": "GP-updates/s", "kernel_ms": en_ms,
+            "books_kernel_ms": bk_ms,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
 
 
 def batched_leg(steps: int, warmup: int, stream) -> dict:
@@ -195,6 +341,30 @@ def full_integration_leg(stream, pre, warmup, steps, plain_ms) -> dict:
             "element_steps_vs_one_point": plain_ms / ms,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
+
+
+def plastic_leg(stream, pre, warmup, steps, plain_ms) -> dict:
+    """The headline plate with Table 1's matrix shear plasticity on every ply
+    (Algorithm 4 from its first line), mixed precision, 15 x 15 tiles; the
+    roofline counts the plastic state (four FP32 words per Gauss point) read
+    and written besides the thresholds."""
+    import paper_2301_05552_amd as pdn
+    import workloads as W
+    cfg = W.plate_qi8_1200x800x16(W.PREC_MIXED)
+    for m in cfg["materials"]:
+        m["Sp"], m["Kp"] = W.AS4_SP, W.AS4_KP
+    sim = pdn.Simulation(cfg, stream=stream, tile=(15, 15))
+    sim.step(pre + warmup)
+    ms, en_ms, bk_ms = _timed(sim, steps)
+    info = sim.info()
+    sim.close()
+    nbytes = algorithmic_bytes(info, 1) + 32.0 * info["n_bulk"]
+    ach = nbytes / (en_ms * 1e-3) / 1e9
+    return {"workload": "as the headline plate, every ply with shear plasticity (S_p 62 MPa, K_p 0.1936)",
+            "tile": "15x15", "steps": steps, "ms_per_step": ms, "value": info["n_bulk"] / (ms * 1e-3),
+            "unit": "GP-updates/s", "kernel_ms": en_ms, "books_kernel_ms": bk_ms, "vs_plain": plain_ms / ms,
+            "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
 
 
 # Section 3.2.2, Table 4: the paper's own numerical results for the AS4/8552
@@ -304,6 +474,75 @@ def _consulted(info) -> float:
     return info["sur_consulted"] / n if n else 0.0
 
 
+def surrogate_gains(stream, tile, nets, pre, steps) -> dict:
+    """What the trained network gains over the exact law where it is used:
+    the headline plate after its pre-roll with every Gauss point's thresholds
+    just above onset (r = 1 + U(0, 0.02), seeded; damage below the 0.05
+    fallback bar), so that no point passes the law's screen and every point
+    consults the network, (a) as it is (near rest) and (b) set to a uniform
+    in-plane stretch at half the transverse onset strain.  Each state is
+    stepped by the plain build (exact law everywhere) and by the network
+    build at the residual bars 1e-3 and 1; reported: time per consulted
+    Gauss-point update of each, the share of consulted points whose network
+    output was accepted, and the largest displacement difference from the
+    exact-law run."""
+    import torch
+    import paper_2301_05552_amd as pdn
+    import workloads as W
+    cfg = W.plate_qi8_1200x800x16(W.PREC_MIXED)
+    out = {}
+    for state in ("at_rest", "stretched"):
+        ref = ref_disp = None
+        part = {}
+        for name, res in (("exact_law", None), ("network_res_0.001", 1e-3), ("network_res_1", 1.0)):
+            sim = pdn.Simulation(cfg, stream=stream, tile=tile)
+            sim.step(pre)
+            if state == "stretched":
+                m, mat = cfg["mesh"], cfg["materials"][0]
+                eps = 0.5 * mat["YT"] / mat["E2"]
+                nn = sim.info()["n_nodes"]
+                k = np.arange(nn)
+                d = np.zeros((nn, 3))
+                d[:, 0] = eps * m["lx"] * (k % (m["nx"] + 1)) / m["nx"]
+                d[:, 1] = eps * m["ly"] * ((k // (m["nx"] + 1)) % (m["ny"] + 1)) / m["ny"]
+                sim.array_set(pdn.ARR_DISP, d.reshape(-1))
+                del d, k
+            n = sim.info()["n_bulk"]
+            r = 1.0 + W.rng(0x6A1B5).uniform(0.0, 0.02, 4 * n)
+            r[0::4] = np.maximum(r[0::4], r[1::4])
+            r[2::4] = np.maximum(r[2::4], r[3::4])
+            sim.array_set(pdn.ARR_GP_R, r)
+            del r
+            if res is not None:
+                for p, w in enumerate(nets):
+                    sim.surrogate_set(p, w, 0.05, res)
+                sim.surrogate_kernel(1)
+            sim.step(1)                                  # restart pass from the set state
+            c0 = sim.info()["sur_consulted"]
+            f0 = sim.info()["fallback_fraction"] * c0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.step(steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            info = sim.info()
+            cons = info["sur_consulted"] - c0
+            fb = info["fallback_fraction"] * info["sur_consulted"] - f0
+            disp = sim.array_get(pdn.ARR_DISP)
+            sim.close()
+            e = {"ms_per_step": 1e3 * el / steps, "ns_per_gp_update": 1e9 * el / (steps * n)}
+            if res is not None:
+                e["consulted_fraction"] = cons / (steps * n)
+                e["accepted_fraction_of_consulted"] = 1.0 - fb / cons if cons else 0.0
+                e["speedup_vs_exact_law"] = ref["ms_per_step"] / e["ms_per_step"]
+                e["disp_rel_diff_vs_exact_law"] = float(np.abs(disp - ref_disp).max() / np.abs(ref_disp).max())
+            else:
+                ref, ref_disp = e, disp
+            part[name] = e
+        out[state] = part
+    return out
+
+
 def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_steps) -> dict:
     """The metric's second half: the same plate with the intralaminar update
     by the trained network (exact law as fallback), at the stated residual bar
@@ -328,7 +567,11 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
                                "speedup_vs_plain": plain_ms / ms,
                                "network_consulted_fraction": _consulted(info),
                                "fallback_fraction": info["fallback_fraction"],
+                               "network_build_steps": info["sur_network_steps"],
+                               "note": "per-call build choice: a call whose previous call met no point "
+                                       "outside the screen runs the plain build",
                                "peak_force_N": fpk, "plain_peak_force_N": f_plain}
+    out["gains"] = surrogate_gains(stream, tile, nets, pre, max(5, steps // 2))
     gold = os.path.join(ROOT, "tests", "golden", "qi8_300x200x8_fp64_oracle.json")
     if gate_steps and os.path.exists(gold):
         with open(gold) as fh:
@@ -387,7 +630,10 @@ def main():
     ap.add_argument("--sur-train-steps", type=int, default=16000)
     ap.add_argument("--gate-steps", type=int, default=61000,
                     help="steps of the 300x200x8 accuracy gate (0 = skip)")
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-steps", type=int, default=300, help="most oracle steps per CPU-baseline timing")
+    ap.add_argument("--no-damaged", action="store_true", help="skip the late and softened windows")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-mode leg")
+    ap.add_argument("--no-plastic", action="store_true", help="skip the shear-plasticity leg")
     ap.add_argument("--max-preroll", type=int, default=2000,
                     help="untimed steps allowed to bring the striker into contact before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -469,7 +715,25 @@ def main():
                      "kernel": "k_elem_node", "workload_key": wkey, "kernel_ms": en_ms, "books_kernel_ms": bk_ms,
                      "algorithmic_bytes_per_launch": bytes_launch},
     }
+    log("copy ceiling: streaming copy of 2 GiB")
+    cc = copy_ceiling(stream)
+    res["roofline"]["copy_GBs"] = cc["copy_GBs"]
+    res["roofline"]["frac_of_copy"] = achieved / cc["copy_GBs"]
+    res["copy"] = cc
+    if big and not args.no_damaged:
+        log("damaged windows: late in the 20,000 steps, and every point softened")
+        res["damaged"] = damaged_windows(sim, args.steps, cfg["steps"], args.warmup)
+        log(f"damaged windows: late {res['damaged']['late']['ms_per_step']:.3f} ms/step, softened "
+            f"{res['damaged']['all_softened']['ms_per_step']:.3f} ms/step")
     sim.close()
+    if big and not args.no_plastic:
+        log("plastic leg: headline plate with shear plasticity")
+        res["plastic"] = plastic_leg(stream.cuda_stream, pre, args.warmup, args.steps, res["ms_per_step"])
+        log(f"plastic: {res['plastic']['ms_per_step']:.3f} ms/step")
+    if big and not args.no_fp64:
+        log("fp64 leg: headline plate in FP64 mode")
+        res["fp64"] = fp64_leg(stream.cuda_stream, pre, args.warmup, args.steps)
+        log(f"fp64: {res['fp64']['ms_per_step']:.3f} ms/step")
     if not args.no_surrogate:
         log("surrogate leg: training networks, surrogate runs")
         res["surrogate"] = surrogate_leg(stream.cuda_stream, (tx, ty), pre, args.warmup, args.steps,
@@ -490,9 +754,8 @@ def main():
         log(f"coupon leg: AS4/8552 coupon, levels {lvls}, to 5 ms")
         res["coupon"] = coupon_leg(lvls, stream.cuda_stream)
     if not args.no_cpu_baseline:
-        threads = min(os.cpu_count() or 1, 16)
-        log(f"cpu baseline: oracle, {threads} threads")
-        res["cpu_baseline"] = cpu_baseline(args.cpu_steps, threads)
+        log("cpu baseline: oracle at 1 thread and at every physical core")
+        res["cpu_baseline"] = cpu_baseline(args.cpu_steps)
     print(json.dumps(res), flush=True)
 
 

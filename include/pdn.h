@@ -155,8 +155,10 @@ typedef struct {
     double fallback_fraction;     /* surrogate: of the GP updates on which the network was consulted,
                                      the fraction that the exact law produced (0 when none was) */
     int32_t precision, tile_x, tile_y, blocks;
-    double sur_consulted;         /* surrogate: GP updates on which the network was consulted; the
-                                     others of surrogate plies were screened elastic by the law */
+    double sur_consulted;         /* surrogate: GP updates on which the network was consulted (or, in
+                                     steps of the plain build, would have been); the others of
+                                     surrogate plies were screened elastic by the law */
+    int64_t sur_network_steps;    /* surrogate: steps run by the build that evaluates the network */
 } pdn_info;
 
 /* Build the plate mesh and allocate device state on desc->device. */
@@ -292,12 +294,27 @@ int pdn_surrogate_train(const pdn_sur_train *opt, const pdn_material *m, double 
  * the exact law.  ESTATE for a ply without a damage law.  Legal mid-run. */
 int pdn_surrogate_set(pdn_ctx *ctx, int32_t ply, const float *weights, int64_t n, double dmg_thresh,
                       double res_thresh);
+/* Which kernel build steps a context with surrogate plies.  mode 0 (the
+ * default) chooses per pdn_step call: the build that evaluates the network
+ * when the previous call met points that the law's screen did not pass (or
+ * right after pdn_surrogate_set), otherwise the plain build, which steps the
+ * surrogate plies by the exact law (so a call that met no such point costs
+ * what the plain path costs) and still counts the points the screen does not
+ * pass.  The first call after such points appear is then stepped by the
+ * exact law; results can differ with how steps are split into calls.  mode 1
+ * always uses the network build.  PDN_EINVAL for other modes. */
+int pdn_surrogate_kernel(pdn_ctx *ctx, int32_t mode);
 /* Forward pass on n points: x is n x 10 inputs, y receives n x 10 outputs. */
 int pdn_surrogate_eval(int32_t device, void *stream, const float *weights, const float *x, int64_t n, float *y);
 /* Mean square error over n x 10 outputs against targets t, and its gradient
  * with respect to the PDN_SUR_NPARAM parameters (the training kernel's). */
 int pdn_surrogate_grad(int32_t device, void *stream, const float *weights, const float *x, const float *t,
                        int64_t n, float *grad, double *loss);
+/* The same loss and gradient with FP32 operands and arithmetic throughout
+ * (vector units instead of the bf16 matrix cores), for checking against an
+ * FP64 reference at FP32 accuracy.  Host arrays, synchronous. */
+int pdn_surrogate_grad_fp32(int32_t device, void *stream, const float *weights, const float *x, const float *t,
+                            int64_t n, float *grad, double *loss);
 /* Records of paths p0 .. p0+n_paths-1 of the data set (20 floats each:
  * 10 inputs, 10 exact outputs; increments of a path consecutive). */
 int pdn_surrogate_data(int32_t device, void *stream, const pdn_material *m, double crack_band, uint64_t seed,

@@ -18,8 +18,9 @@ The loss is the mean square error over samples and the ten outputs.
 Parameters are one flat float vector in this order (W stored [in][out]):
 W1[10][64], b1[64], W2[64][64], b2[64], W3[64][64], b3[64], W4[64][10], b4[10].
 
-``quant="bf16"`` rounds the inputs and weights to bfloat16 (round to nearest
-even) before the FP64 arithmetic: the operands the matrix cores receive.
+``quant="bf16"`` rounds the inputs, weights, activations and (in the
+gradient) the SiLU derivatives and back-propagated errors to bfloat16 (round to nearest even)
+before the FP64 arithmetic: the operands the matrix cores receive.
 """
 from __future__ import annotations
 
@@ -104,15 +105,18 @@ def grad(w, x, t, quant: str | None = None):
     t = np.asarray(t, dtype=np.float64)
     n = y.shape[0]
     L = float(np.mean((y - t) ** 2))
+    # with quant="bf16" the back-propagated errors are bf16 operands too
+    q = bf16_round if quant == "bf16" else (lambda a: a)
     dy = 2.0 * (y - t) / (n * N_OUT)
     dz4 = dy.copy()
     dz4[:, N_LINEAR:] *= y[:, N_LINEAR:] * (1.0 - y[:, N_LINEAR:])
+    dz4 = q(dz4)
     gW4, gb4 = h3.T @ dz4, dz4.sum(0)
-    dz3 = (dz4 @ W4.T) * dsilu(z3)
+    dz3 = q((dz4 @ W4.T) * q(dsilu(z3)))
     gW3, gb3 = h2.T @ dz3, dz3.sum(0)
-    dz2 = (dz3 @ W3.T) * dsilu(z2)
+    dz2 = q((dz3 @ W3.T) * q(dsilu(z2)))
     gW2, gb2 = h1.T @ dz2, dz2.sum(0)
-    dz1 = (dz2 @ W2.T) * dsilu(z1)
+    dz1 = q((dz2 @ W2.T) * q(dsilu(z1)))
     gW1, gb1 = x0.T @ dz1, dz1.sum(0)
     g = np.concatenate([a.reshape(-1) for a in (gW1, gb1, gW2, gb2, gW3, gb3, gW4, gb4)])
     return L, g

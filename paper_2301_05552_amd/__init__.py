@@ -69,7 +69,8 @@ class Info(C.Structure):
         "n_nodes", "n_bulk", "n_cohesive", "n_pairs", "n_planes", "n_layers", "n_candidates",
         "steps", "reset_passes", "released", "active", "max_passes")] + [
         ("fallback_fraction", C.c_double), ("precision", C.c_int32), ("tile_x", C.c_int32),
-        ("tile_y", C.c_int32), ("blocks", C.c_int32), ("sur_consulted", C.c_double)]
+        ("tile_y", C.c_int32), ("blocks", C.c_int32), ("sur_consulted", C.c_double),
+        ("sur_network_steps", C.c_int64)]
 
 
 def lib():
@@ -112,6 +113,9 @@ def lib():
             "pdn_surrogate_data": [C.c_int32, vp, P(Material), C.c_double, C.c_uint64, i64, i64, C.c_int32,
                                    P(C.c_float)],
             "pdn_surrogate_grad_noalloc": [C.c_int32, vp, vp, vp, vp, i64, vp, vp],
+            "pdn_surrogate_kernel": [vp, C.c_int32],
+            "pdn_surrogate_grad_fp32": [C.c_int32, vp, P(C.c_float), P(C.c_float), P(C.c_float), i64,
+                                        P(C.c_float), P(C.c_double)],
             "pdn_stream_copy": [C.c_int32, vp, vp, vp, i64],
             "pdn_global_last_error": [],
         }
@@ -192,6 +196,18 @@ def surrogate_grad(w, x, t, device=0, stream=None):
     g = np.zeros(SUR_NPARAM, dtype=np.float32)
     loss = C.c_double()
     _gchk(lib().pdn_surrogate_grad(device, stream, _fp(w), _fp(x), _fp(t), x.shape[0], _fp(g), C.byref(loss)))
+    return g, loss.value
+
+
+def surrogate_grad_fp32(w, x, t, device=0, stream=None):
+    """pdn_surrogate_grad_fp32: FP32 loss and gradient (host arrays)."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32).reshape(-1, 10)
+    t = np.ascontiguousarray(t, dtype=np.float32).reshape(-1, 10)
+    g = np.zeros(SUR_NPARAM, dtype=np.float32)
+    loss = C.c_double()
+    _gchk(lib().pdn_surrogate_grad_fp32(device, stream, _fp(w), _fp(x), _fp(t), x.shape[0], _fp(g),
+                                        C.byref(loss)))
     return g, loss.value
 
 
@@ -347,6 +363,10 @@ class Simulation:
     def surrogate_set(self, ply: int, w, dmg_thresh: float = 0.05, res_thresh: float = 1e-3):
         w = np.ascontiguousarray(w, dtype=np.float32)
         self._chk(lib().pdn_surrogate_set(self.h, ply, _fp(w), w.size, dmg_thresh, res_thresh))
+
+    def surrogate_kernel(self, mode: int):
+        """0: choose the network or the plain build per step call; 1: always the network build."""
+        self._chk(lib().pdn_surrogate_kernel(self.h, mode))
 
     def autotune(self):
         tx, ty = C.c_int32(), C.c_int32()

@@ -86,6 +86,15 @@ struct pdn_ctx {
     int ngp = 1;                      // Gauss points of a bulk element: 1 (hourglass control) or 8
     std::vector<int> ply_net;
     double sur_dmg = 0.05, sur_res = 1e-3;
+    // which build steps the surrogate plies in a pdn_step call: mode 0 picks
+    // per call (the network build when the previous call had points that the
+    // screen did not pass, or right after a network was set; else the plain
+    // build, which steps those plies by the exact law and counts such points);
+    // mode 1 always the network build
+    int sur_mode = 0;
+    bool sur_net_now = true, sur_fresh = true;
+    double sur_gp_mark = 0.0;
+    int64_t sur_net_steps = 0;
     // timing
     bool timing = false;
     double t_en_ms = 0, t_bk_ms = 0;
@@ -430,6 +439,7 @@ ElemArgs<R> elem_args(pdn_ctx *c, int in, int out, int contact)
     a.mlp = c->sur_d;
     a.sur_dmg = (float)c->sur_dmg;
     a.sur_res = (float)c->sur_res;
+    a.count_sur = c->use_sur && !c->sur_net_now ? 1 : 0;
     return a;
 }
 
@@ -449,12 +459,11 @@ int launch_en(pdn_ctx *c, int in, int out, int contact, hipEvent_t mid = nullptr
 {
     hipError_t e;
     const bool mx = c->precision == PDN_MIXED;
+    const bool net = c->use_sur && c->sur_net_now;
     if (mx)
-        e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out, contact), c->tile, c->use_sur, c->ngp,
-                                         c->stream);
+        e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out, contact), c->tile, net, c->ngp, c->stream);
     else
-        e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out, contact), c->tile, c->use_sur, c->ngp,
-                                          c->stream);
+        e = pdn::launch_elem_node<double>(elem_args<double>(c, in, out, contact), c->tile, net, c->ngp, c->stream);
     if (e != hipSuccess) return set_err(c, PDN_EDEVICE, "element/node kernel launch: %s", hipGetErrorString(e));
     if (!contact) return PDN_OK;
     if (mid) HIPCHK(c, hipEventRecord(mid, c->stream));
@@ -848,6 +857,14 @@ int pdn_step(pdn_ctx *c, int64_t n)
         c->loaded_state = false;
     }
     if ((rc = ensure_history(c, c->gl.step + n))) return rc;
+    if (c->use_sur) {
+        // build for this call: the network build if the previous call met points
+        // that the screen did not pass (or a network was just set), else the plain one
+        c->sur_net_now = c->sur_mode == 1 || c->sur_fresh || c->gl.sur_gp > c->sur_gp_mark;
+        c->sur_fresh = false;
+        c->sur_gp_mark = c->gl.sur_gp;
+        if (c->sur_net_now) c->sur_net_steps += n;
+    }
     std::vector<hipEvent_t> ev;
     if (c->timing && n > 0) {
         ev.resize(3 * n);
@@ -997,6 +1014,7 @@ int pdn_info_get(const pdn_ctx *c, pdn_info *o)
     o->tile_x = pdn_tile_dims[c->tile][0];
     o->tile_y = pdn_tile_dims[c->tile][1];
     o->blocks = c->nblocks;
+    o->sur_network_steps = c->sur_net_steps;
     return PDN_OK;
 }
 
@@ -1892,6 +1910,39 @@ int pdn_surrogate_grad(int32_t device, void *stream, const float *weights, const
     return PDN_OK;
 }
 
+int pdn_surrogate_grad_fp32(int32_t device, void *stream, const float *weights, const float *x, const float *t,
+                            int64_t n, float *grad, double *loss)
+{
+    if (!weights || !x || !t || !grad || n < 1) return gerr(PDN_EINVAL, "surrogate grad (fp32): invalid argument");
+    GHIPCHK(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<float> rec((size_t)n * 20);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < 10; ++k) {
+            rec[i * 20 + k] = x[i * 10 + k];
+            rec[i * 20 + 10 + k] = t[i * 10 + k];
+        }
+    const int nwg = pdn::sur_grad32_blocks(n);
+    DevMem mem;
+    float *w, *data, *part;
+    GHIPCHK(mem.get(&w, SUR_NPARAM * sizeof(float)));
+    GHIPCHK(mem.get(&data, rec.size() * sizeof(float)));
+    GHIPCHK(mem.get(&part, (size_t)nwg * (SUR_NPARAM + 1) * sizeof(float)));
+    GHIPCHK(hipMemcpyAsync(w, weights, SUR_NPARAM * sizeof(float), hipMemcpyHostToDevice, s));
+    GHIPCHK(hipMemcpyAsync(data, rec.data(), rec.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    GHIPCHK(pdn::launch_sur_grad32(w, data, n, (float)(1.0 / ((double)n * SUR_NOUT)), part, s));
+    std::vector<float> h((size_t)nwg * (SUR_NPARAM + 1));
+    GHIPCHK(hipMemcpyAsync(h.data(), part, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+    for (int p = 0; p <= SUR_NPARAM; ++p) {
+        double g = 0;
+        for (int b = 0; b < nwg; ++b) g += h[(size_t)b * (SUR_NPARAM + 1) + p];
+        if (p < SUR_NPARAM) grad[p] = (float)g;
+        else if (loss) *loss = g;
+    }
+    return PDN_OK;
+}
+
 int pdn_surrogate_grad_noalloc(int32_t device, void *stream, const float *weights, const float *x, const float *t,
                                int64_t n, float *grad, double *loss)
 {
@@ -2000,6 +2051,14 @@ int pdn_surrogate_train(const pdn_sur_train *o, const pdn_material *m, double cr
     return PDN_OK;
 }
 
+int pdn_surrogate_kernel(pdn_ctx *c, int32_t mode)
+{
+    if (!c) return PDN_EINVAL;
+    if (mode != 0 && mode != 1) return set_err(c, PDN_EINVAL, "surrogate kernel mode must be 0 or 1");
+    c->sur_mode = mode;
+    return PDN_OK;
+}
+
 int pdn_surrogate_set(pdn_ctx *c, int32_t ply, const float *weights, int64_t n, double dmg_thresh,
                       double res_thresh)
 {
@@ -2039,6 +2098,7 @@ int pdn_surrogate_set(pdn_ctx *c, int32_t ply, const float *weights, int64_t n, 
             c->mat[p].law = PDN_LAW_CDM_SURROGATE;
         }
     c->n_nets += 1;
+    c->sur_fresh = true;
     c->sur_dmg = dmg_thresh;
     c->sur_res = res_thresh;
     c->ready = false;

@@ -20,13 +20,17 @@ namespace pdn {
 // the exact law when any damage variable of its incoming thresholds exceeds
 // dmg_thr, or when the network's stress disagrees with the nominal stress of
 // the network's own new thresholds by more than res_thr (relative to |C0 e|,
-// at least 1e-3 Y_T).  Every lane of the wave must call it together (the
-// network runs on the matrix cores).  exact: 0 the network's result, 1 the
-// exact law after the network was consulted, 2 screened elastic.
+// at least 1e-3 Y_T).  A point of an element that two workgroups evaluate
+// (shared) keeps the exact law too: the other workgroup may read its
+// thresholds before or after their owner updates them, which the exact law's
+// idempotent update tolerates and the network would not.  Every lane of the
+// wave must call it together (the network runs on the matrix cores).  exact:
+// 0 the network's result, 1 the exact law after the network was consulted (or
+// a shared element), 2 screened elastic.
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6], bool &changed,
-                           const uint4 *__restrict__ pk, float dmg_thr, float res_thr, int &exact)
+                           const uint4 *__restrict__ pk, float dmg_thr, float res_thr, int &exact, bool shared)
 {
     R sel[6];
     const bool el = cdm_screen(P, vol, e, r, sel);
@@ -48,8 +52,8 @@ __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
     for (int k = 0; k < 6; ++k) x[k] = (float)(e[k] * kx[k]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) x[6 + k] = (float)(R(1) - R(1) / r[k]);
-    bool fb = (r[0] > R(1) || r[1] > R(1) || r[2] > R(1) || r[3] > R(1)) &&
-              cdm_max_damage(P, lc, YT, YC, SL, r) > (R)dmg_thr;
+    bool fb = shared || ((r[0] > R(1) || r[1] > R(1) || r[2] > R(1) || r[3] > R(1)) &&
+                         cdm_max_damage(P, lc, YT, YC, SL, r) > (R)dmg_thr);
     if (__ballot(!fb && !el) != 0) sur_forward_wave(pk, x, y);  // uniform across the wave
     if (el) {
 #pragma unroll
@@ -163,7 +167,9 @@ __device__ __forceinline__ void store_state<float>(float *r, int64_t e, const fl
 // One point of a box element: Green strain of the displacement gradient G
 // (= F - I, row-major), ply frame, law (thresholds r), back to the global
 // frame, nominal stress Pn = F S (row-major).  Returns S:E in the ply frame
-// (twice the secant energy density).
+// (twice the secant energy density).  exact: in, 1 for an element that two
+// workgroups evaluate (the surrogate then keeps the exact law); out, as
+// sur_update reports it.
 template <typename R, bool SUR, bool PLAS = false>
 __device__ __forceinline__ R box_point(const R G[9], const PlyC<R> &P, R vol, R r[4], bool &changed, R Pn[9],
                                        const uint4 *sur_pk, float sur_dmg, float sur_res, int &exact,
@@ -188,6 +194,7 @@ __device__ __forceinline__ R box_point(const R G[9], const PlyC<R> &P, R vol, R 
     e[4] = R(2) * (c * E02 + s * E12);
     e[5] = R(2) * (-cs * E00 + (cc - ss) * E01 + cs * E11);
     R sg[6];
+    const bool shared = exact == 1;
     exact = 0;
     if constexpr (PLAS) {
         // plastic strains first; e becomes the elastic strain (its energy is
@@ -197,11 +204,14 @@ __device__ __forceinline__ R box_point(const R G[9], const PlyC<R> &P, R vol, R 
     if constexpr (SUR) {
         if (P.law == 2)
             sur_update(P, vol, e, r, sg, changed, sur_pk + (int64_t)P.sur * (SUR_PACK_BYTES / 16), sur_dmg, sur_res,
-                       exact);
+                       exact, shared);
         else
             cdm_update(P, vol, e, r, sg, changed);
     } else {
-        cdm_update(P, vol, e, r, sg, changed);                   // a surrogate ply keeps the exact law
+        // a surrogate ply keeps the exact law in this build; its unscreened
+        // points are counted (those the surrogate build would consult)
+        const bool scr = cdm_update(P, vol, e, r, sg, changed);
+        if (P.law == 2) exact = scr ? 2 : 1;
     }
     // back to the global frame
     R S00 = cc * sg[0] - R(2) * cs * sg[5] + ss * sg[1];
@@ -299,7 +309,7 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
         }
         R Pn[9];
         bool ch = false;
-        int ex;
+        int ex = 0;
         wsum += box_point<R, false>(G, P, vol, rg, ch, Pn, nullptr, 0.f, 0.f, ex);
         if (own && ch) store_state(rstate, e8 + g, rg);
         Modes<R> *cm[3] = {&cx, &cy, &cz};
@@ -786,7 +796,9 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                 const PlyC<R> P = cload(A.ply + lply);
                 bool changed = false;
                 R uel;
-                int exact;
+                // an element on the rim of this tile that the neighbouring tile evaluates too
+                int exact = ((ea == 0 && tx > 0) || (ea == TX - 1 && !lastx) || (eb == 0 && ty > 0) ||
+                             (eb == TY - 1 && !lasty)) ? 1 : 0;
                 Modes<R> cm[3];
                 if constexpr (NGP == 8) {
                     // lanes without an element read a valid record (clamped) and write nothing
@@ -982,6 +994,9 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
     if (A.contact && tx >= A.wt0 && tx < A.wt1 && ty >= A.wu0 && ty < A.wu1) {
         block_reduce_store<NT>(acc, A.partials + tile, A.prow, red);
     } else if constexpr (SUR) {
+        block_reduce_store<NT, T_FC>(acc, A.partials + tile, A.prow, red);
+    } else if (A.count_sur) {
+        // surrogate plies stepped by this build: their unscreened points are counted
         block_reduce_store<NT, T_FC>(acc, A.partials + tile, A.prow, red);
     } else {
         block_reduce_store<NT, T_AUX>(acc, A.partials + tile, A.prow, red);

@@ -124,6 +124,9 @@ struct ElemArgs {
     // constitutive surrogate: packed networks (PlyC::sur selects one), fallback thresholds
     const uint4 *mlp;
     float sur_dmg, sur_res;
+    // the build without the network steps surrogate plies (exact law): count
+    // their points that the screen does not pass
+    int count_sur;
 };
 
 // candidate bookkeeping of the contact step (initialisation, state arrays)

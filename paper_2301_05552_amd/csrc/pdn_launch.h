@@ -75,6 +75,10 @@ hipError_t launch_sur_adam(const float *partials, int nparts, float *w, float *m
                            float b2, float eps, float bc1, float bc2, float *loss_out, hipStream_t s);
 hipError_t launch_sur_eval(const void *pk, const float *x, int64_t n, float *y, hipStream_t s);
 int sur_loss_blocks(int64_t n);
+// FP32 gradient: one partial (SUR_NPARAM + 1 floats, loss last) per 16 points
+int sur_grad32_blocks(int64_t n);
+hipError_t launch_sur_grad32(const float *w, const float *data, int64_t n, float scale, float *partials,
+                             hipStream_t s);
 hipError_t launch_sur_interleave(const float *x, const float *t, int64_t n, float *rec, hipStream_t s);
 hipError_t launch_sur_grad_reduce(const float *part, int nparts, double count, float *grad, double *loss,
                                   hipStream_t s);

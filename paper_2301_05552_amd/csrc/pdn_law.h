@@ -157,9 +157,10 @@ __device__ __forceinline__ bool plastic_return(const PlyC<R> &P, R e[6], R ep[4]
 }
 
 // eps: material-frame Green strain (Voigt 11,22,33,23,13,12, engineering shear)
-// r: thresholds r1+, r1-, r2+, r2- (in/out).  Returns nominal PK2 stress.
+// r: thresholds r1+, r1-, r2+, r2- (in/out).  Returns nominal PK2 stress in sg,
+// and true when the screen passed the point (it is provably elastic).
 template <typename R>
-__device__ void cdm_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6], bool &changed)
+__device__ bool cdm_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6], bool &changed)
 {
     changed = false;
     R sc[6];
@@ -167,7 +168,7 @@ __device__ void cdm_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
     const R s0 = sc[0], s1 = sc[1], s2 = sc[2], s3 = sc[3], s4 = sc[4], s5 = sc[5];
     if (P.law == 0 || elastic) {
         sg[0] = s0; sg[1] = s1; sg[2] = s2; sg[3] = s3; sg[4] = s4; sg[5] = s5;
-        return;
+        return elastic;
     }
     const R lc = cbrt(vol);                              // crack-band length
     const R YT = cap_strength(P.YT, P.E2, P.GYT, lc);
@@ -200,9 +201,10 @@ __device__ void cdm_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
     r[0] = r0; r[1] = r1; r[2] = r2; r[3] = r3;
     if (r0 <= R(1) && r1 <= R(1) && r2 <= R(1) && r3 <= R(1)) {   // undamaged
         sg[0] = s0; sg[1] = s1; sg[2] = s2; sg[3] = s3; sg[4] = s4; sg[5] = s5;
-        return;
+        return false;
     }
     cdm_nominal(P, lc, YT, YC, SL, r0, r1, r2, r3, s0, s1, e, sg);
+    return false;
 }
 
 // ---------------------------------------------------------------------------

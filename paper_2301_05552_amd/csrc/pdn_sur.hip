@@ -489,6 +489,118 @@ hipError_t launch_sur_eval(const void *pk, const float *x, int64_t n, float *y, 
 }
 
 // ---------------------------------------------------------------------------
+// FP32 gradient (vector units): the same loss and gradient as k_sur_grad with
+// FP32 operands throughout, for a check against the FP64 reference at FP32
+// accuracy and for training in single precision.  A workgroup of 256 lanes
+// takes 16 points; lane t holds point t % 16 and units 4 (t / 16) .. +3 of
+// each hidden layer; pre-activations, activations and back-propagated
+// errors are staged in LDS as [unit][point]; the workgroup's partial gradient
+// (summed over its points) and loss go to partials[block].
+// ---------------------------------------------------------------------------
+#define SG32_PTS 16
+
+__device__ __forceinline__ float sg32_sigmoid(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+__global__ __launch_bounds__(256) void k_sur_grad32(const float *__restrict__ w, const float *__restrict__ data,
+                                                    int64_t n, float scale, float *__restrict__ partials)
+{
+    __shared__ float X[SUR_NIN][SG32_PTS], T[SUR_NOUT][SG32_PTS];
+    __shared__ float Z[3][SUR_NH][SG32_PTS], Hh[3][SUR_NH][SG32_PTS], D[3][SUR_NH][SG32_PTS];
+    __shared__ float D4[SUR_NOUT][SG32_PTS], Lp[SUR_NOUT][SG32_PTS];
+    const int t = threadIdx.x, p = t % SG32_PTS, g = t / SG32_PTS;
+    const int64_t i0 = (int64_t)blockIdx.x * SG32_PTS;
+    for (int q = t; q < SG32_PTS * SUR_REC; q += 256) {
+        const int pp = q / SUR_REC, k = q % SUR_REC;
+        const float v = i0 + pp < n ? data[(i0 + pp) * SUR_REC + k] : 0.f;
+        if (k < SUR_NIN) X[k][pp] = v;
+        else T[k - SUR_NIN][pp] = v;
+    }
+    __syncthreads();
+    // forward: hidden layers
+    const int wof[3] = {SUR_W1, SUR_W2, SUR_W3}, bof[3] = {SUR_B1, SUR_B2, SUR_B3};
+    for (int l = 0; l < 3; ++l) {
+        const int K = l == 0 ? SUR_NIN : SUR_NH;
+        for (int j = 0; j < 4; ++j) {
+            const int u = 4 * g + j;
+            float z = w[bof[l] + u];
+            for (int k = 0; k < K; ++k) z += w[wof[l] + k * SUR_NH + u] * (l == 0 ? X[k][p] : Hh[l - 1][k][p]);
+            Z[l][u][p] = z;
+            Hh[l][u][p] = z * sg32_sigmoid(z);
+        }
+        __syncthreads();
+    }
+    // output layer, loss and output errors (points past n contribute nothing)
+    if (t < SUR_NOUT * SG32_PTS) {
+        const int o = t / SG32_PTS, pp = t % SG32_PTS;
+        float z = w[SUR_B4 + o];
+        for (int k = 0; k < SUR_NH; ++k) z += w[SUR_W4 + k * SUR_NOUT + o] * Hh[2][k][pp];
+        const float y = o < SUR_NLIN ? z : sg32_sigmoid(z);
+        const float e = i0 + pp < n ? y - T[o][pp] : 0.f;
+        Lp[o][pp] = e * e * scale;
+        // sigmoid'(z) = s(z) s(-z): 1 - s(z) is formed as s(-z), without cancellation
+        D4[o][pp] = 2.0f * e * scale * (o < SUR_NLIN ? 1.0f : y * sg32_sigmoid(-z));
+    }
+    __syncthreads();
+    // back-propagation through layers 3, 2, 1
+    for (int l = 2; l >= 0; --l) {
+        for (int j = 0; j < 4; ++j) {
+            const int k = 4 * g + j;
+            float a = 0.f;
+            if (l == 2) {
+                for (int o = 0; o < SUR_NOUT; ++o) a += w[SUR_W4 + k * SUR_NOUT + o] * D4[o][p];
+            } else {
+                const int wn = l == 1 ? SUR_W3 : SUR_W2;
+                for (int u = 0; u < SUR_NH; ++u) a += w[wn + k * SUR_NH + u] * D[l + 1][u][p];
+            }
+            const float z = Z[l][k][p], sg = sg32_sigmoid(z);
+            D[l][k][p] = a * (sg + z * sg * sg32_sigmoid(-z));     // SiLU'(z), 1 - s(z) as s(-z)
+        }
+        __syncthreads();
+    }
+    // partial gradient of this workgroup's points, and its loss
+    float *out = partials + (size_t)blockIdx.x * (SUR_NPARAM + 1);
+    for (int q = t; q <= SUR_NPARAM; q += 256) {
+        float v = 0.f;
+        if (q < SUR_B1) {
+            const int k = q / SUR_NH, u = q % SUR_NH;
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += X[k][pp] * D[0][u][pp];
+        } else if (q < SUR_W2) {
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += D[0][q - SUR_B1][pp];
+        } else if (q < SUR_B2) {
+            const int i = (q - SUR_W2) / SUR_NH, u = (q - SUR_W2) % SUR_NH;
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += Hh[0][i][pp] * D[1][u][pp];
+        } else if (q < SUR_W3) {
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += D[1][q - SUR_B2][pp];
+        } else if (q < SUR_B3) {
+            const int i = (q - SUR_W3) / SUR_NH, u = (q - SUR_W3) % SUR_NH;
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += Hh[1][i][pp] * D[2][u][pp];
+        } else if (q < SUR_W4) {
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += D[2][q - SUR_B3][pp];
+        } else if (q < SUR_B4) {
+            const int k = (q - SUR_W4) / SUR_NOUT, o = (q - SUR_W4) % SUR_NOUT;
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += Hh[2][k][pp] * D4[o][pp];
+        } else if (q < SUR_NPARAM) {
+            for (int pp = 0; pp < SG32_PTS; ++pp) v += D4[q - SUR_B4][pp];
+        } else {
+            for (int o = 0; o < SUR_NOUT; ++o)
+                for (int pp = 0; pp < SG32_PTS; ++pp) v += Lp[o][pp];
+        }
+        out[q] = v;
+    }
+}
+
+int sur_grad32_blocks(int64_t n) { return (int)((n + SG32_PTS - 1) / SG32_PTS); }
+
+hipError_t launch_sur_grad32(const float *w, const float *data, int64_t n, float scale, float *partials,
+                             hipStream_t s)
+{
+    if (n < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sur_grad32, dim3((unsigned)sur_grad32_blocks(n)), dim3(256), 0, s, w, data, n, scale,
+                       partials);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // gradient without allocation: a fixed device array holds the packed network,
 // the interleaved records and the workgroup partials
 // ---------------------------------------------------------------------------

@@ -76,13 +76,45 @@ def test_gradient_matches_fp64_reference():
     assert abs(L - Lr) <= 2e-3 * Lr
     err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
     cos = float(g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr)))
-    assert err <= 3e-2 and cos >= 0.999, (err, cos)
+    # the reference rounds every matrix-core operand to bf16 as the device
+    # does (inputs, weights, activations, back-propagated errors); what is
+    # left is FP32 summation order and an occasional one-ulp rounding flip
+    assert err <= 2e-2 and cos >= 0.999, (err, cos)
     o = 0
     for shp in mlp.SHAPES:                              # every parameter block, bias blocks included
         k = int(np.prod(shp))
         gb, rb = g[o:o + k], gr[o:o + k]
-        assert np.linalg.norm(gb - rb) <= 6e-2 * np.linalg.norm(rb) + 1e-9, (o, k)
+        assert np.linalg.norm(gb - rb) <= 2e-2 * np.linalg.norm(rb) + 1e-9, (o, k)
         o += k
+
+
+def test_fp32_gradient_matches_fp64_reference_elementwise():
+    """The FP32 variant of the training gradient against the FP64 reference,
+    element by element: every element within 1e-5 of its own value, or of a
+    tenth of the largest element of its parameter block where it is smaller
+    (an element that cancels over the batch keeps the FP32 rounding of its
+    larger terms: measured 4e-10 on an element of 7e-6 in a block of 4e-3)."""
+    _note("surrogate fp32 gradient vs oracle")
+    rs = np.random.default_rng(3)
+    w = _noisy_weights(7)
+    n = 300                                              # not a multiple of the 16-point workgroup
+    x = rs.uniform(-2, 2, size=(n, 10)).astype(np.float32)
+    t = rs.uniform(-1, 1, size=(n, 10)).astype(np.float32)
+    g, L = pdn.surrogate_grad_fp32(w, x, t)
+    Lr, gr = mlp.grad(w.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    assert abs(L - Lr) <= 1e-6 * Lr
+    o = 0
+    worst, where = 0.0, None
+    for b, shp in enumerate(mlp.SHAPES):
+        k = int(np.prod(shp))
+        gb, rb = g[o:o + k].astype(np.float64), gr[o:o + k]
+        scale = np.maximum(np.abs(rb), 0.1 * np.abs(rb).max())
+        q = np.abs(gb - rb) / scale
+        i = int(np.argmax(q))
+        if q[i] > worst:
+            worst, where = float(q[i]), (b, i, float(gb[i]), float(rb[i]), float(np.abs(rb).max()))
+        o += k
+    assert worst <= 1e-5, (worst, where)
 
 
 def test_training_reduces_validation_error():
@@ -103,14 +135,14 @@ def _cdm_case():
                   ply_thickness=0.5e-3, v0=20.0, mass=0.02, R=4e-3, precision=W.PREC_MIXED)
 
 
-def _trained_networks(cfg, steps=500):
+def _trained_networks(cfg, steps=500, n_paths=60000, batch=16384):
     lc = (cfg["mesh"]["lx"] / cfg["mesh"]["nx"] * cfg["mesh"]["ly"] / cfg["mesh"]["ny"] *
           cfg["mesh"]["ply_thickness"] / cfg["mesh"]["elems_per_ply"]) ** (1.0 / 3.0)
     nets = {}
     for p, m in enumerate(cfg["materials"]):
         key = (m["YT"], m["SL"])
         if key not in nets:
-            nets[key] = pdn.surrogate_train(m, lc, n_paths=60000, steps=steps, batch=16384, lr=3e-3,
+            nets[key] = pdn.surrogate_train(m, lc, n_paths=n_paths, steps=steps, batch=batch, lr=3e-3,
                                             lr_final=1e-4)[0]
     return [nets[(m["YT"], m["SL"])] for m in cfg["materials"]]
 
@@ -204,3 +236,146 @@ def test_surrogate_runs_and_training_are_reproducible():
     assert ia["sur_consulted"] > 0 and ia["fallback_fraction"] < 1.0      # network outputs were accepted
     assert np.array_equal(da, db) and np.array_equal(ra, rb) and np.array_equal(fa, fb)
     assert ia["fallback_fraction"] == ib["fallback_fraction"]
+
+
+def test_surrogate_multi_tile_runs_repeat_bitwise():
+    """A plate of several 15 x 15 tiles, whose rim elements two workgroups
+    evaluate, with network outputs accepted (residual bar 1): two runs give
+    the same state bit for bit.  Rim elements keep the exact law (the other
+    workgroup may read their thresholds before or after the update), so no
+    result depends on the order in which workgroups run."""
+    _note("surrogate reproducibility on a 40x40x4 plate (9 tiles)")
+    cfg = W.tiny(40, 40, 4, 1, angles=[0, 90, 0, 90], law=W.LAW_CDM, lx=20e-3, ly=20e-3,
+                 ply_thickness=0.5e-3, v0=20.0, mass=0.05, R=4e-3, precision=W.PREC_MIXED)
+    nets = _trained_networks(cfg, steps=300)
+    out = []
+    for _ in range(2):
+        g = pdn.Simulation(cfg, tile=(15, 15))
+        for p, w in enumerate(nets):
+            g.surrogate_set(p, w, 0.05, 1.0)
+        g.surrogate_kernel(1)
+        for _ in range(4):
+            g.step(150)
+        out.append((g.array_get(pdn.ARR_DISP), g.array_get(pdn.ARR_GP_R), g.contact_force()[1], g.info()))
+        g.close()
+    (da, ra, fa, ia), (db, rb, fb, ib) = out
+    assert ia["sur_consulted"] > 0 and ia["fallback_fraction"] < 1.0      # network outputs were accepted
+    assert ia["sur_network_steps"] == 600
+    assert np.array_equal(da, db) and np.array_equal(ra, rb) and np.array_equal(fa, fb)
+
+
+def test_surrogate_build_is_chosen_per_call():
+    """Default mode: a call runs the network build only when the previous call
+    met points outside the law's screen (or a network was just set).  A gentle
+    impact never leaves the screen: only the first call runs the network
+    build, and the run equals the plain law bit for bit.  A damaging impact
+    brings the network build back once points leave the screen."""
+    _note("surrogate per-call build choice")
+    cfg = W.tiny(12, 12, 4, 1, angles=[0, 90, 0, 90], law=W.LAW_CDM, lx=12e-3, ly=12e-3,
+                 ply_thickness=0.5e-3, v0=0.5, mass=0.02, R=4e-3, precision=W.PREC_MIXED)
+    cfg["impactor"]["gap"] = 1e-7
+    w = _noisy_weights(11)
+    a, b = pdn.Simulation(cfg), pdn.Simulation(cfg)
+    for p in range(len(cfg["materials"])):
+        b.surrogate_set(p, w, 1.0, 1e9)
+    for _ in range(3):
+        a.step(100)
+        b.step(100)
+    assert b.info()["sur_network_steps"] == 100 and b.info()["sur_consulted"] == 0.0
+    assert np.array_equal(a.array_get(pdn.ARR_DISP), b.array_get(pdn.ARR_DISP))
+    # a damaging impact: points leave the screen, later calls run the network build
+    c = pdn.Simulation(_cdm_case())
+    nets = _trained_networks(_cdm_case(), steps=300)
+    for p, wn in enumerate(nets):
+        c.surrogate_set(p, wn, 0.05, 1e-3)
+    steps = []
+    for _ in range(8):
+        c.step(50)
+        steps.append(c.info()["sur_network_steps"])
+    assert c.info()["sur_consulted"] > 0
+    assert steps[0] == 50 and steps[-1] > 100, steps
+    for s in (a, b, c):
+        s.close()
+
+
+def _softened_state(g, cfg, stretch):
+    """Thresholds just past onset at every Gauss point (r = 1 + U(0, 0.02),
+    seeded; damage below the 0.05 bar at the benchmark plate's element
+    size), so that no point passes the law's screen; with `stretch`, also
+    the displacement of a uniform in-plane stretch at half the transverse
+    onset strain Y_T / E2 in x and y (a strain inside the network's
+    training range at every point)."""
+    m = cfg["mesh"]
+    if stretch:
+        mat = cfg["materials"][0]
+        eps = 0.5 * mat["YT"] / mat["E2"]
+        nx, ny = m["nx"], m["ny"]
+        nn = g.info()["n_nodes"]
+        k = np.arange(nn)
+        i, j = k % (nx + 1), (k // (nx + 1)) % (ny + 1)
+        d = np.zeros((nn, 3))
+        d[:, 0] = eps * m["lx"] * i / nx
+        d[:, 1] = eps * m["ly"] * j / ny
+        g.array_set(pdn.ARR_DISP, d.reshape(-1))
+    n = g.info()["n_bulk"]
+    r = 1.0 + W.rng(0x6A1B5).uniform(0.0, 0.02, 4 * n)
+    r[0::4] = np.maximum(r[0::4], r[1::4])
+    r[2::4] = np.maximum(r[2::4], r[3::4])
+    g.array_set(pdn.ARR_GP_R, r)
+
+
+def test_what_the_network_gains_over_the_exact_law():
+    """The trained network against the method without it, where it is used:
+    the 150 x 100-column cut of the benchmark plate (its element size and
+    laminate) with every Gauss point's thresholds just past onset, so that
+    every point consults the network, (a) at rest and (b) released from a
+    uniform in-plane stretch at half the transverse onset strain.  Each is
+    stepped by the exact law and by the network at the residual bars 1e-3
+    (the stated one) and 1.  Every point is consulted; no more points are
+    accepted at 1e-3 than at 1; at the stated bar the network's answers are
+    taken on under 1 % of the points (its bf16 operands limit its accuracy
+    to about 1e-2), so the run stays with the exact law.  The times per
+    Gauss-point update and the accepted shares are printed: the network
+    build costs about four times the exact law per consulted point on this
+    hardware (measured 1.42 against 0.35 ns), so the network gains nothing
+    in time and, at the stated bar, nothing in what it computes."""
+    _note("surrogate gains over the exact law, 150x100x16 cut, every point consulted")
+    import time
+    cfg = W.plate_qi8_150x100x16_cut(W.PREC_MIXED)
+    cfg["impactor"]["gap"] = 1.0
+    nets = _trained_networks(cfg, steps=4000, n_paths=1_000_000, batch=65536)
+    for stretch in (False, True):
+        res = {}
+        for name, bar in (("exact", None), ("net_1e-3", 1e-3), ("net_1", 1.0)):
+            g = pdn.Simulation(cfg)
+            g.step(1)
+            _softened_state(g, cfg, stretch)
+            if bar is not None:
+                for p, wn in enumerate(nets):
+                    g.surrogate_set(p, wn, 0.05, bar)
+                g.surrogate_kernel(1)
+            g.step(1)
+            n = g.info()["n_bulk"]
+            c0, f0 = g.info()["sur_consulted"], g.info()["sur_consulted"] * g.info()["fallback_fraction"]
+            t0 = time.perf_counter()
+            g.step(100)                                   # returns when the stream has drained
+            el = time.perf_counter() - t0
+            info = g.info()
+            cons = info["sur_consulted"] - c0
+            fb = info["sur_consulted"] * info["fallback_fraction"] - f0
+            res[name] = dict(ns_per_gp=1e9 * el / (100 * n), consulted=cons / (100 * n),
+                             accepted=(1.0 - fb / cons) if cons else 0.0, disp=g.array_get(pdn.ARR_DISP))
+            g.close()
+        ex, lo, hi = res["exact"], res["net_1e-3"], res["net_1"]
+        scale = np.abs(ex["disp"]).max()
+        d_lo = np.abs(lo["disp"] - ex["disp"]).max() / scale
+        d_hi = np.abs(hi["disp"] - ex["disp"]).max() / scale
+        what = "stretched" if stretch else "at rest"
+        print(f"[surrogate gains, {what}] ns per GP update: exact law {ex['ns_per_gp']:.3f}, network bar "
+              f"1e-3 {lo['ns_per_gp']:.3f} (accepted {lo['accepted']:.2e}, displacement diff {d_lo:.2e}), "
+              f"network bar 1 {hi['ns_per_gp']:.3f} (accepted {hi['accepted']:.2e}, displacement diff "
+              f"{d_hi:.2e})", flush=True)
+        assert lo["consulted"] == 1.0 and hi["consulted"] == 1.0    # every point asks the network
+        assert lo["accepted"] <= hi["accepted"]
+        # at the stated bar the network's answers are rarely taken: the run is the exact law's
+        assert lo["accepted"] < 1e-2 and d_lo <= 1e-3
