@@ -338,6 +338,40 @@ int pdn_surrogate_data(int32_t device, void *stream, const pdn_material *m, doub
 #define PDN_SUR_GRAD_NOALLOC_MAX 16384
 int pdn_surrogate_grad_noalloc(int32_t device, void *stream, const float *weights, const float *x, const float *t,
                                int64_t n, float *grad, double *loss);
+/* ---- mesh multiplication ----------------------------------------------------
+ * Section 2.4, Eq. (mmu) and Algorithm 3: ndivi division levels of a
+ * hexahedral mesh with 8-node interface elements, on the device.  One level
+ * splits every edge at its midpoint and every face at its centre and adds a
+ * node at the centre of every bulk element: a bulk hexahedron becomes eight.
+ * An interface element (zero thickness; nodes 0-3 its bottom face, 4-7 the
+ * coincident top face, the stacking direction from bottom to top) is divided
+ * only by planes parallel to its normal: it becomes four, its edges across
+ * the thickness and its lateral faces are not divided and it has no centre.
+ * Node order of both element kinds: bottom face counter-clockwise, then top.
+ * Numbering of each new level: old nodes first; then edge midpoints in
+ * ascending (smaller, larger end node); then face centres in ascending
+ * (smallest node, node diagonally opposite it); then bulk centres in element
+ * order.  Children of bulk element e are 8e..8e+7 (octant i + 2j + 4k of its
+ * natural coordinates), of interface element c are 4c..4c+3 (quadrant
+ * i + 2j); tags (e.g. plies; may be NULL) are inherited.  Positions are the
+ * averages of the edge's, face's (ascending node numbers) or element's
+ * nodes.  All arrays are host arrays: coords 3*n_nodes, hexes 8*n_bulk, cohs
+ * 8*n_interface (int32 node numbers).  counts receives the divided mesh's
+ * sizes and, for the last level, the base mesh's divided edges and faces and
+ * its boundary faces (used by one element; of them, interface lateral faces),
+ * the terms of Eq. (mmu).  With NULL outputs or capacities too small, only
+ * counts is filled and the call returns PDN_ERANGE.  PDN_EINVAL: negative
+ * sizes, ndivi outside 0..6, node numbers out of range, or a divided mesh
+ * beyond int32 numbering; reason in pdn_global_last_error(). */
+typedef struct {
+    int64_t n_nodes, n_bulk, n_interface;
+    int64_t n_edges, n_faces, n_boundary0, n_boundary_interface0;
+} pdn_mmu_counts;
+int pdn_mesh_multiply(int32_t device, void *stream, const double *coords, int64_t n_nodes, const int32_t *hexes,
+                      int64_t n_bulk, const int32_t *cohs, int64_t n_interface, const int32_t *hex_tag,
+                      const int32_t *coh_tag, int32_t ndivi, double *coords_out, int32_t *hexes_out,
+                      int32_t *cohs_out, int32_t *hex_tag_out, int32_t *coh_tag_out, int64_t cap_nodes,
+                      int64_t cap_bulk, int64_t cap_interface, pdn_mmu_counts *counts);
 const char *pdn_global_last_error(void);
 
 #ifdef __cplusplus

@@ -64,6 +64,11 @@ class Energy(C.Structure):
                                           "w_contact_plate", "w_striker", "d_pdn", "ke0", "u_el", "residual")]
 
 
+class MmuCounts(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in ("n_nodes", "n_bulk", "n_interface", "n_edges", "n_faces",
+                                          "n_boundary0", "n_boundary_interface0")]
+
+
 class Info(C.Structure):
     _fields_ = [("dt", C.c_double)] + [(f, C.c_int64) for f in (
         "n_nodes", "n_bulk", "n_cohesive", "n_pairs", "n_planes", "n_layers", "n_candidates",
@@ -117,6 +122,9 @@ def lib():
             "pdn_surrogate_grad_fp32": [C.c_int32, vp, P(C.c_float), P(C.c_float), P(C.c_float), i64,
                                         P(C.c_float), P(C.c_double)],
             "pdn_stream_copy": [C.c_int32, vp, vp, vp, i64],
+            "pdn_mesh_multiply": [C.c_int32, vp, P(C.c_double), i64, P(C.c_int32), i64, P(C.c_int32), i64,
+                                  P(C.c_int32), P(C.c_int32), C.c_int32, P(C.c_double), P(C.c_int32),
+                                  P(C.c_int32), P(C.c_int32), P(C.c_int32), i64, i64, i64, P(MmuCounts)],
             "pdn_global_last_error": [],
         }
         for name, args in sig.items():
@@ -223,6 +231,33 @@ def stream_copy(src_ptr: int, dst_ptr: int, nbytes: int, device=0, stream=None):
     rc = lib().pdn_stream_copy(device, stream, src_ptr, dst_ptr, nbytes)
     if rc != 0:
         raise PdnError(rc, "pdn_stream_copy: bad size, alignment or device")
+
+
+def _ip(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def mesh_multiply(coords, hexes, cohs, ndivi: int, hex_tag=None, coh_tag=None, device=0, stream=None):
+    """pdn_mesh_multiply: ndivi division levels on the device.  Returns
+    (coords, hexes, cohs, hex_tag, coh_tag, counts)."""
+    X = np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 3)
+    H = np.ascontiguousarray(hexes, dtype=np.int32).reshape(-1, 8)
+    Cc = np.ascontiguousarray(cohs, dtype=np.int32).reshape(-1, 8)
+    ht = None if hex_tag is None else np.ascontiguousarray(hex_tag, dtype=np.int32)
+    ct = None if coh_tag is None else np.ascontiguousarray(coh_tag, dtype=np.int32)
+    cnt = MmuCounts()
+    args = (device, stream, _dp(X), len(X), _ip(H), len(H), _ip(Cc), len(Cc), _ip(ht), _ip(ct), ndivi)
+    rc = lib().pdn_mesh_multiply(*args, None, None, None, None, None, 0, 0, 0, C.byref(cnt))
+    if rc != -6:
+        _gchk(rc)
+    Xo = np.zeros((cnt.n_nodes, 3))
+    Ho = np.zeros((cnt.n_bulk, 8), np.int32)
+    Co = np.zeros((cnt.n_interface, 8), np.int32)
+    hto = None if ht is None else np.zeros(cnt.n_bulk, np.int32)
+    cto = None if ct is None else np.zeros(cnt.n_interface, np.int32)
+    _gchk(lib().pdn_mesh_multiply(*args, _dp(Xo), _ip(Ho), _ip(Co), _ip(hto), _ip(cto), len(Xo), len(Ho), len(Co),
+                                  C.byref(cnt)))
+    return Xo, Ho, Co, hto, cto, {f: getattr(cnt, f) for f, _ in MmuCounts._fields_}
 
 
 def surrogate_data(mat: dict, crack_band: float, p0: int, n_paths: int, increments=32, seed=SUR_SEED,

@@ -1910,6 +1910,77 @@ int pdn_surrogate_grad(int32_t device, void *stream, const float *weights, const
     return PDN_OK;
 }
 
+int pdn_mesh_multiply(int32_t device, void *stream, const double *coords, int64_t n_nodes, const int32_t *hexes,
+                      int64_t n_bulk, const int32_t *cohs, int64_t n_interface, const int32_t *hex_tag,
+                      const int32_t *coh_tag, int32_t ndivi, double *coords_out, int32_t *hexes_out,
+                      int32_t *cohs_out, int32_t *hex_tag_out, int32_t *coh_tag_out, int64_t cap_nodes,
+                      int64_t cap_bulk, int64_t cap_interface, pdn_mmu_counts *counts)
+{
+    if (!counts || n_nodes < 0 || n_bulk < 0 || n_interface < 0 || ndivi < 0 || ndivi > 6 ||
+        (n_nodes > 0 && !coords) || (n_bulk > 0 && !hexes) || (n_interface > 0 && !cohs) || n_nodes > INT32_MAX)
+        return gerr(PDN_EINVAL, "mesh multiplication: invalid argument");
+    for (int64_t i = 0; i < 8 * n_bulk; ++i)
+        if (hexes[i] < 0 || hexes[i] >= n_nodes) return gerr(PDN_EINVAL, "mesh multiplication: bulk node out of range");
+    for (int64_t i = 0; i < 8 * n_interface; ++i)
+        if (cohs[i] < 0 || cohs[i] >= n_nodes)
+            return gerr(PDN_EINVAL, "mesh multiplication: interface node out of range");
+    std::memset(counts, 0, sizeof *counts);
+    GHIPCHK(hipSetDevice(device));
+    hipStream_t s = (hipStream_t)stream;
+    // current level on the device (freed as levels are replaced)
+    struct Level {
+        double *X = nullptr;
+        int32_t *H = nullptr, *C = nullptr, *ht = nullptr, *ct = nullptr;
+        void release()
+        {
+            for (void *p : {(void *)X, (void *)H, (void *)C, (void *)ht, (void *)ct})
+                if (p) (void)hipFree(p);
+            X = nullptr; H = C = ht = ct = nullptr;
+        }
+        ~Level() { release(); }
+    } cur, nxt;
+    auto up = [&](void **d, const void *h, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(d, bytes ? bytes : 1);
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(*d, h, bytes, hipMemcpyHostToDevice, s);
+        return e;
+    };
+    GHIPCHK(up((void **)&cur.X, coords, 3 * n_nodes * sizeof(double)));
+    GHIPCHK(up((void **)&cur.H, hexes, 8 * n_bulk * sizeof(int32_t)));
+    GHIPCHK(up((void **)&cur.C, cohs, 8 * n_interface * sizeof(int32_t)));
+    if (hex_tag) GHIPCHK(up((void **)&cur.ht, hex_tag, n_bulk * sizeof(int32_t)));
+    if (coh_tag) GHIPCHK(up((void **)&cur.ct, coh_tag, n_interface * sizeof(int32_t)));
+    int64_t nn = n_nodes, nh = n_bulk, nc = n_interface;
+    for (int lv = 0; lv < ndivi; ++lv) {
+        pdn::MmuLevel info{};
+        const hipError_t e = pdn::mmu_divide(cur.X, nn, cur.H, nh, cur.C, nc, cur.ht, cur.ct, &nxt.X, &nxt.H, &nxt.C,
+                                             &nxt.ht, &nxt.ct, &info, s);
+        if (e == hipErrorInvalidValue) return gerr(PDN_EINVAL, "mesh multiplication: the divided mesh exceeds int32 numbering");
+        GHIPCHK(e);
+        cur.release();
+        std::swap(cur.X, nxt.X); std::swap(cur.H, nxt.H); std::swap(cur.C, nxt.C);
+        std::swap(cur.ht, nxt.ht); std::swap(cur.ct, nxt.ct);
+        nn = info.nn; nh = info.nh; nc = info.nc;
+        counts->n_edges = info.n_edges;
+        counts->n_faces = info.n_faces;
+        counts->n_boundary0 = info.nb0;
+        counts->n_boundary_interface0 = info.nb_int0;
+    }
+    counts->n_nodes = nn;
+    counts->n_bulk = nh;
+    counts->n_interface = nc;
+    if (!coords_out || !hexes_out || !cohs_out || cap_nodes < nn || cap_bulk < nh || cap_interface < nc ||
+        (hex_tag && !hex_tag_out) || (coh_tag && !coh_tag_out))
+        return gerr(PDN_ERANGE, "mesh multiplication: outputs need %lld nodes, %lld bulk and %lld interface elements",
+                    (long long)nn, (long long)nh, (long long)nc);
+    if (nn) GHIPCHK(hipMemcpyAsync(coords_out, cur.X, 3 * nn * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (nh) GHIPCHK(hipMemcpyAsync(hexes_out, cur.H, 8 * nh * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (nc) GHIPCHK(hipMemcpyAsync(cohs_out, cur.C, 8 * nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (hex_tag && nh) GHIPCHK(hipMemcpyAsync(hex_tag_out, cur.ht, nh * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (coh_tag && nc) GHIPCHK(hipMemcpyAsync(coh_tag_out, cur.ct, nc * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GHIPCHK(hipStreamSynchronize(s));
+    return PDN_OK;
+}
+
 int pdn_surrogate_grad_fp32(int32_t device, void *stream, const float *weights, const float *x, const float *t,
                             int64_t n, float *grad, double *loss)
 {

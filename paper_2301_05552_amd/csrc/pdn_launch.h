@@ -50,6 +50,16 @@ template <typename R>
 hipError_t launch_elem_node_batch_sur(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
                                       hipStream_t s);
 
+// mesh multiplication (pdn_mmu.hip): one division level on the device
+struct MmuLevel {
+    int64_t nn, nh, nc;              // the divided mesh
+    int64_t n_edges, n_faces;        // divided edges and faces of the base mesh
+    int64_t nb0, nb_int0;            // boundary faces of the base mesh (of them, interface lateral faces)
+};
+hipError_t mmu_divide(const double *X, int64_t nn, const int32_t *H, int64_t nh, const int32_t *C, int64_t nc,
+                      const int32_t *htag, const int32_t *ctag, double **Xo, int32_t **Ho, int32_t **Co,
+                      int32_t **hto, int32_t **cto, MmuLevel *info, hipStream_t s);
+
 int elem_node_lds_bytes(int mixed, int tile, bool sur);   // static LDS of one workgroup (-1 on error)
 int elem_node_lds_bytes_sur(int mixed, int tile);
 hipError_t launch_contact_init(const ContactArgs &c, int reset_active, hipStream_t s);

@@ -322,6 +322,77 @@ def tiny(nx=4, ny=4, n_plies=2, elems_per_ply=1, *, angles=None, cohesive=0,
 
 
 # ---------------------------------------------------------------------------
+# explicit (unstructured) hexahedral meshes, for the mesh multiplication
+# ---------------------------------------------------------------------------
+
+def hex_mesh(mesh: dict):
+    """The plate of a workload mesh dict as an explicit mesh: node coordinates
+    (n_nodes x 3), bulk hex8 and 8-node interface connectivity (node order:
+    bottom face counter-clockwise from (-,-), then the top face; an interface
+    element's bottom and top nodes are the coincident nodes of the duplicated
+    plane) and the ply of each element.  Node n = i + (nx+1)(j + (ny+1)k) on
+    node plane k; elements i fastest, then j, then layer."""
+    nx, ny, P, epp = mesh["nx"], mesh["ny"], mesh["n_plies"], mesh["elems_per_ply"]
+    ang = mesh["ply_angle_deg"]
+    hz = mesh["ply_thickness"] / epp
+    coh_layer, ply = [], []
+    for p in range(P):
+        for _ in range(epp):
+            coh_layer.append(False)
+            ply.append(p)
+        if mesh.get("cohesive", 0) and p + 1 < P and ang[p] != ang[p + 1]:
+            coh_layer.append(True)
+            ply.append(p)
+    K = len(coh_layer) + 1
+    z = np.zeros(K)
+    for l, c in enumerate(coh_layer):
+        z[l + 1] = z[l] + (0.0 if c else hz)
+    i, j, k = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), np.arange(K), indexing="ij")
+    nid = lambda a, b, c: a + (nx + 1) * (b + (ny + 1) * c)
+    coords = np.zeros(((nx + 1) * (ny + 1) * K, 3))
+    n = nid(i, j, k).reshape(-1)
+    coords[n, 0] = mesh["lx"] * i.reshape(-1) / nx
+    coords[n, 1] = mesh["ly"] * j.reshape(-1) / ny
+    coords[n, 2] = z[k.reshape(-1)]
+    ie, je = np.meshgrid(np.arange(nx), np.arange(ny), indexing="xy")
+    ie, je = ie.reshape(-1), je.reshape(-1)
+    hexes, cohs, hply, cply = [], [], [], []
+    for l, c in enumerate(coh_layer):
+        e = np.stack([nid(ie, je, l), nid(ie + 1, je, l), nid(ie + 1, je + 1, l), nid(ie, je + 1, l),
+                      nid(ie, je, l + 1), nid(ie + 1, je, l + 1), nid(ie + 1, je + 1, l + 1),
+                      nid(ie, je + 1, l + 1)], axis=1)
+        (cohs if c else hexes).append(e)
+        (cply if c else hply).append(np.full(len(e), ply[l]))
+    cat = lambda a: np.concatenate(a).astype(np.int32) if a else np.zeros((0, 8), np.int32)
+    return (coords, cat(hexes), cat(cohs),
+            np.concatenate(hply).astype(np.int32) if hply else np.zeros(0, np.int32),
+            np.concatenate(cply).astype(np.int32) if cply else np.zeros(0, np.int32))
+
+
+def renumbered(coords, hexes, cohs, seed: int, distort: float = 0.0):
+    """A seeded random renumbering of the nodes and a shuffle of the element
+    order of an explicit mesh, with the in-plane node positions moved by up
+    to `distort` times the smallest in-plane spacing (the same move for the
+    coincident nodes of an interface, so it keeps zero thickness)."""
+    g = rng(seed)
+    perm = g.permutation(len(coords))              # old node -> new node
+    out = np.zeros_like(coords)
+    out[perm] = coords
+    if distort > 0:
+        xs = np.unique(np.round(coords[:, 0], 12))
+        ys = np.unique(np.round(coords[:, 1], 12))
+        h = min(np.diff(xs).min(), np.diff(ys).min())
+        key = np.round(coords[:, :2] / (1e-9 * h)).astype(np.int64)
+        _, col = np.unique(key, axis=0, return_inverse=True)
+        mv = g.uniform(-distort * h, distort * h, size=(col.max() + 1, 2))
+        out[perm, 0] += mv[col.reshape(-1), 0]
+        out[perm, 1] += mv[col.reshape(-1), 1]
+    he = perm[hexes][g.permutation(len(hexes))] if len(hexes) else hexes
+    ce = perm[cohs][g.permutation(len(cohs))] if len(cohs) else cohs
+    return out, he.astype(np.int32), ce.astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
 # synthetic states (seeded) for one-step parity at any size
 # ---------------------------------------------------------------------------
 
