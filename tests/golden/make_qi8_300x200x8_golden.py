@@ -11,10 +11,16 @@ the force averaged over the last FILTER steps (a trailing moving average,
 about 12 us): the kinematic contact makes the per-step force spiky, and the
 maximum of the raw history is a property of its noise, not of the impact.
 
-Only the oracle and the input generators are called.  Usage (about two and a
-half hours on 6 cores):
+With --reverse-assembly the oracle sums the nodal forces in descending
+element order: the same arithmetic in another order.  That run, stored
+beside the first, measures how far this impact amplifies rounding by itself.
+
+Only the oracle and the input generators are called.  Usage (about three
+hours on 6 cores each):
 
     python tests/golden/make_qi8_300x200x8_golden.py [--threads 6] [--t-end 4.5e-3]
+    python tests/golden/make_qi8_300x200x8_golden.py --reverse-assembly \
+        --out tests/golden/qi8_300x200x8_fp64_oracle_reversed.json
 """
 import argparse
 import json
@@ -64,10 +70,14 @@ def main():
     ap.add_argument("--t-end", type=float, default=4.5e-3)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                   "qi8_300x200x8_fp64_oracle.json"))
+    ap.add_argument("--reverse-assembly", action="store_true",
+                    help="sum nodal forces in descending element order (a second realization of the "
+                         "same arithmetic in another order, for the problem's own sensitivity)")
     args = ap.parse_args()
     oracle.build(force=False)
     cfg = W.plate_qi8_300x200x8(W.PREC_FP64)
     o = oracle.Oracle(cfg, threads=args.threads)
+    o.set_assembly_order(args.reverse_assembly)
     steps = int(math.ceil(args.t_end / o.dt))
     t0 = time.time()
     done = 0
@@ -89,6 +99,7 @@ def main():
         "source": "FP64 oracle (oracle/pdn_oracle.c) on workloads.plate_qi8_300x200x8, written by make_qi8_300x200x8_golden.py",
         "basis": "laminate, supports and striker of the drop-weight coupon (Sec. 4), Table 1 material; "
                  "contact force and projected damage are the outputs of Tabs. 2 and 4 and Fig. 9",
+        "assembly_order": "descending" if args.reverse_assembly else "ascending",
         "dt": o.dt, "steps": steps, "t_end": float(t[-1]),
         "peak_force_N": float(f[i]), "t_peak_s": float(t[i]),
         "filter_steps": FILTER,
