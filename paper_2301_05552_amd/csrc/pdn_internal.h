@@ -90,8 +90,6 @@ struct ElemArgs {
     const double *d_in, *v_in;       // state at level n (AoS xyz)
     double *d_out, *v_out;           // predictor for level n+1
     R *r;                            // 4 per bulk GP
-    R *ep;                           // 4 per bulk GP (plastic gamma12, gamma13, accumulated, unused);
-                                     // null unless a ply is plastic (then the plastic kernel runs)
     R *rd;                           // 1 per cohesive node pair
     const R *hx, *hy;                // element sizes (nx, ny)
     const R *ihx, *ihy;              // their reciprocals
@@ -127,6 +125,11 @@ struct ElemArgs {
     // the build without the network steps surrogate plies (exact law): count
     // their points that the screen does not pass
     int count_sur;
+    // 4 per bulk GP (plastic gamma12, gamma13, accumulated, unused); null unless
+    // a ply is plastic (then the plastic kernel runs).  Last: a field inserted
+    // among the ones above moved their offsets and cost the batched kernel
+    // (which copies its arguments from a table) 6 % of its time.
+    R *ep;
 };
 
 // candidate bookkeeping of the contact step (initialisation, state arrays)
