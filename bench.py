@@ -307,15 +307,20 @@ def batched_leg(steps: int, warmup: int, stream) -> dict:
                          "algorithmic_bytes_per_step": nbytes}}
 
 
-def full_integration_leg(stream, pre, warmup, steps, plain_ms) -> dict:
+def full_integration_leg(stream, pre, warmup, steps, plain_ms, plastic=False) -> dict:
     """The 1200 x 800 x 16 plate with full 2x2x2 Gauss integration of the bulk
     elements (the paper's element; eight Gauss-point updates per element and
-    step, each with its own thresholds), in mixed precision, autotuned tile."""
+    step, each with its own thresholds), in mixed precision, autotuned tile.
+    With `plastic`, every ply also has Table 1's shear plasticity (a plastic
+    state per Gauss point: the paper's element with the paper's law)."""
     import torch
     import paper_2301_05552_amd as pdn
     import workloads as W
     cfg = W.plate_qi8_1200x800x16(1)
     cfg["mesh"]["integration"] = 8
+    if plastic:
+        for m in cfg["materials"]:
+            m["Sp"], m["Kp"] = W.AS4_SP, W.AS4_KP
     sim = pdn.Simulation(cfg, stream=stream)
     sim.step(0)                          # set-up before the tile autotuner times its passes
     tx, ty = sim.autotune()
@@ -331,11 +336,15 @@ def full_integration_leg(stream, pre, warmup, steps, plain_ms) -> dict:
     info = sim.info()
     sim.close()
     ngp = 8 * info["n_bulk"]
-    # 96 B per node, four FP32 thresholds read + written per Gauss point, 8 B per pair
-    nbytes = 96.0 * info["n_nodes"] + 8 * 32.0 * info["n_bulk"] + 8.0 * info["n_pairs"]
+    # 96 B per node, four FP32 thresholds (and with plasticity four FP32 plastic
+    # words) read + written per Gauss point, 8 B per pair
+    per_gp = 64.0 if plastic else 32.0
+    nbytes = 96.0 * info["n_nodes"] + 8 * per_gp * info["n_bulk"] + 8.0 * info["n_pairs"]
     achieved = nbytes / (en_ms * 1e-3) / 1e9
     ms = 1e3 * el / steps
-    return {"workload": "as the headline plate, bulk elements with 2x2x2 Gauss points (8 states each)",
+    what = ("as the headline plate, bulk elements with 2x2x2 Gauss points (8 states each)"
+            + (", every ply with shear plasticity (S_p 62 MPa, K_p 0.1936)" if plastic else ""))
+    return {"workload": what,
             "gauss_points": ngp, "tile": f"{tx}x{ty}", "steps": steps, "ms_per_step": ms,
             "value": ngp * steps / el, "unit": "GP-updates/s", "kernel_ms": en_ms, "books_kernel_ms": bk_ms,
             "element_steps_vs_one_point": plain_ms / ms,
@@ -373,16 +382,20 @@ COUPON_PAPER = {0: {"f_max_kN": 8.70, "d_max_mm": 3.60, "E_dis_J": 7.70, "A_del_
                 1: {"f_max_kN": 8.30, "d_max_mm": 3.70, "E_dis_J": 7.90, "A_del_mm2": 5249.2}}
 
 
-def coupon_leg(levels, stream) -> dict:
+def coupon_leg(levels, stream, full_levels=()) -> dict:
     """The AS4/8552 drop-weight coupon (Section 3.2.2; Table 3's meshes, phi =
-    1.033) run to 5 ms in mixed precision: speed of the whole run and the
-    quantities Table 4 tabulates."""
+    1.033, Table 1's shear plasticity) run to 5 ms in mixed precision: speed
+    of the whole run and the quantities Table 4 tabulates.  Levels in
+    `full_levels` are run again with 2x2x2 Gauss points (the paper's
+    element): keys level<L> and level<L>_full."""
     import torch
     import paper_2301_05552_amd as pdn
     import workloads as W
     out = {}
-    for lv in levels:
+    runs = [(lv, 1) for lv in levels] + [(lv, 8) for lv in full_levels]
+    for lv, ngp in runs:
         cfg = W.coupon_as4(lv, W.PREC_MIXED)
+        cfg["mesh"]["integration"] = ngp
         sim = pdn.Simulation(cfg, stream=stream)
         sim.step(0)                      # set-up (stable time step) without stepping
         info = sim.info()
@@ -390,11 +403,18 @@ def coupon_leg(levels, stream) -> dict:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         done = 0
-        while done < n:
-            k = min(20000, n - done)
-            sim.step(k)
-            done += k
-            log(f"coupon level {lv}: {done}/{n} steps")
+        key = f"level{lv}" + ("_full" if ngp == 8 else "")
+        try:
+            while done < n:
+                k = min(20000, n - done)
+                sim.step(k)
+                done += k
+                log(f"coupon level {lv}{' (full integration)' if ngp == 8 else ''}: {done}/{n} steps")
+        except pdn.PdnError as err:
+            log(f"coupon {key} stopped: {err}")
+            out[key] = {"error": str(err), "steps_before_error_chunk": done, "steps": n}
+            sim.close()
+            continue
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         t, f, x = sim.contact_force()
@@ -402,8 +422,9 @@ def coupon_leg(levels, stream) -> dict:
         m = cfg["mesh"]
         cell = (m["lx"] / m["nx"]) * (m["ly"] / m["ny"])
         dcoh = sim.damage_field(pdn.DMG_PROJ_COHESIVE)
-        out[f"level{lv}"] = {
+        out[key] = {
             "mesh": f"{m['nx']}x{m['ny']} in-plane, {m['elems_per_ply']} element(s) per cluster, 6 interfaces",
+            "integration": "2x2x2 Gauss points" if ngp == 8 else "one point with hourglass control",
             "bulk_gauss_points": info["n_bulk"], "interface_pairs": info["n_pairs"],
             "dt_s": info["dt"], "steps": n, "wall_s": el, "ms_per_step": 1e3 * el / n,
             "value": info["n_bulk"] * n / el, "unit": "GP-updates/s",
@@ -414,6 +435,31 @@ def coupon_leg(levels, stream) -> dict:
                           "D>=0.999": float((dcoh >= 0.999).sum()) * cell * 1e6},
             "paper_numerical": COUPON_PAPER[lv]}
         sim.close()
+    return out
+
+
+def mmu_leg(stream, levels=(1, 2)) -> dict:
+    """Mesh multiplication (Section 2.4, Eq. mmu, Algorithm 3) of the
+    AS4/8552 coupon's level-0 mesh (Table 3), ndivi = 1 and 2, on the device.
+    The call takes and returns host arrays: the time is that of the whole
+    call, transfers and device allocations included (after one untimed call
+    of the same size)."""
+    import paper_2301_05552_amd as pdn
+    import workloads as W
+    cfg = W.coupon_as4(0, W.PREC_MIXED)
+    X, H, C, hp, cp = W.hex_mesh(cfg["mesh"])
+    out = {"base_mesh": f"AS4/8552 coupon level 0: {len(H)} hex8, {len(C)} interface elements, {len(X)} nodes"}
+    for nd in levels:
+        *_, cnt = pdn.mesh_multiply(X, H, C, nd, hp, cp, stream=stream)
+        t0 = time.perf_counter()
+        Xo, Ho, Co, _, _, cnt = pdn.mesh_multiply(X, H, C, nd, hp, cp, stream=stream, counts=cnt)
+        el = time.perf_counter() - t0
+        nbytes = Xo.nbytes + Ho.nbytes + Co.nbytes + 4 * (len(Ho) + len(Co))
+        out[f"ndivi{nd}"] = {"n_bulk": int(cnt["n_bulk"]), "n_interface": int(cnt["n_interface"]),
+                             "n_nodes": int(cnt["n_nodes"]), "wall_s": el,
+                             "elements_per_s": (len(Ho) + len(Co)) / el, "output_bytes": nbytes,
+                             "timing": "whole call, host arrays in and out"}
+        del Xo, Ho, Co
     return out
 
 
@@ -624,6 +670,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-case batched leg")
     ap.add_argument("--batched-steps", type=int, default=1000)
     ap.add_argument("--no-full", action="store_true", help="skip the full-integration leg")
+    ap.add_argument("--coupon-full-levels", default="",
+                    help="coupon levels run again with full integration (comma list; none by default: "
+                         "crushed elements under the striker invert and the run loses stability)")
     ap.add_argument("--coupon-levels", default="0",
                     help="refinement levels of the AS4/8552 coupon run to 5 ms ('' = skip, '0,1' = both)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
@@ -634,6 +683,7 @@ def main():
     ap.add_argument("--no-damaged", action="store_true", help="skip the late and softened windows")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-mode leg")
     ap.add_argument("--no-plastic", action="store_true", help="skip the shear-plasticity leg")
+    ap.add_argument("--no-mmu", action="store_true", help="skip the mesh-multiplication leg")
     ap.add_argument("--max-preroll", type=int, default=2000,
                     help="untimed steps allowed to bring the striker into contact before the warm-up")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -749,10 +799,18 @@ def main():
                                                        res["ms_per_step"])
         log(f"full integration: {res['full_integration']['ms_per_step']:.3f} ms/step, "
             f"tile {res['full_integration']['tile']}")
+        res["full_integration"]["plastic"] = full_integration_leg(stream.cuda_stream, pre, args.warmup,
+                                                                  args.steps // 2, res["ms_per_step"], True)
+        log(f"full integration with plasticity: {res['full_integration']['plastic']['ms_per_step']:.3f} ms/step")
     if args.coupon_levels:
         lvls = [int(v) for v in args.coupon_levels.split(",")]
         log(f"coupon leg: AS4/8552 coupon, levels {lvls}, to 5 ms")
-        res["coupon"] = coupon_leg(lvls, stream.cuda_stream)
+        full = [int(v) for v in args.coupon_full_levels.split(",")] if args.coupon_full_levels else []
+        res["coupon"] = coupon_leg(lvls, stream.cuda_stream, full)
+    if not args.no_mmu:
+        log("mesh multiplication leg: coupon level 0, ndivi 1 and 2")
+        res["mesh_multiplication"] = mmu_leg(stream.cuda_stream)
+        log(f"mesh multiplication: ndivi 2 in {res['mesh_multiplication']['ndivi2']['wall_s']:.3f} s")
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle at 1 thread and at every physical core")
         res["cpu_baseline"] = cpu_baseline(args.cpu_steps)

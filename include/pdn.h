@@ -58,11 +58,13 @@ enum { PDN_DMG_FIBRE = 0, PDN_DMG_MATRIX = 1, PDN_DMG_SHEAR = 2, PDN_DMG_COHESIV
        PDN_DMG_PROJ_FIBRE = 4, PDN_DMG_PROJ_MATRIX = 5, PDN_DMG_PROJ_COHESIVE = 6 };
 enum { PDN_ARR_DISP = 0,    /* 3 * n_nodes: displacement at the last completed level */
        PDN_ARR_VEL = 1,     /* 3 * n_nodes: velocity (TW velocity = CD half-step velocity) */
-       PDN_ARR_GP_R = 2,    /* 4 * n_bulk: damage thresholds r1+, r1-, r2+, r2- per element */
+       PDN_ARR_GP_R = 2,    /* 4 per bulk Gauss point (as PDN_ARR_GP_EP): damage thresholds r1+, r1-,
+                               r2+, r2- */
        PDN_ARR_COH_R = 3,   /* n_pairs: cohesive damage threshold per interface node pair */
        PDN_ARR_MASS = 4,    /* n_nodes: lumped mass (get only) */
-       PDN_ARR_GP_EP = 5 }; /* 3 * n_bulk: plastic state per element: plastic gamma12, gamma13 and
-                               accumulated plastic shear (zeros, and set rejected, without plasticity) */
+       PDN_ARR_GP_EP = 5 }; /* 3 per bulk Gauss point (n_bulk, or 8 n_bulk with full integration, points
+                               of an element consecutive): plastic gamma12, gamma13 and accumulated
+                               plastic shear (zeros, and set rejected, without plasticity) */
 
 /* Plate description (Section 3.2 set-up): nx*ny element columns on lx*ly,
  * n_plies plies of ply_thickness each split into elems_per_ply hex8 layers.
@@ -116,9 +118,9 @@ typedef struct {
      * isotropic hardening of the longitudinal shear tau_L = |(tau12, tau13)|
      * in effective stress, yield when tau_L > Sp + Kp G12 abar (abar the
      * accumulated plastic shear), radial return; the damage criteria act on
-     * the stress of the elastic strains.  Needs G13 = G12, the one-point
-     * element, the 15x15 or 16x16 tile, no surrogate plies and no batch;
-     * otherwise PDN_EINVAL. */
+     * the stress of the elastic strains; one plastic state per Gauss point
+     * (one-point or full integration).  Needs G13 = G12, the 15x15 or 16x16
+     * tile, no surrogate plies and no batch; otherwise PDN_EINVAL. */
     double Sp, Kp;
 } pdn_material;
 

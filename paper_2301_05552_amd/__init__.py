@@ -237,9 +237,12 @@ def _ip(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
 
 
-def mesh_multiply(coords, hexes, cohs, ndivi: int, hex_tag=None, coh_tag=None, device=0, stream=None):
+def mesh_multiply(coords, hexes, cohs, ndivi: int, hex_tag=None, coh_tag=None, device=0, stream=None,
+                  counts=None):
     """pdn_mesh_multiply: ndivi division levels on the device.  Returns
-    (coords, hexes, cohs, hex_tag, coh_tag, counts)."""
+    (coords, hexes, cohs, hex_tag, coh_tag, counts).  `counts` (the dict a
+    previous call on the same mesh and ndivi returned) sizes the outputs and
+    saves the sizing call."""
     X = np.ascontiguousarray(coords, dtype=np.float64).reshape(-1, 3)
     H = np.ascontiguousarray(hexes, dtype=np.int32).reshape(-1, 8)
     Cc = np.ascontiguousarray(cohs, dtype=np.int32).reshape(-1, 8)
@@ -247,9 +250,13 @@ def mesh_multiply(coords, hexes, cohs, ndivi: int, hex_tag=None, coh_tag=None, d
     ct = None if coh_tag is None else np.ascontiguousarray(coh_tag, dtype=np.int32)
     cnt = MmuCounts()
     args = (device, stream, _dp(X), len(X), _ip(H), len(H), _ip(Cc), len(Cc), _ip(ht), _ip(ct), ndivi)
-    rc = lib().pdn_mesh_multiply(*args, None, None, None, None, None, 0, 0, 0, C.byref(cnt))
-    if rc != -6:
-        _gchk(rc)
+    if counts is None:
+        rc = lib().pdn_mesh_multiply(*args, None, None, None, None, None, 0, 0, 0, C.byref(cnt))
+        if rc != -6:
+            _gchk(rc)
+    else:
+        for f, _ in MmuCounts._fields_:
+            setattr(cnt, f, int(counts[f]))
     Xo = np.zeros((cnt.n_nodes, 3))
     Ho = np.zeros((cnt.n_bulk, 8), np.int32)
     Co = np.zeros((cnt.n_interface, 8), np.int32)

@@ -324,7 +324,7 @@ int prepare(pdn_ctx *c)
         if (!pdn::tile_has_full(c->tile))
             return set_err(c, PDN_EINVAL, "shear plasticity is built for the 15x15 and 16x16 tiles");
         if (!c->ep) {                 // plastic state, zero at the start (Algorithm 4)
-            const size_t bytes = 4 * (size_t)std::max<int64_t>(1, c->ne) * rsize(c);
+            const size_t bytes = 4 * (size_t)c->ngp * (size_t)std::max<int64_t>(1, c->ne) * rsize(c);
             if ((rc = dalloc(c, &c->ep, bytes))) return rc;
             HIPCHK(c, hipMemsetAsync(c->ep, 0, bytes, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -782,8 +782,6 @@ int pdn_material_set(pdn_ctx *c, int32_t ply, const pdn_material *m)
         return set_err(c, PDN_EINVAL, "shear plasticity is built for the exact damage law, not the surrogate");
     if (ply_plastic(*m) && m->G13 != m->G12)
         return set_err(c, PDN_EINVAL, "shear plasticity needs an isotropic longitudinal shear plane (G13 = G12)");
-    if (ply_plastic(*m) && c->ngp != 1)
-        return set_err(c, PDN_EINVAL, "shear plasticity is built for the one-point element");
     for (int p = 0; p < c->P; ++p)
         if (ply < 0 || p == ply) { c->mat[p] = *m; c->mat_set[p] = 1; }
     c->ready = false;
@@ -1028,7 +1026,7 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
     case PDN_ARR_GP_R: n = 4 * c->ngp * c->ne; break;
     case PDN_ARR_COH_R: n = c->npairs; break;
     case PDN_ARR_MASS: n = c->nn; break;
-    case PDN_ARR_GP_EP: n = 3 * c->ne; break;
+    case PDN_ARR_GP_EP: n = 3 * c->ngp * c->ne; break;
     default: return set_err(c, PDN_EINVAL, "unknown array kind %d", kind);
     }
     if (n_out) *n_out = n;
@@ -1056,9 +1054,10 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
             for (int64_t i = 0; i < n; ++i) out[i] = 0.0;
             return PDN_OK;
         }
-        std::vector<double> all(4 * c->ne);
+        const int64_t ng = c->ngp * c->ne;
+        std::vector<double> all(4 * ng);
         if (c->precision == PDN_MIXED) {
-            std::vector<float> tmp(4 * c->ne);
+            std::vector<float> tmp(4 * ng);
             HIPCHK(c, hipMemcpyAsync(tmp.data(), c->ep, tmp.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             for (size_t i = 0; i < tmp.size(); ++i) all[i] = tmp[i];
@@ -1066,7 +1065,7 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
             HIPCHK(c, hipMemcpyAsync(all.data(), c->ep, all.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         }
-        for (int64_t e = 0; e < c->ne; ++e)
+        for (int64_t e = 0; e < ng; ++e)
             for (int q = 0; q < 3; ++q) out[3 * e + q] = all[4 * e + q];
         return PDN_OK;
     }
@@ -1093,7 +1092,7 @@ int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
     case PDN_ARR_GP_R: need = 4 * c->ngp * c->ne; break;
     case PDN_ARR_COH_R: need = c->npairs; break;
     case PDN_ARR_GP_EP:
-        need = 3 * c->ne;
+        need = 3 * c->ngp * c->ne;
         if (!c->ep) return set_err(c, PDN_EINVAL, "no plastic state: no ply has shear plasticity (or no step yet)");
         break;
     default: return set_err(c, PDN_EINVAL, "array kind %d cannot be set", kind);
@@ -1120,15 +1119,16 @@ int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
         HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     } else if (kind == PDN_ARR_GP_EP) {
+        const int64_t ng = c->ngp * c->ne;
         if (c->precision == PDN_MIXED) {
-            std::vector<float> tmp(4 * c->ne, 0.0f);
-            for (int64_t e = 0; e < c->ne; ++e)
+            std::vector<float> tmp(4 * ng, 0.0f);
+            for (int64_t e = 0; e < ng; ++e)
                 for (int q = 0; q < 3; ++q) tmp[4 * e + q] = (float)in[3 * e + q];
             HIPCHK(c, hipMemcpyAsync(c->ep, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         } else {
-            std::vector<double> tmp(4 * c->ne, 0.0);
-            for (int64_t e = 0; e < c->ne; ++e)
+            std::vector<double> tmp(4 * ng, 0.0);
+            for (int64_t e = 0; e < ng; ++e)
                 for (int q = 0; q < 3; ++q) tmp[4 * e + q] = in[3 * e + q];
             HIPCHK(c, hipMemcpyAsync(c->ep, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1177,7 +1177,7 @@ int pdn_state_save(const pdn_ctx *cc, void *buf, int64_t cap, int64_t *n_out)
     const size_t rs = rsize(c);
     const int64_t ncand = (int64_t)(c->ci1 - c->ci0) * (c->cj1 - c->cj0);
     const int64_t hn = c->gl.step;
-    const size_t eps_bytes = c->plastic ? 4 * c->ne * rs : 0;
+    const size_t eps_bytes = c->plastic ? 4 * c->ngp * c->ne * rs : 0;
     const size_t need = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) +
                         4 * c->ngp * c->ne * rs + eps_bytes +
                         c->npairs * rs + ncand * (1 + 6 * sizeof(double)) + 3 * hn * sizeof(double);
@@ -1227,7 +1227,7 @@ int pdn_state_load(pdn_ctx *c, const void *buf, int64_t n)
     // the blob must be exactly what pdn_state_save writes for this context and
     // history length; nothing is read or changed before this holds
     const size_t rs = rsize(c);
-    const size_t eps_bytes = plas ? 4 * c->ne * rs : 0;
+    const size_t eps_bytes = plas ? 4 * c->ngp * c->ne * rs : 0;
     const size_t fixed = sizeof(BlobHeader) + sizeof(DevGlobals) + 2 * 3 * c->nn * sizeof(double) +
                          4 * c->ngp * c->ne * rs + eps_bytes + c->npairs * rs + ncand * (1 + 6 * sizeof(double));
     if (h.hist_n < 0 || (uint64_t)h.hist_n > ((uint64_t)INT64_MAX - fixed) / (3 * sizeof(double)))

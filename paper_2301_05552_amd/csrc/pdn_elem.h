@@ -277,10 +277,10 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
 // is no hourglass control.  The thresholds of point g are record e8 + g of
 // rstate, read one point ahead and written back (by the owning lane) when they
 // changed, so at most two points' states are live at a time.
-template <typename R>
+template <typename R, bool PLAS = false>
 __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
                                    R ihx, R ihy, R ihz, const PlyC<R> &P, R *rstate, int64_t e8, bool own,
-                                   Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel)
+                                   Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel, R *epstate = nullptr)
 {
     const Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
     const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
@@ -289,13 +289,21 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
     const R ax = wq * gx, ay = wq * gy, az = wq * gz;
     cx = cy = cz = Modes<R>{R(0), R(0), R(0), R(0), R(0), R(0), R(0)};
     R wsum = R(0);
-    // the next point's thresholds are loaded while this point is computed
-    R rn[4];
+    // the next point's thresholds (and plastic state) are loaded while this
+    // point is computed
+    R rn[4], epn[4];
     load_state(rstate, e8, rn);
+    if constexpr (PLAS) load_state(epstate, e8, epn);
 #pragma unroll 1
     for (int g = 0; g < 8; ++g) {
         R rg[4] = {rn[0], rn[1], rn[2], rn[3]};
         load_state(rstate, e8 + (g < 7 ? g + 1 : 7), rn);
+        R epg[4];
+        if constexpr (PLAS) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) epg[q] = epn[q];
+            load_state(epstate, e8 + (g < 7 ? g + 1 : 7), epn);
+        }
         const R xi = (g & 1) ? gp : -gp, eta = (g & 2) ? gp : -gp, zeta = (g & 4) ? gp : -gp;
         const R ez = eta * zeta, xz = xi * zeta, xe = xi * eta;
         R G[9];
@@ -308,10 +316,13 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
             G[3 * c + 2] = gz * (m.zeta + xi * m.xz + eta * m.ez + xe * m.xez);
         }
         R Pn[9];
-        bool ch = false;
+        bool ch = false, pch = false;
         int ex = 0;
-        wsum += box_point<R, false>(G, P, vol, rg, ch, Pn, nullptr, 0.f, 0.f, ex);
+        wsum += box_point<R, false, PLAS>(G, P, vol, rg, ch, Pn, nullptr, 0.f, 0.f, ex, epg, &pch);
         if (own && ch) store_state(rstate, e8 + g, rg);
+        if constexpr (PLAS) {
+            if (own && pch) store_state(epstate, e8 + g, epg);
+        }
         Modes<R> *cm[3] = {&cx, &cy, &cz};
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -650,7 +661,7 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
         const int64_t eidx = lt == 0 ? iv + (int64_t)nx * (jv + (int64_t)ny * li) : 0;
         const int64_t pidx = lt == 0 ? 0 : (nvalid ? col : 0) + plane * li;
         if constexpr (NGP == 1) load_state(A.r, eidx, rn);
-        if constexpr (PLAS) load_state(A.ep, eidx, epn);
+        if constexpr (PLAS && NGP == 1) load_state(A.ep, eidx, epn);
         rdn = A.rd[pidx];
     };
 
@@ -803,8 +814,8 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                 if constexpr (NGP == 8) {
                     // lanes without an element read a valid record (clamped) and write nothing
                     const int64_t e8 = 8 * (iv + (int64_t)nx * (jv + (int64_t)ny * lidx));
-                    hex_box_force_full<R>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.r, e8, eown, cm[0],
-                                          cm[1], cm[2], uel);
+                    hex_box_force_full<R, PLAS>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.r, e8, eown,
+                                                cm[0], cm[1], cm[2], uel, A.ep);
                     if (eown) acc[T_UEL] += (double)uel;
                 } else {
                     bool pchanged = false;
@@ -1026,9 +1037,12 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
 // alone, the network code takes 430 VGPRs and AGPRs and the whole kernel
 // runs at 1 wave per SIMD even where no point reaches the network.  The
 // spills this costs sit around the network evaluation; the plain build
-// (bound 1, the default) is unaffected.
+// (bound 1, the default) is unaffected.  The FP32 build with full
+// integration and plasticity is held to 2 waves as well: it needs one
+// register more than 256.
 template <typename R, int TX, int TY, bool SUR, int NGP = 1, bool PLAS = false>
-__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY)) __attribute__((amdgpu_waves_per_eu(SUR ? 2 : 1)))
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY))
+__attribute__((amdgpu_waves_per_eu((SUR || (PLAS && NGP == 8 && sizeof(R) == 4)) ? 2 : 1)))
 void k_elem_node(ElemArgs<R> A)
 {
     elem_node_tile<R, TX, TY, SUR, NGP, PLAS>(A, xcd_tile(blockIdx.x, gridDim.x));
@@ -1145,13 +1159,13 @@ static hipError_t launch_elem_node_plas_v(const ElemArgs<R> &a, int tile, hipStr
     }
 }
 
-// full integration: the tiles it is built for
-template <typename R>
+// full integration (PLAS: with shear plasticity): the tiles it is built for
+template <typename R, bool PLAS = false>
 static hipError_t launch_elem_node_full_v(const ElemArgs<R> &a, int tile, hipStream_t s)
 {
     switch (tile) {
-    case PDN_TILE_16x16: return launch_en<R, 16, 16, false, 8>(a, s);
-    case PDN_TILE_15x15: return launch_en<R, 15, 15, false, 8>(a, s);
+    case PDN_TILE_16x16: return launch_en<R, 16, 16, false, 8, PLAS>(a, s);
+    case PDN_TILE_15x15: return launch_en<R, 15, 15, false, 8, PLAS>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -133,7 +133,9 @@ __global__ void k_project_max(const double *in, int64_t ncol, int nlayers, doubl
 template <typename R>
 hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, int ngp, hipStream_t s)
 {
-    if (ngp == 8) return sur || a.ep ? hipErrorInvalidValue : launch_elem_node_full<R>(a, tile, s);
+    if (ngp == 8)
+        return sur ? hipErrorInvalidValue
+                   : a.ep ? launch_elem_node_full_plas<R>(a, tile, s) : launch_elem_node_full<R>(a, tile, s);
     if (a.ep) return sur ? hipErrorInvalidValue : launch_elem_node_plas<R>(a, tile, s);
     return sur ? launch_elem_node_sur<R>(a, tile, s) : launch_elem_node_v<R, false>(a, tile, s);
 }

@@ -32,6 +32,10 @@ hipError_t launch_elem_node_plas(const ElemArgs<R> &a, int tile, hipStream_t s);
 // full integration (ngp 8): built for the 15x15 and 16x16 tiles
 template <typename R>
 hipError_t launch_elem_node_full(const ElemArgs<R> &a, int tile, hipStream_t s);
+// full integration with shear plasticity (ngp 8, a.ep non-null: 4 per Gauss
+// point): the same tiles
+template <typename R>
+hipError_t launch_elem_node_full_plas(const ElemArgs<R> &a, int tile, hipStream_t s);
 template <typename R>
 hipError_t launch_elem_node_batch_full(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
                                        hipStream_t s);

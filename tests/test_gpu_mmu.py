@@ -64,6 +64,21 @@ def test_coupon_level1_from_level0_table3():
     _same(out, mmu.multiply(X, H, C, 1, hp, cp))
 
 
+def test_coupon_two_levels_at_the_benchmark_size():
+    """The benchmark's mesh multiplication: the level-0 AS4/8552 coupon
+    divided twice (14.6M elements, 15.0M nodes), in full against the host
+    refinement; a second call given the sizes of the first returns the same
+    mesh."""
+    _note("mesh multiplication: AS4/8552 coupon level 0, ndivi 2 (benchmark size)")
+    X, H, C, hp, cp = W.hex_mesh(W.coupon_as4(0)["mesh"])
+    out = pdn.mesh_multiply(X, H, C, 2, hp, cp)
+    _same(out, mmu.multiply(X, H, C, 2, hp, cp))
+    again = pdn.mesh_multiply(X, H, C, 2, hp, cp, counts=out[5])
+    for a, b in zip(out[:5], again[:5]):
+        assert np.array_equal(a, b)
+    assert again[5] == out[5]
+
+
 def test_mesh_multiply_errors_and_empty_mesh():
     _note("mesh multiplication: errors, empty mesh, ndivi 0")
     X, H, C, hp, cp = W.hex_mesh(W.tiny(2, 2, 2, 1, angles=[0, 90], cohesive=1)["mesh"])

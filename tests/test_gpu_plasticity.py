@@ -6,7 +6,8 @@ relative of the oracle over a run in which points yield, harden and then
 damage.  Mixed precision: the peak contact force within 0.5 % of the FP64
 oracle.  The plastic state is bitwise independent of the tile shape (rim
 elements are evaluated by two workgroups; the update is idempotent), runs
-repeat bit for bit, and a checkpoint carries it.
+repeat bit for bit, and a checkpoint carries it.  The same with full 2x2x2
+integration, a plastic state per Gauss point (the paper's element and law).
 """
 import copy
 import sys
@@ -109,6 +110,64 @@ def test_plastic_checkpoint_round_trip():
         s.close()
 
 
+def full_plastic_case(nx=12, ny=12, precision=W.PREC_FP64):
+    c = plastic_case(nx, ny, precision)
+    c["mesh"]["integration"] = 8
+    return c
+
+
+def test_full_integration_plastic_fp64_matches_the_oracle():
+    """The paper's element with the paper's law: 2x2x2 Gauss points, each
+    with its own thresholds and plastic state, against the oracle's fully
+    integrated element in FP64."""
+    _note("plasticity + full integration fp64 12x12x4+3 800 steps")
+    cfg = full_plastic_case()
+    o, g = run_both(cfg, 800, chunks=2)
+    d = compare(o, g, cfg)
+    for k in ("dt", "t", "force", "imp_disp", "disp", "gp_r", "coh_r", "energy"):
+        assert d[k] <= TOL64, f"{k}: {d[k]:.3e}"
+    assert d["vel"] <= 10 * TOL64
+    epo, epg = o.get(oracle.GP_EP), g.array_get(pdn.ARR_GP_EP)
+    assert epo.size == 3 * 8 * g.info()["n_bulk"] and epo.max() > 0.01
+    assert rel(epg, epo) <= TOL64
+    e = g.energies()
+    assert abs(e["residual"]) <= 1e-6 * e["ke0"]
+    assert e["w_int"] - e["u_el"] > 0
+
+
+def test_full_integration_plastic_mixed_tiles_repeat_and_checkpoint():
+    """Mixed precision: peak force within 0.5 % of the FP64 oracle; 15x15 and
+    16x16 tiles give bitwise equal states on a ragged plate; a checkpoint
+    carries the eight plastic states of every element."""
+    _note("plasticity + full integration mixed 12x12x4+3 vs oracle; 41x29 tiles; checkpoint")
+    cfg = full_plastic_case()
+    o, g = run_both(cfg, 800, precision=W.PREC_MIXED)
+    fo, fg = o.history()[1], g.contact_force()[1]
+    assert abs(fg.max() - fo.max()) <= 5e-3 * fo.max()
+    g.close()
+    big = full_plastic_case(41, 29, W.PREC_MIXED)
+    runs = []
+    for tile in ((15, 15), (16, 16)):
+        s = pdn.Simulation(big, tile=tile)
+        s.step(700)
+        runs.append([s.array_get(pdn.ARR_GP_EP), s.array_get(pdn.ARR_GP_R), s.array_get(pdn.ARR_DISP)])
+        if tile == (15, 15):
+            blob = s.state_save()
+            s.step(150)
+            after = [s.array_get(pdn.ARR_GP_EP), s.array_get(pdn.ARR_DISP)]
+        s.close()
+    assert runs[0][0].max() > 0
+    for a, b in zip(runs[0], runs[1]):
+        assert np.array_equal(a, b)
+    t = pdn.Simulation(big)
+    t.step(1)
+    t.state_load(blob)
+    t.step(150)
+    assert np.array_equal(t.array_get(pdn.ARR_GP_EP), after[0])
+    assert np.array_equal(t.array_get(pdn.ARR_DISP), after[1])
+    t.close()
+
+
 def test_plastic_combinations_not_built_are_rejected():
     _note("plasticity: rejected combinations")
     cfg = plastic_case(precision=W.PREC_MIXED)
@@ -129,10 +188,9 @@ def test_plastic_combinations_not_built_are_rejected():
     with pytest.raises(pdn.PdnError) as e:
         pdn.Batch([s, s2])
     assert e.value.code == EINVAL
-    full = copy.deepcopy(cfg)
-    full["mesh"]["integration"] = 8
+    full = pdn.Simulation(full_plastic_case(precision=W.PREC_MIXED))
     with pytest.raises(pdn.PdnError) as e:
-        pdn.Simulation(full)
+        full.set_tile(32, 8)
     assert e.value.code == EINVAL
-    for x in (s, t, s2):
+    for x in (s, t, s2, full):
         x.close()

@@ -858,13 +858,16 @@ def test_plasticity_off_is_the_elastic_damage_law():
             assert np.array_equal(a[0], c[0]) and (c[2] == 0).all()
 
 
-def test_plastic_plate_energy_identity():
-    """A small laminate struck hard enough to yield in shear: the energy
-    identity closes to 1e-6 of the impact energy, the plastic strains are
-    non-zero, and the dissipated work W_int - U_el (U_el: energy of the elastic
-    strains) is non-negative and grows."""
+@pytest.mark.parametrize("integration", [1, 8])
+def test_plastic_plate_energy_identity(integration):
+    """A small laminate struck hard enough to yield in shear, with one-point
+    or fully integrated elements: the energy identity closes to 1e-6 of the
+    impact energy, the plastic strains are non-zero, and the dissipated work
+    W_int - U_el (U_el: energy of the elastic strains) is non-negative and
+    grows."""
     cfg = W.tiny(8, 8, 4, 1, angles=[0, 45, -45, 90], law=W.LAW_CDM, lx=8e-3, ly=8e-3,
                  ply_thickness=0.25e-3, v0=12.0, mass=0.05, R=3e-3, plastic=True)
+    cfg["mesh"]["integration"] = integration
     o = oracle.Oracle(cfg)
     dis = []
     for _ in range(6):
@@ -876,6 +879,50 @@ def test_plastic_plate_energy_identity():
     assert ep[:, 2].max() > 0
     assert min(dis) >= -1e-9 * o.energies()["ke0"]
     assert dis[-1] > dis[0]
+
+
+@pytest.mark.parametrize("angle", [0.0, 30.0])
+def test_plastic_state_of_every_gauss_point_under_homogeneous_shear(angle):
+    """A free one-ply plate given the displacement of a uniform in-plane
+    simple shear beyond yield, u_x = gamma y, and its forces evaluated once
+    at that configuration (a zero-step call re-initialises the level): every
+    element, with one point or with 2x2x2 Gauss points, sees the same Green
+    strain E = (G + G^T + G^T G)/2, so the plastic state of every point is
+    the return map of that strain in the ply frame (the law called alone,
+    from zero).  Pins where the plate keeps the state of each point.  (A
+    step after it would move the free edges, whose tractions are not
+    balanced, and the edge elements would flow further.)"""
+    gam = 0.03
+    th = math.radians(angle)
+    c, s_ = math.cos(th), math.sin(th)
+    E00, E01, E11 = 0.0, 0.5 * gam, 0.5 * gam * gam
+    e = np.zeros(6)
+    e[0] = c * c * E00 + 2 * c * s_ * E01 + s_ * s_ * E11
+    e[1] = s_ * s_ * E00 - 2 * c * s_ * E01 + c * c * E11
+    e[5] = 2 * (-c * s_ * E00 + (c * c - s_ * s_) * E01 + c * s_ * E11)
+    states = {}
+    for ngp in (1, 8):
+        cfg = W.tiny(3, 3, 1, 1, angles=[angle], law=W.LAW_CDM, ply_thickness=0.5e-3, bc=W.BC_FREE,
+                     v0=0.0, gravity=0.0, plastic=True)
+        cfg["impactor"]["gap"] = 1.0
+        cfg["mesh"]["integration"] = ngp
+        m = cfg["mesh"]
+        o = oracle.Oracle(cfg)
+        o.step(1)
+        nn = o.nn
+        k = np.arange(nn)
+        j = (k // (m["nx"] + 1)) % (m["ny"] + 1)
+        d = np.zeros((nn, 3))
+        d[:, 0] = gam * m["ly"] * j / m["ny"]
+        o.set(oracle.DISP, d.reshape(-1))
+        o.step(0)
+        states[ngp] = o.get(oracle.GP_EP).reshape(-1, 3)
+        assert len(states[ngp]) == ngp * o.ne
+    mat = W.tiny(1, 1, 1, 1, law=W.LAW_CDM, plastic=True)["materials"][0]
+    _, _, ep, _ = oracle.cdm_plastic(mat, 1e-3, e, np.ones(4), np.zeros(3))
+    assert ep[2] > 1e-3                                     # the strain is beyond yield
+    for ngp, st in states.items():
+        assert np.abs(st - ep).max() <= 1e-9 * ep[2], ngp
 
 
 def test_plasticity_needs_an_isotropic_shear_plane():
