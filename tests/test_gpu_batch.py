@@ -77,6 +77,28 @@ def test_batch_matches_single_bitwise(prec):
     batch.close()
 
 
+def test_64_case_batch_matches_solo_runs_bitwise():
+    """The benchmark's batch (64 seeded plates of 20k-400k elements, 4-16
+    plies, mixed precision) stepped 403 times in one launch per kernel and
+    step: every case equals the same case stepped alone on the batch's tile,
+    bit for bit (states, histories, energy books)."""
+    _note("64-case batch (13.6M GPs) vs 64 solo runs, 403 steps")
+    cfgs = W.batch_cases_64()
+    sims = [pdn.Simulation(c) for c in cfgs]
+    batch = pdn.Batch(sims)
+    tile = batch.info()["tile"]
+    batch.step(403)
+    assert sum(s.info()["active"] > 0 for s in sims) > 0
+    for k, c in enumerate(cfgs):
+        r = pdn.Simulation(c, tile=tile)
+        r.step(403)
+        _same(sims[k], r, f"case {k}")
+        r.close()
+    batch.close()
+    for s in sims:
+        s.close()
+
+
 def test_batched_case_matches_oracle_fp64():
     _note("batched case vs oracle")
     cfgs = _cases(W.PREC_FP64)

@@ -881,6 +881,32 @@ def test_plastic_plate_energy_identity(integration):
     assert dis[-1] > dis[0]
 
 
+def test_velocity_carries_several_times_the_relative_difference_of_displacement():
+    """Why the FP64 parity tests hold the velocity to ten times the
+    displacement's bar: the velocity is a one-step difference quotient of
+    displacements, so the same perturbation shows up several times larger
+    in it, relative to its size.  Two oracle runs of the damaged 12 x 12 x 4
+    parity plate whose striker speeds differ by 1e-14 (relative), 300 and
+    400 steps."""
+    cfg = W.tiny(12, 12, 4, 1, angles=[0, 90, 0, 90], law=W.LAW_CDM, lx=12e-3, ly=12e-3,
+                 ply_thickness=0.5e-3, v0=20.0, mass=0.02, R=4e-3)
+    a = oracle.Oracle(cfg)
+    c2 = W.tiny(12, 12, 4, 1, angles=[0, 90, 0, 90], law=W.LAW_CDM, lx=12e-3, ly=12e-3,
+                ply_thickness=0.5e-3, v0=20.0 * (1 + 1e-14), mass=0.02, R=4e-3)
+    b = oracle.Oracle(c2)
+    ratios = []
+    for n in (300, 100):
+        a.step(n)
+        b.step(n)
+        da, db = a.get(oracle.DISP), b.get(oracle.DISP)
+        va, vb = a.get(oracle.VEL), b.get(oracle.VEL)
+        rd = np.abs(db - da).max() / np.abs(da).max()
+        rv = np.abs(vb - va).max() / np.abs(va).max()
+        assert rd > 0
+        ratios.append(rv / rd)
+    assert min(ratios) >= 3.0, ratios
+
+
 @pytest.mark.parametrize("angle", [0.0, 30.0])
 def test_plastic_state_of_every_gauss_point_under_homogeneous_shear(angle):
     """A free one-ply plate given the displacement of a uniform in-plane
