@@ -619,43 +619,83 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
                                "peak_force_N": fpk, "plain_peak_force_N": f_plain}
     out["gains"] = surrogate_gains(stream, tile, nets, pre, max(5, steps // 2))
     gold = os.path.join(ROOT, "tests", "golden", "qi8_300x200x8_fp64_oracle.json")
-    if gate_steps and os.path.exists(gold):
-        with open(gold) as fh:
-            g = json.load(fh)
-        c2 = W.plate_qi8_300x200x8(1)
-        nets2, _ = _train_networks(c2, train_steps)
-        n = min(gate_steps, g["steps"])
-        gate = {"workload": "300x200x8 [0/45/-45/90]s plate, 15 J, to %.2f ms" % (n * g["dt"] * 1e3),
-                "oracle_peak_force_N": g["peak_force_N"] if n == g["steps"] else None}
-        for name, nn, res in (("plain_mixed", None, 0), ("surrogate_res_0.001", nets2, 1e-3),
-                              ("surrogate_res_0.03", nets2, 3e-2)):
-            ar = {}
-            ms, info, fpk = _run(c2, stream, (15, 15), nn, res, 0, 0, n, areas=ar)
-            e = {"peak_force_N": fpk, "ms_per_step": ms}
-            if gate["oracle_peak_force_N"]:
-                # deterministic window (before contact-node releases make correct
-                # runs drift apart): the 0.5 % peak-force bar applies here
-                ev = g["history_every"]
-                fo = np.asarray(g["history"]["force"])[:5800 // ev]
-                fr = ar["force"][ev - 1::ev][:5800 // ev]
-                e["peak_force_rel_err_first_5800_steps"] = abs(fr.max() - fo.max()) / fo.max()
-                xo = np.asarray(g["history"]["imp_disp"])
-                xr = ar["disp"][ev - 1::ev][:len(xo)]            # same sampling as the stored run
-                e["max_striker_disp_rel_err"] = abs(xr.max() - xo.max()) / xo.max()
-                # whole run: chaotic at the few-per-cent level (FP64 runs with the
-                # impact energy perturbed by 1e-12 spread +-2.5 % / +-3.4 %)
-                e["peak_force_rel_err"] = abs(fpk - g["peak_force_N"]) / g["peak_force_N"]
-                e["damage_area_rel_err"] = {
-                    f"{k}_{thr}": abs(ar[k][thr] - g["projected_damage"][k][thr]["area_m2"]) /
-                    g["projected_damage"][k][thr]["area_m2"]
-                    for k in ("fibre", "matrix") for thr in ("0", "0.5", "0.999")
-                    if g["projected_damage"][k][thr]["area_m2"] > 0}
-            if nn is not None:
-                e["network_consulted_fraction"] = _consulted(info)
-                e["fallback_fraction"] = info["fallback_fraction"]
-            gate[name] = e
-        out["accuracy_gate"] = gate
+    if gate_steps >= 0 and os.path.exists(gold):
+        out["accuracy_gate"] = accuracy_gate(stream, train_steps, gate_steps, gold)
     return out
+
+
+def _trailing_mean(f, n):
+    """Trailing moving average of a force history over n steps (shorter at
+    the start): the per-step contact force of the kinematic contact is
+    spiky, its raw maximum a property of that noise."""
+    c = np.concatenate([[0.0], np.cumsum(f)])
+    k = np.arange(1, len(f) + 1)
+    lo = np.maximum(k - n, 0)
+    return (c[k] - c[lo]) / (k - lo)
+
+
+def accuracy_gate(stream, train_steps, gate_steps, gold) -> dict:
+    """The reduced-precision gate on the 300 x 200 x 8 plate through the whole
+    loading (past the force peak and the striker's largest displacement),
+    against the stored FP64 oracle run and, where it is stored, the oracle's
+    run with its nodal sums in the opposite order (the impact's own
+    amplification of rounding): plain mixed precision and the surrogate at
+    two residual bars.  Errors are reported plainly, with whether the
+    0.5 % peak-force and 2 % damaged-area bars are met."""
+    import workloads as W
+    with open(gold) as fh:
+        g = json.load(fh)
+    rev_path = gold.replace(".json", "_reversed.json")
+    rev = None
+    if os.path.exists(rev_path):
+        with open(rev_path) as fh:
+            rev = json.load(fh)
+    c2 = W.plate_qi8_300x200x8(1)
+    nets2, _ = _train_networks(c2, train_steps)
+    n = g["steps"] if gate_steps == 0 else min(gate_steps, g["steps"])
+    whole = n == g["steps"]
+    filt = g.get("filter_steps", 250)
+    keys = [("matrix", thr) for thr in ("0", "0.5", "0.999")] + [("fibre", thr) for thr in ("0", "0.5", "0.999")]
+    keys = [k for k in keys if g["projected_damage"][k[0]][k[1]]["area_m2"] > 0]
+    gate = {"workload": "300x200x8 [0/45/-45/90]s plate, 15 J, to %.2f ms" % (n * g["dt"] * 1e3),
+            "filter_steps": filt}
+    if whole:
+        gate["oracle"] = {"peak_force_filtered_N": g["peak_force_filtered_N"],
+                          "t_peak_filtered_s": g["t_peak_filtered_s"], "max_imp_disp_m": g["max_imp_disp_m"],
+                          "damage_area_m2": {f"{k}_{t}": g["projected_damage"][k][t]["area_m2"] for k, t in keys}}
+        if rev is not None:
+            gate["oracle_reversed_order_rel_diff"] = {
+                "peak_force_filtered": abs(rev["peak_force_filtered_N"] - g["peak_force_filtered_N"])
+                / g["peak_force_filtered_N"],
+                "max_imp_disp": abs(rev["max_imp_disp_m"] - g["max_imp_disp_m"]) / g["max_imp_disp_m"],
+                "damage_area": {f"{k}_{t}": abs(rev["projected_damage"][k][t]["area_m2"]
+                                                - g["projected_damage"][k][t]["area_m2"])
+                                / g["projected_damage"][k][t]["area_m2"] for k, t in keys}}
+    ev = g["history_every"]
+    for name, nn, res in (("plain_mixed", None, 0), ("surrogate_res_0.001", nets2, 1e-3),
+                          ("surrogate_res_0.03", nets2, 3e-2)):
+        ar = {}
+        ms, info, fpk = _run(c2, stream, (15, 15), nn, res, 0, 0, n, areas=ar)
+        e = {"ms_per_step": ms}
+        # deterministic window (before contact-node releases make correct runs
+        # drift apart): the 0.5 % peak-force bar applied where runs agree
+        fo = np.asarray(g["history"]["force"])[:5800 // ev]
+        fr = ar["force"][ev - 1::ev][:5800 // ev]
+        e["peak_force_rel_err_first_5800_steps"] = abs(fr.max() - fo.max()) / fo.max()
+        if whole:
+            ff = _trailing_mean(ar["force"], filt)
+            e["peak_force_filtered_N"] = float(ff.max())
+            e["peak_force_filtered_rel_err"] = abs(ff.max() - g["peak_force_filtered_N"]) / g["peak_force_filtered_N"]
+            e["max_striker_disp_rel_err"] = abs(ar["disp"].max() - g["max_imp_disp_m"]) / g["max_imp_disp_m"]
+            e["damage_area_rel_err"] = {f"{k}_{t}": abs(ar[k][t] - g["projected_damage"][k][t]["area_m2"])
+                                        / g["projected_damage"][k][t]["area_m2"] for k, t in keys}
+            e["meets_0.5pct_force_2pct_area"] = bool(e["peak_force_filtered_rel_err"] <= 5e-3 and
+                                                     max(e["damage_area_rel_err"].values()) <= 2e-2)
+        if nn is not None:
+            e["network_consulted_fraction"] = _consulted(info)
+            e["fallback_fraction"] = info["fallback_fraction"]
+        gate[name] = e
+    return gate
 
 
 def main():
@@ -677,8 +717,9 @@ def main():
                     help="refinement levels of the AS4/8552 coupon run to 5 ms ('' = skip, '0,1' = both)")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg")
     ap.add_argument("--sur-train-steps", type=int, default=16000)
-    ap.add_argument("--gate-steps", type=int, default=61000,
-                    help="steps of the 300x200x8 accuracy gate (0 = skip)")
+    ap.add_argument("--gate-steps", type=int, default=0,
+                    help="steps of the 300x200x8 accuracy gate (0 = all the stored oracle run's steps, "
+                         "-1 = skip)")
     ap.add_argument("--cpu-steps", type=int, default=300, help="most oracle steps per CPU-baseline timing")
     ap.add_argument("--no-damaged", action="store_true", help="skip the late and softened windows")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-mode leg")

@@ -250,6 +250,16 @@ PlyC<R> make_ply(const pdn_material &m, double ang_deg, int net = -1, double lc_
 
 bool ply_plastic(const pdn_material &m) { return m.law == PDN_LAW_CDM && m.Sp > 0; }
 
+// device record of Gauss point k = ngp e + g (the order of the exposed
+// arrays): record e with one point; with eight, a layer's records point by
+// point (point g of every element of the layer, then point g + 1)
+int64_t gp_record(const pdn_ctx *c, int64_t k)
+{
+    if (c->ngp == 1) return k;
+    const int64_t pl = (int64_t)c->nx * c->ny, e = k / 8, g = k % 8;
+    return 8 * pl * (e / pl) + g * pl + e % pl;
+}
+
 bool all_set(const pdn_ctx *c)
 {
     for (int p = 0; p < c->P; ++p)
@@ -1049,8 +1059,10 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return PDN_OK;
     }
-    if (kind == PDN_ARR_GP_EP) {     // 4 per GP on the device, 3 per GP out
-        if (!c->ep) {
+    if (kind == PDN_ARR_GP_R || kind == PDN_ARR_GP_EP) {   // 4 words per GP record on the device
+        const void *src = kind == PDN_ARR_GP_R ? c->r : c->ep;
+        const int w = kind == PDN_ARR_GP_R ? 4 : 3;           // values per GP out
+        if (!src) {
             for (int64_t i = 0; i < n; ++i) out[i] = 0.0;
             return PDN_OK;
         }
@@ -1058,18 +1070,20 @@ int pdn_array_get(const pdn_ctx *cc, int32_t kind, double *out, int64_t cap, int
         std::vector<double> all(4 * ng);
         if (c->precision == PDN_MIXED) {
             std::vector<float> tmp(4 * ng);
-            HIPCHK(c, hipMemcpyAsync(tmp.data(), c->ep, tmp.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(tmp.data(), src, tmp.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
             for (size_t i = 0; i < tmp.size(); ++i) all[i] = tmp[i];
         } else {
-            HIPCHK(c, hipMemcpyAsync(all.data(), c->ep, all.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipMemcpyAsync(all.data(), src, all.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         }
-        for (int64_t e = 0; e < ng; ++e)
-            for (int q = 0; q < 3; ++q) out[3 * e + q] = all[4 * e + q];
+        for (int64_t k = 0; k < ng; ++k) {
+            const int64_t rec = gp_record(c, k);
+            for (int q = 0; q < w; ++q) out[w * k + q] = all[4 * rec + q];
+        }
         return PDN_OK;
     }
-    const void *src = kind == PDN_ARR_GP_R ? c->r : c->rd;
+    const void *src = c->rd;
     if (c->precision == PDN_MIXED) {
         std::vector<float> tmp(n);
         HIPCHK(c, hipMemcpyAsync(tmp.data(), src, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
@@ -1118,29 +1132,30 @@ int pdn_array_set(pdn_ctx *c, int32_t kind, const double *in, int64_t n)
         double *dst = kind == PDN_ARR_DISP ? c->d[c->cur] : c->v[c->cur];
         HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(double), hipMemcpyHostToDevice, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
-    } else if (kind == PDN_ARR_GP_EP) {
+    } else if (kind == PDN_ARR_GP_R || kind == PDN_ARR_GP_EP) {
+        void *dst = kind == PDN_ARR_GP_R ? c->r : c->ep;
+        const int w = kind == PDN_ARR_GP_R ? 4 : 3;           // values per GP in
         const int64_t ng = c->ngp * c->ne;
+        std::vector<double> all(4 * ng, 0.0);
+        for (int64_t k = 0; k < ng; ++k) {
+            const int64_t rec = gp_record(c, k);
+            for (int q = 0; q < w; ++q) all[4 * rec + q] = in[w * k + q];
+        }
         if (c->precision == PDN_MIXED) {
-            std::vector<float> tmp(4 * ng, 0.0f);
-            for (int64_t e = 0; e < ng; ++e)
-                for (int q = 0; q < 3; ++q) tmp[4 * e + q] = (float)in[3 * e + q];
-            HIPCHK(c, hipMemcpyAsync(c->ep, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            std::vector<float> tmp(all.begin(), all.end());
+            HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         } else {
-            std::vector<double> tmp(4 * ng, 0.0);
-            for (int64_t e = 0; e < ng; ++e)
-                for (int q = 0; q < 3; ++q) tmp[4 * e + q] = in[3 * e + q];
-            HIPCHK(c, hipMemcpyAsync(c->ep, tmp.data(), tmp.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(dst, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         }
     } else {
-        void *dst = kind == PDN_ARR_GP_R ? c->r : c->rd;
         if (c->precision == PDN_MIXED) {
             std::vector<float> tmp(in, in + n);
-            HIPCHK(c, hipMemcpyAsync(dst, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->rd, tmp.data(), n * sizeof(float), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         } else {
-            HIPCHK(c, hipMemcpyAsync(dst, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(c->rd, in, n * sizeof(double), hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
         }
     }

@@ -274,13 +274,15 @@ __device__ void hex_box_force(const R ux[8], const R uy[8], const R uz[8], R hx,
 //   du/dx = (s.xi + eta s.xe + zeta s.xz + eta zeta s.xez) / (4 hx);
 // each point calls the law with its own thresholds r[g], and its virtual work
 // (weight det J = V/8) lands on all seven corner-basis coefficients.  There
-// is no hourglass control.  The thresholds of point g are record e8 + g of
-// rstate, read one point ahead and written back (by the owning lane) when they
-// changed, so at most two points' states are live at a time.
+// is no hourglass control.  The thresholds of point g are record e8 + g gs of
+// rstate (with plasticity, also its plastic state in epstate), read one point
+// ahead and written back (by the owning lane) when they changed, so at most
+// two points' states are live at a time.
 template <typename R, bool PLAS = false>
 __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], R hx, R hy, R hz,
-                                   R ihx, R ihy, R ihz, const PlyC<R> &P, R *rstate, int64_t e8, bool own,
-                                   Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel, R *epstate = nullptr)
+                                   R ihx, R ihy, R ihz, const PlyC<R> &P, R *rstate, int64_t e8, int64_t gs,
+                                   bool own, Modes<R> &cx, Modes<R> &cy, Modes<R> &cz, R &uel,
+                                   R *epstate = nullptr)
 {
     const Modes<R> sx = fwd8(ux), sy = fwd8(uy), sz = fwd8(uz);
     const R gx = R(0.25) * ihx, gy = R(0.25) * ihy, gz = R(0.25) * ihz;
@@ -297,12 +299,13 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
 #pragma unroll 1
     for (int g = 0; g < 8; ++g) {
         R rg[4] = {rn[0], rn[1], rn[2], rn[3]};
-        load_state(rstate, e8 + (g < 7 ? g + 1 : 7), rn);
+        const int64_t nxt = e8 + (g < 7 ? g + 1 : 7) * gs;
+        load_state(rstate, nxt, rn);
         R epg[4];
         if constexpr (PLAS) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) epg[q] = epn[q];
-            load_state(epstate, e8 + (g < 7 ? g + 1 : 7), epn);
+            load_state(epstate, nxt, epn);
         }
         const R xi = (g & 1) ? gp : -gp, eta = (g & 2) ? gp : -gp, zeta = (g & 4) ? gp : -gp;
         const R ez = eta * zeta, xz = xi * zeta, xe = xi * eta;
@@ -319,9 +322,9 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
         bool ch = false, pch = false;
         int ex = 0;
         wsum += box_point<R, false, PLAS>(G, P, vol, rg, ch, Pn, nullptr, 0.f, 0.f, ex, epg, &pch);
-        if (own && ch) store_state(rstate, e8 + g, rg);
+        if (own && ch) store_state(rstate, e8 + g * gs, rg);
         if constexpr (PLAS) {
-            if (own && pch) store_state(epstate, e8 + g, epg);
+            if (own && pch) store_state(epstate, e8 + g * gs, epg);
         }
         Modes<R> *cm[3] = {&cx, &cy, &cz};
 #pragma unroll
@@ -813,9 +816,12 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                 Modes<R> cm[3];
                 if constexpr (NGP == 8) {
                     // lanes without an element read a valid record (clamped) and write nothing
-                    const int64_t e8 = 8 * (iv + (int64_t)nx * (jv + (int64_t)ny * lidx));
-                    hex_box_force_full<R, PLAS>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.r, e8, eown,
-                                                cm[0], cm[1], cm[2], uel, A.ep);
+                    // a layer's records point by point: point g of every element of the
+                    // layer, then point g + 1 (a wave's record loads are contiguous)
+                    const int64_t gs = (int64_t)nx * ny;
+                    const int64_t e8 = 8 * gs * lidx + iv + (int64_t)nx * jv;
+                    hex_box_force_full<R, PLAS>(ux, uy, uz, ehx, ehy, lhz, eihx, eihy, lihz, P, A.r, e8, gs,
+                                                eown, cm[0], cm[1], cm[2], uel, A.ep);
                     if (eown) acc[T_UEL] += (double)uel;
                 } else {
                     bool pchanged = false;

@@ -73,7 +73,9 @@ __global__ void k_damage_bulk(const R *r, int ngp, const LayerInfo *layers, cons
         // the largest over the element's Gauss points
         for (int g = 0; g < ngp && P.law != 0; ++g) {
             const R lc = cbrt(hx[ie] * hy[je] * (R)L.hz);
-            const R *q = r + 4 * (ngp * e + g);
+            // one point: record e; eight: a layer's records point by point
+            const int64_t rec = ngp == 1 ? e : 8 * (int64_t)nx * ny * lb + (int64_t)g * nx * ny + ie + (int64_t)nx * je;
+            const R *q = r + 4 * rec;
             double vg;
             if (kind == 0) {
                 R a = damage_bilinear(q[0], P.XT, P.E1, P.GXT, P.fXT, P.fGT, lc);
