@@ -594,7 +594,8 @@ def surrogate_leg(stream, tile, pre, warmup, steps, plain_ms, train_steps, gate_
     by the trained network (exact law as fallback), at the stated residual bar
     1e-3 and at a looser 3e-2; speed against the plain path on this GPU, and
     the peak-force and damage-area errors against the FP64 oracle on the
-    300 x 200 x 8 plate run to 3 ms (when its stored oracle run is present)."""
+    300 x 200 x 8 plate run through its whole loading (when its stored
+    oracle run is present)."""
     import workloads as W
     cfg = W.plate_qi8_1200x800x16(1)
     t0 = time.perf_counter()
