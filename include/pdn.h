@@ -202,7 +202,10 @@ int pdn_array_set(pdn_ctx *ctx, int32_t kind, const double *in, int64_t n);
 /* Checkpoint: opaque blob of every device array, striker, books and history. */
 int pdn_state_save(const pdn_ctx *ctx, void *buf, int64_t cap, int64_t *n_out);
 int pdn_state_load(pdn_ctx *ctx, const void *buf, int64_t n);
-/* Element-tile shape of the element/node kernel (autotuner hook): 0 = default. */
+/* Element-tile shape of the element/node kernel (autotuner hook): 0, 0 = the
+ * default, 15 x 15 element columns.  Others: 16x16, 32x8, 8x8, 31x15 (full
+ * integration and shear plasticity: 15x15 and 16x16 only).  PDN_EINVAL for
+ * other shapes or one whose workgroup does not fit the device's LDS. */
 int pdn_set_tile(pdn_ctx *ctx, int32_t tile_x, int32_t tile_y);
 /* Mean device time per step of the element/node kernel (with the contact
  * step on the top plane) and of the one-workgroup books kernel that closes
