@@ -562,7 +562,7 @@ def surrogate_gains(stream, tile, nets, pre, steps) -> dict:
             if res is not None:
                 for p, w in enumerate(nets):
                     sim.surrogate_set(p, w, 0.05, res)
-                sim.surrogate_kernel(1)
+                sim.surrogate_kernel(0)          # per-call choice: the 1-wave network build here
             sim.step(1)                                  # restart pass from the set state
             c0 = sim.info()["sur_consulted"]
             f0 = sim.info()["fallback_fraction"] * c0

@@ -300,14 +300,19 @@ int pdn_surrogate_train(const pdn_sur_train *opt, const pdn_material *m, double 
 int pdn_surrogate_set(pdn_ctx *ctx, int32_t ply, const float *weights, int64_t n, double dmg_thresh,
                       double res_thresh);
 /* Which kernel build steps a context with surrogate plies.  mode 0 (the
- * default) chooses per pdn_step call: the build that evaluates the network
- * when the previous call met points that the law's screen did not pass (or
- * right after pdn_surrogate_set), otherwise the plain build, which steps the
- * surrogate plies by the exact law (so a call that met no such point costs
- * what the plain path costs) and still counts the points the screen does not
- * pass.  The first call after such points appear is then stepped by the
- * exact law; results can differ with how steps are split into calls.  mode 1
- * always uses the network build.  PDN_EINVAL for other modes. */
+ * default) chooses per pdn_step call from the previous call: when it met no
+ * point that the law's screen did not pass, the plain build, which steps the
+ * surrogate plies by the exact law (so such a call costs what the plain path
+ * costs) and still counts the points the screen does not pass; when it met
+ * some, the build that evaluates the network, at 2 waves per SIMD while they
+ * are under a tenth of its GP updates, else at 1 wave per SIMD (no register
+ * spills around the network; on 15x15 tiles, others take the 2-wave
+ * build); right after pdn_surrogate_set, the 2-wave network build.  The
+ * first call after such points appear is stepped by the exact law; results
+ * can differ with how steps are split into calls.  mode 1 always uses the
+ * 2-wave network build, mode 2 the 1-wave one (both network builds compute
+ * the same bits).
+ * PDN_EINVAL for other modes. */
 int pdn_surrogate_kernel(pdn_ctx *ctx, int32_t mode);
 /* Forward pass on n points: x is n x 10 inputs, y receives n x 10 outputs. */
 int pdn_surrogate_eval(int32_t device, void *stream, const float *weights, const float *x, int64_t n, float *y);

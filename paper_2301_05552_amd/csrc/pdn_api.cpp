@@ -28,6 +28,12 @@ struct Buf {
 
 }  // namespace
 
+// Share of a call's GP updates outside the law's screen above which the
+// surrogate network runs in its 1-wave-per-SIMD build.  On the 1200x800x16
+// plate a step took about 0.74 + 5.1 f ms with the 2-wave build and
+// 0.99 + 3.4 f ms with the 1-wave build, f the share (equal at f = 0.14).
+constexpr double SUR_WIDE_SHARE = 0.1;
+
 struct pdn_ctx {
     std::string err;
     int device = 0;
@@ -86,14 +92,18 @@ struct pdn_ctx {
     int ngp = 1;                      // Gauss points of a bulk element: 1 (hourglass control) or 8
     std::vector<int> ply_net;
     double sur_dmg = 0.05, sur_res = 1e-3;
-    // which build steps the surrogate plies in a pdn_step call: mode 0 picks
-    // per call (the network build when the previous call had points that the
-    // screen did not pass, or right after a network was set; else the plain
-    // build, which steps those plies by the exact law and counts such points);
-    // mode 1 always the network build
+    // which build steps the surrogate plies in a pdn_step call (0 plain, 1
+    // network at 2 waves/SIMD, 2 network at 1 wave/SIMD): mode 0 picks per
+    // call from the share of GP updates of the previous call that the screen
+    // did not pass (none: the plain build, which steps those plies by the
+    // exact law and counts such points; under SUR_WIDE_SHARE: build 1; else
+    // build 2; right after a network was set: build 1); modes 1 and 2 pin
+    // that build
     int sur_mode = 0;
-    bool sur_net_now = true, sur_fresh = true;
+    int sur_build = 1;
+    bool sur_fresh = true;
     double sur_gp_mark = 0.0;
+    int64_t sur_prev_n = 0;
     int64_t sur_net_steps = 0;
     // timing
     bool timing = false;
@@ -449,7 +459,7 @@ ElemArgs<R> elem_args(pdn_ctx *c, int in, int out, int contact)
     a.mlp = c->sur_d;
     a.sur_dmg = (float)c->sur_dmg;
     a.sur_res = (float)c->sur_res;
-    a.count_sur = c->use_sur && !c->sur_net_now ? 1 : 0;
+    a.count_sur = c->use_sur && c->sur_build == 0 ? 1 : 0;
     return a;
 }
 
@@ -469,7 +479,7 @@ int launch_en(pdn_ctx *c, int in, int out, int contact, hipEvent_t mid = nullptr
 {
     hipError_t e;
     const bool mx = c->precision == PDN_MIXED;
-    const bool net = c->use_sur && c->sur_net_now;
+    const int net = c->use_sur ? c->sur_build : 0;
     if (mx)
         e = pdn::launch_elem_node<float>(elem_args<float>(c, in, out, contact), c->tile, net, c->ngp, c->stream);
     else
@@ -867,13 +877,22 @@ int pdn_step(pdn_ctx *c, int64_t n)
         c->loaded_state = false;
     }
     if ((rc = ensure_history(c, c->gl.step + n))) return rc;
-    if (c->use_sur) {
-        // build for this call: the network build if the previous call met points
-        // that the screen did not pass (or a network was just set), else the plain one
-        c->sur_net_now = c->sur_mode == 1 || c->sur_fresh || c->gl.sur_gp > c->sur_gp_mark;
+    if (c->use_sur && n > 0) {
+        // build for this call, from the previous call's share of GP updates
+        // outside the screen (network build 2 pays at high shares, 1 at low)
+        const double outside = c->gl.sur_gp + c->gl.sur_unscreened;
+        if (c->sur_mode != 0) {
+            c->sur_build = c->sur_mode;
+        } else if (c->sur_fresh || c->sur_prev_n <= 0) {
+            c->sur_build = 1;
+        } else {
+            const double share = (outside - c->sur_gp_mark) / ((double)c->sur_prev_n * c->ngp * c->ne);
+            c->sur_build = share <= 0.0 ? 0 : share < SUR_WIDE_SHARE ? 1 : 2;
+        }
         c->sur_fresh = false;
-        c->sur_gp_mark = c->gl.sur_gp;
-        if (c->sur_net_now) c->sur_net_steps += n;
+        c->sur_gp_mark = outside;
+        c->sur_prev_n = n;
+        if (c->sur_build != 0) c->sur_net_steps += n;
     }
     std::vector<hipEvent_t> ev;
     if (c->timing && n > 0) {
@@ -2142,7 +2161,7 @@ int pdn_surrogate_train(const pdn_sur_train *o, const pdn_material *m, double cr
 int pdn_surrogate_kernel(pdn_ctx *c, int32_t mode)
 {
     if (!c) return PDN_EINVAL;
-    if (mode != 0 && mode != 1) return set_err(c, PDN_EINVAL, "surrogate kernel mode must be 0 or 1");
+    if (mode < 0 || mode > 2) return set_err(c, PDN_EINVAL, "surrogate kernel mode must be 0, 1 or 2");
     c->sur_mode = mode;
     return PDN_OK;
 }

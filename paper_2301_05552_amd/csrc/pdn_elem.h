@@ -525,8 +525,15 @@ __device__ void contact_books(const ElemArgs<R> &A, double *sh)
     G.e_ws = G.ws_acc;
     G.e_wgs = G.wgs_acc;
     G.e_level = (double)G.step;
-    G.fallback_gp += P[T_AUX];
-    G.sur_gp += P[T_SURN];
+    // the element terms are those of the previous pass: its build decides
+    // whether its points consulted the network
+    if (G.plain_prev) {
+        G.sur_unscreened += P[T_SURN];      // the plain build: no point consulted the network
+    } else {
+        G.fallback_gp += P[T_AUX];
+        G.sur_gp += P[T_SURN];
+    }
+    G.plain_prev = A.count_sur;
     // a non-finite displacement or velocity propagates into these sums
     if (!(isfinite(P[T_KE]) && isfinite(P[T_WA]) && isfinite(P[T_WB]) && isfinite(P[T_MZ])))
         G.flag_unstable = 1;
@@ -1054,6 +1061,16 @@ void k_elem_node(ElemArgs<R> A)
     elem_node_tile<R, TX, TY, SUR, NGP, PLAS>(A, xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// The surrogate build without the 2-waves bound (about 430 VGPRs and AGPRs,
+// 1 wave per SIMD, no spills): faster where most points reach the network,
+// slower where few do (the march then runs at half the occupancy).
+template <typename R, int TX, int TY>
+__global__ __launch_bounds__(PDN_TILE_THREADS(TX, TY)) __attribute__((amdgpu_waves_per_eu(1)))
+void k_elem_node_sur_wide(ElemArgs<R> A)
+{
+    elem_node_tile<R, TX, TY, true, 1, false>(A, xcd_tile(blockIdx.x, gridDim.x));
+}
+
 // many plates in one launch: case c has start[c+1] - start[c] tiles.  After
 // the ncase + 1 offsets, the table holds for each block (after the XCD remap)
 // its case and its tile within the case (gridDim.x entries each), in the
@@ -1105,6 +1122,21 @@ static hipError_t launch_elem_node_v(const ElemArgs<R> &a, int tile, hipStream_t
     case PDN_TILE_8x8: return launch_en<R, 8, 8, SUR>(a, s);
     case PDN_TILE_15x15: return launch_en<R, 15, 15, SUR>(a, s);
     case PDN_TILE_31x15: return launch_en<R, 31, 15, SUR>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// the surrogate build at 1 wave per SIMD: built for the 15x15 tile (a
+// workgroup of 16x16 node columns is four waves, one per SIMD; the larger
+// tiles' workgroups put two waves on a SIMD)
+template <typename R>
+static hipError_t launch_elem_node_sur_wide_v(const ElemArgs<R> &a, int tile, hipStream_t s)
+{
+    const int nb = a.tiles_x * a.tiles_y;
+    switch (tile) {
+    case PDN_TILE_15x15:
+        hipLaunchKernelGGL((k_elem_node_sur_wide<R, 15, 15>), dim3(nb), dim3(PDN_TILE_THREADS(15, 15)), 0, s, a);
+        return hipGetLastError();
     default: return hipErrorInvalidValue;
     }
 }

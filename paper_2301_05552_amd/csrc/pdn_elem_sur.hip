@@ -13,6 +13,14 @@ template hipError_t launch_elem_node_sur<float>(const ElemArgs<float> &, int, hi
 template hipError_t launch_elem_node_sur<double>(const ElemArgs<double> &, int, hipStream_t);
 
 template <typename R>
+hipError_t launch_elem_node_sur_wide(const ElemArgs<R> &a, int tile, hipStream_t s)
+{
+    return launch_elem_node_sur_wide_v<R>(a, tile, s);
+}
+template hipError_t launch_elem_node_sur_wide<float>(const ElemArgs<float> &, int, hipStream_t);
+template hipError_t launch_elem_node_sur_wide<double>(const ElemArgs<double> &, int, hipStream_t);
+
+template <typename R>
 hipError_t launch_elem_node_batch_sur(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
                                       hipStream_t s)
 {

@@ -66,7 +66,8 @@ struct DevGlobals {
     int64_t step;                    // completed steps
     int64_t hist_cap;
     int32_t first;                   // first contact pass after (re)initialisation
-    int32_t flag_unstable, flag_overflow, pad0;
+    int32_t flag_unstable, flag_overflow;
+    int32_t plain_prev;              // the pass whose element terms the books sum next ran the plain build
     // energy books at the last complete level
     double e_level, e_kep, e_kes, e_wint, e_wgp, e_wgs, e_wc, e_ws, e_uel, ke0;
     double half_int, mz0;            // opening half of the current interval; initial sum m d_z
@@ -74,6 +75,8 @@ struct DevGlobals {
     int64_t reset_passes, released, max_passes, active;
     double fallback_gp;              // surrogate: consulted GP updates that the exact law produced
     double sur_gp;                   // surrogate: GP updates on which the network was consulted
+    double sur_unscreened;           // surrogate plies stepped by the plain build: GP updates the
+                                     // screen did not pass (the exact law produced them)
     unsigned int pad1;
 };
 

@@ -133,16 +133,17 @@ __global__ void k_project_max(const double *in, int64_t ncol, int nlayers, doubl
 // ---------------------------------------------------------------------------
 
 template <typename R>
-hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, int ngp, hipStream_t s)
+hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, int sur, int ngp, hipStream_t s)
 {
     if (ngp == 8)
         return sur ? hipErrorInvalidValue
                    : a.ep ? launch_elem_node_full_plas<R>(a, tile, s) : launch_elem_node_full<R>(a, tile, s);
     if (a.ep) return sur ? hipErrorInvalidValue : launch_elem_node_plas<R>(a, tile, s);
+    if (sur == 2 && tile == PDN_TILE_15x15) return launch_elem_node_sur_wide<R>(a, tile, s);
     return sur ? launch_elem_node_sur<R>(a, tile, s) : launch_elem_node_v<R, false>(a, tile, s);
 }
-template hipError_t launch_elem_node<float>(const ElemArgs<float> &, int, bool, int, hipStream_t);
-template hipError_t launch_elem_node<double>(const ElemArgs<double> &, int, bool, int, hipStream_t);
+template hipError_t launch_elem_node<float>(const ElemArgs<float> &, int, int, int, hipStream_t);
+template hipError_t launch_elem_node<double>(const ElemArgs<double> &, int, int, int, hipStream_t);
 
 template <typename R>
 hipError_t launch_books(const ElemArgs<R> &a, hipStream_t s)

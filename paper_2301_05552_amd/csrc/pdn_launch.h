@@ -22,10 +22,12 @@ enum { PDN_TILE_16x16 = 0, PDN_TILE_32x8 = 1, PDN_TILE_8x8 = 2, PDN_TILE_15x15 =
 static const int pdn_tile_dims[PDN_TILE_COUNT][2] = {{16, 16}, {32, 8}, {8, 8}, {15, 15}, {31, 15}};
 
 namespace pdn {
-// sur: the instantiation that evaluates the surrogate network on plies of law 2;
-// ngp: Gauss points of a bulk element (1 with hourglass control, or 8)
+// sur: 0 the plain build; 1 the build that evaluates the surrogate network on
+// plies of law 2 (held to 2 waves per SIMD); 2 the same at 1 wave per SIMD
+// (15x15 tile; other tiles take 1).  ngp: Gauss points of a bulk
+// element (1 with hourglass control, or 8)
 template <typename R>
-hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, bool sur, int ngp, hipStream_t s);
+hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, int sur, int ngp, hipStream_t s);
 // shear plasticity (one point, a.ep non-null): built for the 15x15 and 16x16 tiles
 template <typename R>
 hipError_t launch_elem_node_plas(const ElemArgs<R> &a, int tile, hipStream_t s);
@@ -45,6 +47,9 @@ template <typename R>
 hipError_t launch_books(const ElemArgs<R> &a, hipStream_t s);
 template <typename R>
 hipError_t launch_elem_node_sur(const ElemArgs<R> &a, int tile, hipStream_t s);
+// the same at 1 wave per SIMD (15x15 tile)
+template <typename R>
+hipError_t launch_elem_node_sur_wide(const ElemArgs<R> &a, int tile, hipStream_t s);
 // batched launches: case c owns blocks start[c] .. start[c+1]-1 (args and start in device memory)
 // contact: the arguments are contact passes; a books kernel closes each case's step
 template <typename R>

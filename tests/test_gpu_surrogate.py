@@ -241,27 +241,31 @@ def test_surrogate_runs_and_training_are_reproducible():
 def test_surrogate_multi_tile_runs_repeat_bitwise():
     """A plate of several 15 x 15 tiles, whose rim elements two workgroups
     evaluate, with network outputs accepted (residual bar 1): two runs give
-    the same state bit for bit.  Rim elements keep the exact law (the other
-    workgroup may read their thresholds before or after the update), so no
-    result depends on the order in which workgroups run."""
-    _note("surrogate reproducibility on a 40x40x4 plate (9 tiles)")
+    the same state bit for bit, and the network build at 1 wave per SIMD
+    (mode 2) gives the same bits as the one at 2 waves (mode 1).  Rim
+    elements keep the exact law (the other workgroup may read their
+    thresholds before or after the update), so no result depends on the
+    order in which workgroups run."""
+    _note("surrogate reproducibility on a 40x40x4 plate (9 tiles), both network builds")
     cfg = W.tiny(40, 40, 4, 1, angles=[0, 90, 0, 90], law=W.LAW_CDM, lx=20e-3, ly=20e-3,
                  ply_thickness=0.5e-3, v0=20.0, mass=0.05, R=4e-3, precision=W.PREC_MIXED)
     nets = _trained_networks(cfg, steps=300)
     out = []
-    for _ in range(2):
+    for mode in (1, 1, 2):
         g = pdn.Simulation(cfg, tile=(15, 15))
         for p, w in enumerate(nets):
             g.surrogate_set(p, w, 0.05, 1.0)
-        g.surrogate_kernel(1)
+        g.surrogate_kernel(mode)
         for _ in range(4):
             g.step(150)
         out.append((g.array_get(pdn.ARR_DISP), g.array_get(pdn.ARR_GP_R), g.contact_force()[1], g.info()))
         g.close()
-    (da, ra, fa, ia), (db, rb, fb, ib) = out
+    (da, ra, fa, ia) = out[0]
     assert ia["sur_consulted"] > 0 and ia["fallback_fraction"] < 1.0      # network outputs were accepted
     assert ia["sur_network_steps"] == 600
-    assert np.array_equal(da, db) and np.array_equal(ra, rb) and np.array_equal(fa, fb)
+    for db, rb, fb, ib in out[1:]:
+        assert np.array_equal(da, db) and np.array_equal(ra, rb) and np.array_equal(fa, fb)
+        assert ib["sur_consulted"] == ia["sur_consulted"] and ib["fallback_fraction"] == ia["fallback_fraction"]
 
 
 def test_surrogate_build_is_chosen_per_call():
