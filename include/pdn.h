@@ -305,7 +305,7 @@ int pdn_surrogate_set(pdn_ctx *ctx, int32_t ply, const float *weights, int64_t n
  * surrogate plies by the exact law (so such a call costs what the plain path
  * costs) and still counts the points the screen does not pass; when it met
  * some, the build that evaluates the network, at 2 waves per SIMD while they
- * are under a tenth of its GP updates, else at 1 wave per SIMD (no register
+ * are under 1 % of its GP updates, else at 1 wave per SIMD (no register
  * spills around the network; on 15x15 tiles, others take the 2-wave
  * build); right after pdn_surrogate_set, the 2-wave network build.  The
  * first call after such points appear is stepped by the exact law; results

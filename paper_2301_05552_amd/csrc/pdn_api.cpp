@@ -29,10 +29,14 @@ struct Buf {
 }  // namespace
 
 // Share of a call's GP updates outside the law's screen above which the
-// surrogate network runs in its 1-wave-per-SIMD build.  On the 1200x800x16
-// plate a step took about 0.74 + 5.1 f ms with the 2-wave build and
-// 0.99 + 3.4 f ms with the 1-wave build, f the share (equal at f = 0.14).
-constexpr double SUR_WIDE_SHARE = 0.1;
+// surrogate network runs in its 1-wave-per-SIMD build.  A wave with one such
+// point evaluates the network for all its lanes, so what decides is the
+// share of waves, which sparse points make much larger than f.  Measured:
+// on the 300x200x8 plate at f = 1.3 %, 0.141 (1-wave) against 0.198 ms per
+// step (2-wave); on the 1200x800x16 plate at f = 1, 4.35 against 5.9 ms;
+// with no point outside the screen the 1-wave build's march costs a third
+// more on the large plate (that case runs the plain build).
+constexpr double SUR_WIDE_SHARE = 0.01;
 
 struct pdn_ctx {
     std::string err;
