@@ -119,3 +119,32 @@ def test_batch_rejects_cases_of_other_precisions():
     assert e.value.code == EINVAL and "repeats" in str(e.value)
     for s in sims:
         s.close()
+
+
+def test_forced_instability_and_snap_back_rejection():
+    """Failure paths forced from the host: a time step three times the stable
+    one makes the explicit scheme diverge, and pdn_step reports
+    PDN_EUNSTABLE (non-finite state) and keeps reporting it; a fibre law
+    whose bilinear softening is not ordered at the element size (a toughness
+    far too small for the crack band) is rejected by pdn_material_set."""
+    _note("errors: forced instability (cfl_safety 3), snap-back rejection")
+    EUNSTABLE = -5
+    cfg = _cfg()
+    cfg["mesh"]["cfl_safety"] = 3.0
+    s = pdn.Simulation(cfg)
+    code, steps = None, 0
+    while code is None and steps < 5000:
+        try:
+            s.step(100)
+            steps += 100
+        except pdn.PdnError as e:
+            code = e.code
+    assert code == EUNSTABLE, (code, steps)
+    assert _code(s.step, 1) == EUNSTABLE
+    s.close()
+    t = pdn.Simulation(_cfg())
+    bad = copy.deepcopy(_cfg()["materials"][0])
+    bad["GXT"] = 1.0                       # J/m^2: the softening would start below the onset strain
+    assert _code(t.material_set, 0, bad) == EINVAL
+    t.step(5)                              # the context keeps its materials and steps on
+    t.close()
