@@ -398,6 +398,7 @@ def coupon_leg(levels, stream, full_levels=()) -> dict:
         cfg["mesh"]["integration"] = ngp
         sim = pdn.Simulation(cfg, stream=stream)
         sim.step(0)                      # set-up (stable time step) without stepping
+        tx, ty = sim.autotune()          # the tile shape that runs this plate fastest
         info = sim.info()
         n = int(math.ceil(cfg["t_end"] / info["dt"]))
         torch.cuda.synchronize()
@@ -425,6 +426,7 @@ def coupon_leg(levels, stream, full_levels=()) -> dict:
         out[key] = {
             "mesh": f"{m['nx']}x{m['ny']} in-plane, {m['elems_per_ply']} element(s) per cluster, 6 interfaces",
             "integration": "2x2x2 Gauss points" if ngp == 8 else "one point with hourglass control",
+            "tile": f"{tx}x{ty}",
             "bulk_gauss_points": info["n_bulk"], "interface_pairs": info["n_pairs"],
             "dt_s": info["dt"], "steps": n, "wall_s": el, "ms_per_step": 1e3 * el / n,
             "value": info["n_bulk"] * n / el, "unit": "GP-updates/s",

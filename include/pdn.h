@@ -119,8 +119,9 @@ typedef struct {
      * in effective stress, yield when tau_L > Sp + Kp G12 abar (abar the
      * accumulated plastic shear), radial return; the damage criteria act on
      * the stress of the elastic strains; one plastic state per Gauss point
-     * (one-point or full integration).  Needs G13 = G12, the 15x15 or 16x16
-     * tile, no surrogate plies and no batch; otherwise PDN_EINVAL. */
+     * (one-point or full integration).  Needs G13 = G12, the 15x15, 16x16
+     * or 8x8 tile (full integration: 15x15 or 16x16), no surrogate plies and
+     * no batch; otherwise PDN_EINVAL. */
     double Sp, Kp;
 } pdn_material;
 
@@ -204,8 +205,9 @@ int pdn_state_save(const pdn_ctx *ctx, void *buf, int64_t cap, int64_t *n_out);
 int pdn_state_load(pdn_ctx *ctx, const void *buf, int64_t n);
 /* Element-tile shape of the element/node kernel (autotuner hook): 0, 0 = the
  * default, 15 x 15 element columns.  Others: 16x16, 32x8, 8x8, 31x15 (full
- * integration and shear plasticity: 15x15 and 16x16 only).  PDN_EINVAL for
- * other shapes or one whose workgroup does not fit the device's LDS. */
+ * integration: 15x15 and 16x16 only; shear plasticity: 15x15, 16x16 and
+ * 8x8).  PDN_EINVAL for other shapes or one whose workgroup does not fit
+ * the device's LDS. */
 int pdn_set_tile(pdn_ctx *ctx, int32_t tile_x, int32_t tile_y);
 /* Mean device time per step of the element/node kernel (with the contact
  * step on the top plane) and of the one-workgroup books kernel that closes

@@ -345,8 +345,9 @@ int prepare(pdn_ctx *c)
         if (ply_plastic(c->mat[p])) c->plastic = true;
     if (c->plastic) {
         if (c->use_sur) return set_err(c, PDN_EINVAL, "shear plasticity and surrogate plies are not built together");
-        if (!pdn::tile_has_full(c->tile))
-            return set_err(c, PDN_EINVAL, "shear plasticity is built for the 15x15 and 16x16 tiles");
+        if (c->ngp == 1 ? !pdn::tile_has_plas(c->tile) : !pdn::tile_has_full(c->tile))
+            return set_err(c, PDN_EINVAL, "shear plasticity is built for the 15x15, 16x16 and 8x8 tiles "
+                                          "(with full integration: 15x15 and 16x16)");
         if (!c->ep) {                 // plastic state, zero at the start (Algorithm 4)
             const size_t bytes = 4 * (size_t)c->ngp * (size_t)std::max<int64_t>(1, c->ne) * rsize(c);
             if ((rc = dalloc(c, &c->ep, bytes))) return rc;
@@ -1624,7 +1625,8 @@ int pdn_autotune(pdn_ctx *c, int32_t *tile_x, int32_t *tile_y)
     } else {
         float best_ms = 0;
         for (int t : kTileOrder) {
-            if (!tile_fits(c, t) || ((c->ngp == 8 || plas) && !pdn::tile_has_full(t))) continue;
+            if (!tile_fits(c, t) || (c->ngp == 8 && !pdn::tile_has_full(t)) || (plas && !pdn::tile_has_plas(t)))
+                continue;
             float ms = 0;
             if ((rc = use_tile(c, t)) || (rc = time_single(c, 3, &ms))) return rc;
             if (best < 0 || ms < best_ms) { best = t; best_ms = ms; }

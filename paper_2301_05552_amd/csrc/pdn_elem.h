@@ -1193,6 +1193,7 @@ static hipError_t launch_elem_node_plas_v(const ElemArgs<R> &a, int tile, hipStr
     switch (tile) {
     case PDN_TILE_16x16: return launch_en<R, 16, 16, false, 1, true>(a, s);
     case PDN_TILE_15x15: return launch_en<R, 15, 15, false, 1, true>(a, s);
+    case PDN_TILE_8x8: return launch_en<R, 8, 8, false, 1, true>(a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -28,7 +28,7 @@ namespace pdn {
 // element (1 with hourglass control, or 8)
 template <typename R>
 hipError_t launch_elem_node(const ElemArgs<R> &a, int tile, int sur, int ngp, hipStream_t s);
-// shear plasticity (one point, a.ep non-null): built for the 15x15 and 16x16 tiles
+// shear plasticity (one point, a.ep non-null): built for the 15x15, 16x16 and 8x8 tiles
 template <typename R>
 hipError_t launch_elem_node_plas(const ElemArgs<R> &a, int tile, hipStream_t s);
 // full integration (ngp 8): built for the 15x15 and 16x16 tiles
@@ -42,6 +42,9 @@ template <typename R>
 hipError_t launch_elem_node_batch_full(const ElemArgs<R> *args, const int *start, int ncase, int nblocks, int tile,
                                        hipStream_t s);
 inline bool tile_has_full(int tile) { return tile == PDN_TILE_15x15 || tile == PDN_TILE_16x16; }
+// one-point elements with shear plasticity: those and 8x8 (more workgroups on small plates;
+// the autotuner chooses)
+inline bool tile_has_plas(int tile) { return tile_has_full(tile) || tile == PDN_TILE_8x8; }
 // closes a contact pass (a.contact): books, striker update, history row
 template <typename R>
 hipError_t launch_books(const ElemArgs<R> &a, hipStream_t s);

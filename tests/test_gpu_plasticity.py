@@ -64,14 +64,14 @@ def test_plastic_mixed_peak_force():
 
 
 def test_plastic_state_is_tile_invariant_and_repeatable():
-    """A ragged multi-tile plate: 15x15 and 16x16 tiles give bitwise equal
+    """A ragged multi-tile plate: 15x15, 16x16 and 8x8 tiles give bitwise equal
     plastic states, thresholds and displacements (rim elements read their
     plastic state before or after its owner updates it), and a second run
     repeats the first bit for bit."""
     _note("plasticity mixed 41x29x4+3 tiles 15x15 / 16x16, repeat")
     cfg = plastic_case(41, 29, W.PREC_MIXED)
     runs = []
-    for tile in ((15, 15), (16, 16), (15, 15)):
+    for tile in ((15, 15), (16, 16), (8, 8), (15, 15)):
         g = pdn.Simulation(cfg, tile=tile)
         g.step(900)
         runs.append([g.array_get(pdn.ARR_GP_EP), g.array_get(pdn.ARR_GP_R), g.array_get(pdn.ARR_DISP),
