@@ -306,10 +306,9 @@ int pdn_surrogate_set(pdn_ctx *ctx, int32_t ply, const float *weights, int64_t n
  * point that the law's screen did not pass, the plain build, which steps the
  * surrogate plies by the exact law (so such a call costs what the plain path
  * costs) and still counts the points the screen does not pass; when it met
- * some, the build that evaluates the network, at 2 waves per SIMD while they
- * are under 1 % of its GP updates, else at 1 wave per SIMD (no register
- * spills around the network; on 15x15 tiles, others take the 2-wave
- * build); right after pdn_surrogate_set, the 2-wave network build.  The
+ * some, or right after pdn_surrogate_set, the build that evaluates the
+ * network at 1 wave per SIMD (no register spills around the network; on
+ * 15x15 tiles, other tiles take the build held to 2 waves per SIMD).  The
  * first call after such points appear is stepped by the exact law; results
  * can differ with how steps are split into calls.  mode 1 always uses the
  * 2-wave network build, mode 2 the 1-wave one (both network builds compute

@@ -28,16 +28,6 @@ struct Buf {
 
 }  // namespace
 
-// Share of a call's GP updates outside the law's screen above which the
-// surrogate network runs in its 1-wave-per-SIMD build.  A wave with one such
-// point evaluates the network for all its lanes, so what decides is the
-// share of waves, which sparse points make much larger than f.  Measured:
-// on the 300x200x8 plate at f = 1.3 %, 0.141 (1-wave) against 0.198 ms per
-// step (2-wave); on the 1200x800x16 plate at f = 1, 4.35 against 5.9 ms;
-// with no point outside the screen the 1-wave build's march costs a third
-// more on the large plate (that case runs the plain build).
-constexpr double SUR_WIDE_SHARE = 0.01;
-
 struct pdn_ctx {
     std::string err;
     int device = 0;
@@ -97,12 +87,14 @@ struct pdn_ctx {
     std::vector<int> ply_net;
     double sur_dmg = 0.05, sur_res = 1e-3;
     // which build steps the surrogate plies in a pdn_step call (0 plain, 1
-    // network at 2 waves/SIMD, 2 network at 1 wave/SIMD): mode 0 picks per
-    // call from the share of GP updates of the previous call that the screen
-    // did not pass (none: the plain build, which steps those plies by the
-    // exact law and counts such points; under SUR_WIDE_SHARE: build 1; else
-    // build 2; right after a network was set: build 1); modes 1 and 2 pin
-    // that build
+    // network at 2 waves/SIMD, 2 network at 1 wave/SIMD where built): mode 0
+    // picks per call from the previous call (a point outside the law's screen
+    // or a network just set: build 2; none: the plain build, which steps those
+    // plies by the exact law and counts such points); modes 1 and 2 pin that
+    // build.  Build 2 is the faster network build in every case measured on
+    // MI355X (1200x800x16 plate: 1.04 against 2.12 ms per step with no point
+    // consulting the network, 4.35 against 5.9 with every point; 300x200x8
+    // plate, 1.3 % consulting: 0.141 against 0.198 ms)
     int sur_mode = 0;
     int sur_build = 1;
     bool sur_fresh = true;
@@ -883,17 +875,12 @@ int pdn_step(pdn_ctx *c, int64_t n)
     }
     if ((rc = ensure_history(c, c->gl.step + n))) return rc;
     if (c->use_sur && n > 0) {
-        // build for this call, from the previous call's share of GP updates
-        // outside the screen (network build 2 pays at high shares, 1 at low)
+        // build for this call, from the previous call's points outside the screen
         const double outside = c->gl.sur_gp + c->gl.sur_unscreened;
-        if (c->sur_mode != 0) {
+        if (c->sur_mode != 0)
             c->sur_build = c->sur_mode;
-        } else if (c->sur_fresh || c->sur_prev_n <= 0) {
-            c->sur_build = 1;
-        } else {
-            const double share = (outside - c->sur_gp_mark) / ((double)c->sur_prev_n * c->ngp * c->ne);
-            c->sur_build = share <= 0.0 ? 0 : share < SUR_WIDE_SHARE ? 1 : 2;
-        }
+        else
+            c->sur_build = c->sur_fresh || c->sur_prev_n <= 0 || outside > c->sur_gp_mark ? 2 : 0;
         c->sur_fresh = false;
         c->sur_gp_mark = outside;
         c->sur_prev_n = n;
