@@ -407,7 +407,9 @@ class Simulation:
         self._chk(lib().pdn_surrogate_set(self.h, ply, _fp(w), w.size, dmg_thresh, res_thresh))
 
     def surrogate_kernel(self, mode: int):
-        """0: choose the network or the plain build per step call; 1: always the network build."""
+        """pdn_surrogate_kernel.  0: choose per step call between the plain
+        build and the network build at 1 wave/SIMD; 1: always the network
+        build held to 2 waves/SIMD; 2: always the 1-wave network build."""
         self._chk(lib().pdn_surrogate_kernel(self.h, mode))
 
     def autotune(self):
