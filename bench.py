@@ -36,6 +36,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "Gauss-point updates/s per explicit step; plain vs surrogate at \u22640.5% force error"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_elem_node_plate1200x800x16_traffic.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "k_elem_node_variants_plate1200x800x16_sq_counters.txt")
+WKEY_HEADLINE = "plate1200x800x16/prec1/tile15x15"          # the workload the SQ summary was taken on
 # every source the element/node kernel is compiled from: the counter summary
 # is used only while they are unchanged
 KERNEL_SOURCES = tuple(f"paper_2301_05552_amd/csrc/{f}" for f in (
@@ -79,6 +81,23 @@ def measured_traffic(workload_key: str):
     if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload_key") != workload_key:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def measured_valu_busy(variant: str):
+    """Share of the kernel's cycles in which the vector ALUs issue, for an
+    element/node kernel variant ("one_point", "one_point_plastic", "full",
+    "full_plastic"), from the committed SQ counter summary of the
+    1200x800x16 plate.  None when the summary is missing or was taken on a
+    different kernel source."""
+    try:
+        with open(SQ_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh if ":" in line and not line.startswith(" "))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256") != kernel_source_hash() or f"valu_busy_{variant}" not in kv:
+        return None
+    return float(kv[f"valu_busy_{variant}"])
 
 
 def copy_calibration(nbytes: int):
@@ -349,7 +368,9 @@ def full_integration_leg(stream, pre, warmup, steps, plain_ms, plastic=False) ->
             "value": ngp * steps / el, "unit": "GP-updates/s", "kernel_ms": en_ms, "books_kernel_ms": bk_ms,
             "element_steps_vs_one_point": plain_ms / ms,
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
+                         "frac": achieved / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes,
+                         # eight law calls per element: vector instruction issue, not HBM, limits it
+                         "valu_busy": measured_valu_busy("full_plastic" if plastic else "full")}}
 
 
 def plastic_leg(stream, pre, warmup, steps, plain_ms) -> dict:
@@ -373,7 +394,8 @@ def plastic_leg(stream, pre, warmup, steps, plain_ms) -> dict:
             "tile": "15x15", "steps": steps, "ms_per_step": ms, "value": info["n_bulk"] / (ms * 1e-3),
             "unit": "GP-updates/s", "kernel_ms": en_ms, "books_kernel_ms": bk_ms, "vs_plain": plain_ms / ms,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes,
+                         "valu_busy": measured_valu_busy("one_point_plastic")}}
 
 
 # Section 3.2.2, Table 4: the paper's own numerical results for the AS4/8552
@@ -814,7 +836,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wkey),
                      "kernel": "k_elem_node", "workload_key": wkey, "kernel_ms": en_ms, "books_kernel_ms": bk_ms,
-                     "algorithmic_bytes_per_launch": bytes_launch},
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "valu_busy": measured_valu_busy("one_point") if wkey == WKEY_HEADLINE else None},
     }
     log("copy ceiling: streaming copy of 2 GiB")
     cc = copy_ceiling(stream)
