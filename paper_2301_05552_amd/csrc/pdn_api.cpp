@@ -96,7 +96,7 @@ struct pdn_ctx {
     // consulting the network, 4.35 against 5.9 with every point; 300x200x8
     // plate, 1.3 % consulting: 0.141 against 0.198 ms)
     int sur_mode = 0;
-    int sur_build = 1;
+    int sur_build = 2;                 // also the build of set-up evaluations
     bool sur_fresh = true;
     double sur_gp_mark = 0.0;
     int64_t sur_prev_n = 0;
@@ -2156,6 +2156,7 @@ int pdn_surrogate_kernel(pdn_ctx *c, int32_t mode)
     if (!c) return PDN_EINVAL;
     if (mode < 0 || mode > 2) return set_err(c, PDN_EINVAL, "surrogate kernel mode must be 0, 1 or 2");
     c->sur_mode = mode;
+    c->sur_build = mode != 0 ? mode : 2;
     return PDN_OK;
 }
 
