@@ -321,7 +321,13 @@ __device__ void hex_box_force_full(const R ux[8], const R uy[8], const R uz[8], 
         R Pn[9];
         bool ch = false, pch = false;
         int ex = 0;
-        wsum += box_point<R, false, PLAS>(G, P, vol, rg, ch, Pn, nullptr, 0.f, 0.f, ex, epg, &pch);
+        // The law's element-size terms (crack band, capped strengths) are
+        // needed only where a point leaves the elastic screen: an empty asm
+        // on the volume keeps the compiler from hoisting them out of this
+        // loop, where every element would compute them whether used or not.
+        R volg = vol;
+        asm volatile("" : "+v"(volg));
+        wsum += box_point<R, false, PLAS>(G, P, volg, rg, ch, Pn, nullptr, 0.f, 0.f, ex, epg, &pch);
         if (own && ch) store_state(rstate, e8 + g * gs, rg);
         if constexpr (PLAS) {
             if (own && pch) store_state(epstate, e8 + g * gs, epg);
