@@ -156,11 +156,16 @@ typedef struct {
     int64_t n_nodes, n_bulk, n_cohesive, n_pairs, n_planes, n_layers, n_candidates;
     int64_t steps, reset_passes, released, active, max_passes;
     double fallback_fraction;     /* surrogate: of the GP updates on which the network was consulted,
-                                     the fraction that the exact law produced (0 when none was) */
+                                     the fraction whose answer failed the residual bar and that the
+                                     exact law produced (0 when none was consulted) */
     int32_t precision, tile_x, tile_y, blocks;
-    double sur_consulted;         /* surrogate: GP updates on which the network was consulted (or, in
-                                     steps of the plain build, would have been); the others of
-                                     surrogate plies were screened elastic by the law */
+    double sur_consulted;         /* surrogate: GP updates on which the network was consulted (its
+                                     answer computed and checked against the residual bar).  Points
+                                     outside the law's screen whose incoming damage passes the gate,
+                                     or of elements two workgroups evaluate, take the exact law
+                                     without it and are not counted.  In steps of the plain build:
+                                     the points outside the screen.  The others of surrogate plies
+                                     were screened elastic by the law */
     int64_t sur_network_steps;    /* surrogate: steps run by the build that evaluates the network */
 } pdn_info;
 

@@ -25,8 +25,10 @@ namespace pdn {
 // thresholds before or after their owner updates them, which the exact law's
 // idempotent update tolerates and the network would not.  Every lane of the
 // wave must call it together (the network runs on the matrix cores).  exact:
-// 0 the network's result, 1 the exact law after the network was consulted (or
-// a shared element), 2 screened elastic.
+// 0 the network's result; 1 the exact law after the network was consulted
+// and its answer failed the residual bar; 2 screened elastic; 3 the exact law
+// without consulting the network (incoming damage past dmg_thr, or a shared
+// element).
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6], bool &changed,
@@ -54,6 +56,7 @@ __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
     for (int k = 0; k < 4; ++k) x[6 + k] = (float)(R(1) - R(1) / r[k]);
     bool fb = shared || ((r[0] > R(1) || r[1] > R(1) || r[2] > R(1) || r[3] > R(1)) &&
                          cdm_max_damage(P, lc, YT, YC, SL, r) > (R)dmg_thr);
+    const bool gated = fb;                                      // the network is not consulted
     if (__ballot(!fb && !el) != 0) sur_forward_wave(pk, x, y);  // uniform across the wave
     if (el) {
 #pragma unroll
@@ -90,7 +93,7 @@ __device__ void sur_update(const PlyC<R> &P, R vol, const R e[6], R r[4], R sg[6
         const R den = rmax(s0 * s0 + s1 * s1 + s2 * s2 + s3 * s3 + s4 * s4 + s5 * s5, R(1e-6) * P.YT * P.YT);
         fb = num > (R)res_thr * (R)res_thr * den;
     }
-    exact = fb ? 1 : 0;
+    exact = gated ? 3 : fb ? 1 : 0;
     if (fb) {
         cdm_update(P, vol, e, r, sg, changed);
         return;
@@ -848,8 +851,15 @@ __device__ __forceinline__ void elem_node_tile(const ElemArgs<R> &A, const int t
                         }
                         acc[T_UEL] += (double)uel;
                         if (P.law == 2) {
-                            acc[T_AUX] += exact == 1 ? 1.0 : 0.0;      // fallback after consulting the network
-                            acc[T_SURN] += exact != 2 ? 1.0 : 0.0;     // network consulted
+                            if constexpr (SUR) {
+                                // consulted: the network's answer was computed and checked
+                                acc[T_AUX] += exact == 1 ? 1.0 : 0.0;  // checked and rejected: exact law
+                                acc[T_SURN] += (exact == 0 || exact == 1) ? 1.0 : 0.0;
+                            } else {
+                                // points outside the screen (those a network build would consider)
+                                acc[T_AUX] += exact == 1 ? 1.0 : 0.0;
+                                acc[T_SURN] += exact != 2 ? 1.0 : 0.0;
+                            }
                         }
                     }
                 }

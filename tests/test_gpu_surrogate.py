@@ -335,8 +335,10 @@ def test_what_the_network_gains_over_the_exact_law():
     every point consults the network, (a) at rest and (b) released from a
     uniform in-plane stretch at half the transverse onset strain.  Each is
     stepped by the exact law and by the network at the residual bars 1e-3
-    (the stated one) and 1.  Every point is consulted; no more points are
-    accepted at 1e-3 than at 1; at the stated bar the network's answers are
+    (the stated one) and 1.  Every point is outside the law's screen; those
+    whose incoming damage is under the gate (0.05) consult the network, the
+    others take the exact law without it.  No more points are accepted at
+    1e-3 than at 1; at the stated bar the network's answers are
     taken on under 1 % of the points (its bf16 operands limit its accuracy
     to about 1e-2).  The residual bar checks that the network's stress is
     consistent with its own thresholds, not that those are the law's: the
@@ -382,7 +384,9 @@ def test_what_the_network_gains_over_the_exact_law():
               f"1e-3 {lo['ns_per_gp']:.3f} (accepted {lo['accepted']:.2e}, displacement diff {d_lo:.2e}), "
               f"network bar 1 {hi['ns_per_gp']:.3f} (accepted {hi['accepted']:.2e}, displacement diff "
               f"{d_hi:.2e})", flush=True)
-        assert lo["consulted"] == 1.0 and hi["consulted"] == 1.0    # every point asks the network
+        print(f"[surrogate gains, {what}] consulted: bar 1e-3 {lo['consulted']:.3f}, bar 1 {hi['consulted']:.3f} "
+              f"of the GP updates", flush=True)
+        assert lo["consulted"] > 0 and hi["consulted"] > 0           # the network is asked
         assert lo["accepted"] <= hi["accepted"]
         # at the stated bar the network's answers are rarely taken
         assert lo["accepted"] < 1e-2
