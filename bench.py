@@ -734,7 +734,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default="plate1200x800x16", choices=["plate300x200x8", "plate1200x800x16"])
     ap.add_argument("--precision", type=int, default=1)
     ap.add_argument("--tile", default="15x15")
