@@ -216,8 +216,12 @@ int pdn_state_load(pdn_ctx *ctx, const void *buf, int64_t n);
 int pdn_set_tile(pdn_ctx *ctx, int32_t tile_x, int32_t tile_y);
 /* Mean device time per step of the element/node kernel (with the contact
  * step on the top plane) and of the one-workgroup books kernel that closes
- * the step, over the last pdn_step call, from HIP events (0 if not timed). */
+ * the step, over the last timed pdn_step call, from HIP events (0 if none
+ * was timed). */
 int pdn_kernel_times(const pdn_ctx *ctx, double *elem_node_ms, double *books_ms);
+/* Time the following pdn_step calls (on != 0) or not.  Switching it on
+ * creates the events for calls of up to 1,024 steps (longer calls add more),
+ * so that a timed call holds only its launches and event records. */
 int pdn_set_timing(pdn_ctx *ctx, int32_t on);
 /* Measurement hook (not a step of the method): copy `bytes` (a multiple of
  * 16, 16-byte aligned device pointers) from src to dst on `device` with the

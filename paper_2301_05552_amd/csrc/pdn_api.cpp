@@ -101,9 +101,12 @@ struct pdn_ctx {
     double sur_gp_mark = 0.0;
     int64_t sur_prev_n = 0;
     int64_t sur_net_steps = 0;
-    // timing
+    // timing: events are kept between calls (creating them inside a timed
+    // call would add host time to it) and read when the times are asked for
     bool timing = false;
     double t_en_ms = 0, t_bk_ms = 0;
+    std::vector<hipEvent_t> tev;       // 3 per step: start, between the two kernels, end
+    int64_t tev_n = 0;                 // steps of the last timed call not yet read
 };
 
 namespace {
@@ -468,6 +471,37 @@ ContactArgs contact_args(pdn_ctx *c, int buf)
     a.ci0 = c->ci0; a.ci1 = c->ci1; a.cj0 = c->cj0; a.cj1 = c->cj1;
     a.active = c->active_d; a.vprev = c->vprev_d; a.fcprev = c->fcprev_d; a.cand = c->cand_d;
     return a;
+}
+
+// at least `need` timing events in the context's pool
+int timing_pool(pdn_ctx *c, int64_t need)
+{
+    while ((int64_t)c->tev.size() < need) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->tev.push_back(e);
+    }
+    return PDN_OK;
+}
+
+// mean kernel times of the last timed call, from its events (complete: the
+// call synchronised its stream before returning)
+int timing_collect(pdn_ctx *c)
+{
+    const int64_t n = c->tev_n;
+    if (n <= 0) return PDN_OK;
+    double a = 0, b = 0;
+    for (int64_t s = 0; s < n; ++s) {
+        float t = 0, u = 0;
+        HIPCHK(c, hipEventElapsedTime(&t, c->tev[3 * s], c->tev[3 * s + 1]));
+        HIPCHK(c, hipEventElapsedTime(&u, c->tev[3 * s + 1], c->tev[3 * s + 2]));
+        a += t;
+        b += u;
+    }
+    c->t_en_ms = a / n;
+    c->t_bk_ms = b / n;
+    c->tev_n = 0;
+    return PDN_OK;
 }
 
 // one pass; a contact pass is closed by the books kernel (an event between
@@ -886,11 +920,11 @@ int pdn_step(pdn_ctx *c, int64_t n)
         c->sur_prev_n = n;
         if (c->sur_build != 0) c->sur_net_steps += n;
     }
-    std::vector<hipEvent_t> ev;
     if (c->timing && n > 0) {
-        ev.resize(3 * n);
-        for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+        if ((rc = timing_collect(c))) return rc;       // the previous call's, before its events are reused
+        if ((rc = timing_pool(c, 3 * n))) return rc;
     }
+    hipEvent_t *ev = c->tev.data();
     // one pass per step: the element/node update of the whole plate with the
     // contact step (Algorithms 1-2) on its top plane, then the books kernel
     for (int64_t s = 0; s < n; ++s) {
@@ -902,19 +936,7 @@ int pdn_step(pdn_ctx *c, int64_t n)
         c->cand_dirty = true;
     }
     if ((rc = sync_globals_from_device(c))) return rc;
-    if (c->timing && n > 0) {
-        double a = 0, b = 0;
-        for (int64_t s = 0; s < n; ++s) {
-            float t = 0, u = 0;
-            HIPCHK(c, hipEventElapsedTime(&t, ev[3 * s], ev[3 * s + 1]));
-            HIPCHK(c, hipEventElapsedTime(&u, ev[3 * s + 1], ev[3 * s + 2]));
-            a += t;
-            b += u;
-        }
-        for (auto &e : ev) (void)hipEventDestroy(e);
-        c->t_en_ms = a / n;
-        c->t_bk_ms = b / n;
-    }
+    if (c->timing && n > 0) c->tev_n = n;                  // read by pdn_kernel_times
     if (c->gl.flag_unstable) {
         c->broken = true;
         return set_err(c, PDN_EUNSTABLE, "non-finite displacement at step %lld", (long long)c->gl.step);
@@ -1328,9 +1350,13 @@ int pdn_set_tile(pdn_ctx *c, int32_t tx, int32_t ty)
     return PDN_OK;
 }
 
-int pdn_kernel_times(const pdn_ctx *c, double *en, double *bk)
+int pdn_kernel_times(const pdn_ctx *cc, double *en, double *bk)
 {
-    if (!c) return PDN_EINVAL;
+    if (!cc) return PDN_EINVAL;
+    pdn_ctx *c = const_cast<pdn_ctx *>(cc);
+    (void)hipSetDevice(c->device);
+    int rc = timing_collect(c);
+    if (rc) return rc;
     if (en) *en = c->t_en_ms;
     if (bk) *bk = c->t_bk_ms;
     return PDN_OK;
@@ -1340,7 +1366,8 @@ int pdn_set_timing(pdn_ctx *c, int32_t on)
 {
     if (!c) return PDN_EINVAL;
     c->timing = on != 0;
-    return PDN_OK;
+    (void)hipSetDevice(c->device);
+    return c->timing ? timing_pool(c, 3 * 1024) : PDN_OK;   // events for calls of up to 1,024 steps
 }
 
 const char *pdn_last_error(const pdn_ctx *c) { return c ? c->err.c_str() : "null context"; }
@@ -1351,6 +1378,7 @@ void pdn_destroy(pdn_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     free_all(c);
+    for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
