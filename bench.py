@@ -86,7 +86,7 @@ def measured_traffic(workload_key: str):
 def measured_valu_busy(variant: str):
     """Share of the kernel's cycles in which the vector ALUs issue, for an
     element/node kernel variant ("one_point", "one_point_plastic", "full",
-    "full_plastic"), from the committed SQ counter summary of the
+    "full_plastic", "fp64", "batch"), from the committed SQ counter summary of the
     1200x800x16 plate.  None when the summary is missing or was taken on a
     different kernel source."""
     try:
@@ -281,7 +281,9 @@ def fp64_leg(stream, pre, warmup, steps) -> dict:
             "value": info["n_bulk"] / (ms * 1e-3), "unit": "GP-updates/s", "kernel_ms": en_ms,
             "books_kernel_ms": bk_ms,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
+                         "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes,
+                         # one wave per SIMD: memory latency, not issue, holds it
+                         "valu_busy": measured_valu_busy("fp64")}}
 
 
 def batched_leg(steps: int, warmup: int, stream) -> dict:
@@ -323,7 +325,7 @@ def batched_leg(steps: int, warmup: int, stream) -> dict:
             # a lower bound on the element/node kernel's rate
             "roofline": {"bound": "hbm", "achieved": nbytes / (el / steps) / 1e9, "peak": 8000.0,
                          "unit": "GB/s", "frac": nbytes / (el / steps) / 8e12, "timing": "whole step",
-                         "algorithmic_bytes_per_step": nbytes}}
+                         "algorithmic_bytes_per_step": nbytes, "valu_busy": measured_valu_busy("batch")}}
 
 
 def full_integration_leg(stream, pre, warmup, steps, plain_ms, plastic=False) -> dict:
