@@ -229,10 +229,13 @@ int pdn_set_timing(pdn_ctx *ctx, int32_t on);
  * it reaches is the practical ceiling the element/node kernel's roofline is
  * read against.  PDN_EINVAL on bad sizes or alignment. */
 int pdn_stream_copy(int32_t device, void *stream, const void *src, void *dst, int64_t bytes);
-/* Autotuner: time one element/node pass per supported tile shape that fits
- * the device, keep the fastest (remembered per plate shape for the process)
- * and report it.  The timed passes recompute the current predictor, so the
- * simulation state is unchanged.  ESTATE before materials and striker. */
+/* Autotuner: time ten element/node passes per supported tile shape that
+ * fits the device, keep the fastest (remembered per plate shape for the
+ * process) and report it.  The default 15 x 15 is kept unless another shape
+ * is faster by more than 5 %: the timed passes leave out the contact step
+ * and the books kernel, whose work grows with the number of tiles.  They
+ * recompute the current predictor, so the simulation state is unchanged.
+ * ESTATE before materials and striker. */
 int pdn_autotune(pdn_ctx *ctx, int32_t *tile_x, int32_t *tile_y);
 
 /* Batched stepping of independent impact cases (many plates of uneven size

@@ -1638,15 +1638,20 @@ int pdn_autotune(pdn_ctx *c, int32_t *tile_x, int32_t *tile_y)
     if (it != tune_cache().end()) {
         best = it->second;
     } else {
-        float best_ms = 0;
+        // The passes timed are restart passes (no contact step, no books
+        // kernel, whose work grows with the number of tiles): another shape
+        // replaces the default 15 x 15 only when it is faster by a margin.
+        float best_ms = 0, dflt_ms = -1;
         for (int t : kTileOrder) {
             if (!tile_fits(c, t) || (c->ngp == 8 && !pdn::tile_has_full(t)) || (plas && !pdn::tile_has_plas(t)))
                 continue;
             float ms = 0;
-            if ((rc = use_tile(c, t)) || (rc = time_single(c, 3, &ms))) return rc;
+            if ((rc = use_tile(c, t)) || (rc = time_single(c, 10, &ms))) return rc;
+            if (t == PDN_TILE_15x15) dflt_ms = ms;
             if (best < 0 || ms < best_ms) { best = t; best_ms = ms; }
         }
         if (best < 0) return set_err(c, PDN_EINVAL, "no element tile fits this device");
+        if (dflt_ms > 0 && best != PDN_TILE_15x15 && best_ms > 0.95f * dflt_ms) best = PDN_TILE_15x15;
         tune_cache()[key] = best;
     }
     if ((rc = use_tile(c, best))) return rc;
