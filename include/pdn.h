@@ -314,17 +314,18 @@ int pdn_surrogate_train(const pdn_sur_train *opt, const pdn_material *m, double 
 int pdn_surrogate_set(pdn_ctx *ctx, int32_t ply, const float *weights, int64_t n, double dmg_thresh,
                       double res_thresh);
 /* Which kernel build steps a context with surrogate plies.  mode 0 (the
- * default) chooses per pdn_step call from the previous call: when it met no
- * point that the law's screen did not pass, the plain build, which steps the
- * surrogate plies by the exact law (so such a call costs what the plain path
- * costs) and still counts the points the screen does not pass; when it met
- * some, or right after pdn_surrogate_set, the build that evaluates the
- * network at 1 wave per SIMD (no register spills around the network; on
- * 15x15 tiles, other tiles take the build held to 2 waves per SIMD).  The
- * first call after such points appear is stepped by the exact law; results
- * can differ with how steps are split into calls.  mode 1 always uses the
- * 2-wave network build, mode 2 the 1-wave one (both network builds compute
- * the same bits).
+ * default) chooses per pdn_step call from the previous call: when that call
+ * met no point that would consult the network (in the plain build: no point
+ * outside the law's screen; in a network build: no point that consulted it),
+ * the plain build, which steps the surrogate plies by the exact law (so such
+ * a call costs what the plain path costs) and still counts the points outside
+ * the screen; otherwise, and right after pdn_surrogate_set, the build that
+ * evaluates the network at 1 wave per SIMD (no register spills around the
+ * network; on 15x15 tiles, other tiles take the build held to 2 waves per
+ * SIMD), which set-up evaluations also use.  The first call after such
+ * points appear is stepped by the exact law; results can differ with how
+ * steps are split into calls.  mode 1 always uses the 2-wave network build,
+ * mode 2 the 1-wave one (both network builds compute the same bits).
  * PDN_EINVAL for other modes. */
 int pdn_surrogate_kernel(pdn_ctx *ctx, int32_t mode);
 /* Forward pass on n points: x is n x 10 inputs, y receives n x 10 outputs. */
