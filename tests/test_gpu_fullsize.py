@@ -211,3 +211,39 @@ def test_full_size_200_steps_light_cone():
           f"{int((gr > st['r'].reshape(-1, 4)[eid[sel_e]]).sum())} of {gr.size} centre values", flush=True)
     assert worst["d"] <= 1e-10 and worst["v"] <= 1e-9, worst
     assert worst["r"] <= 1e-10 and worst["rd"] <= 1e-10, worst
+
+
+def test_benchmark_plate_whole_run_20000_steps():
+    """The benchmark's whole run: the 1200 x 800 x 16 plate for its 20,000
+    steps (0.21 ms) from rest, in mixed precision and in FP64, in the 15 x 15
+    launch.  Each run stays stable with the contact inside its search window,
+    its energy identity closes to 1e-6 of the impact energy, thresholds never
+    fall below onset, and the mixed run's contact-force history (peak and
+    final value) and striker displacement stay within 0.5 % of the FP64 run's
+    (FP64 on the GPU is held to the oracle by the tests above)."""
+    _note("1200x800x16 plate, the benchmark's 20,000 steps, mixed and fp64")
+    out = {}
+    for prec in (W.PREC_MIXED, W.PREC_FP64):
+        sim = pdn.Simulation(W.plate_qi8_1200x800x16(prec), tile=(15, 15))
+        try:
+            for k in range(4):
+                sim.step(5000)
+                print(f"[20k] precision {prec}: {5000 * (k + 1)} steps", flush=True)
+            _, f, x = sim.contact_force()
+            e = sim.energies()
+            r = sim.array_get(pdn.ARR_GP_R)
+            assert np.isfinite(r).all() and r.min() >= 1.0
+            assert abs(e["residual"]) <= 1e-6 * e["ke0"], (e["residual"], e["ke0"])
+            out[prec] = dict(f=f, x=x, dmg=int((sim.damage_field(pdn.DMG_MATRIX) > 0).sum()),
+                             res=e["residual"] / e["ke0"])
+        finally:
+            sim.close()
+    m, d = out[W.PREC_MIXED], out[W.PREC_FP64]
+    assert len(m["f"]) == len(d["f"]) == 20000
+    print(f"[20k] fp64: peak force {d['f'].max():.2f} N, final {d['f'][-1]:.2f} N, striker {d['x'][-1]:.4e} m, "
+          f"matrix-damaged points {d['dmg']}, energy residual {d['res']:.1e} of the impact energy; mixed: peak "
+          f"{m['f'].max():.2f} N, final {m['f'][-1]:.2f} N, striker {m['x'][-1]:.4e} m, damaged {m['dmg']}, "
+          f"residual {m['res']:.1e}", flush=True)
+    assert d["f"].max() > 100.0                                # the striker has loaded the plate
+    assert abs(m["f"].max() - d["f"].max()) <= 5e-3 * d["f"].max()
+    assert abs(m["x"][-1] - d["x"][-1]) <= 5e-3 * abs(d["x"][-1])
