@@ -226,10 +226,13 @@ def _window(sim, steps, precision, what) -> dict:
     ach = nbytes / (en_ms * 1e-3) / 1e9
     dm = sim.damage_field(pdn.DMG_MATRIX)
     _, f, _ = sim.contact_force()
+    e = sim.energies()
     return {"window": what, "steps": steps, "at_step": info["steps"], "ms_per_step": ms,
             "value": info["n_bulk"] / (ms * 1e-3), "unit": "GP-updates/s", "kernel_ms": en_ms,
             "books_kernel_ms": bk_ms, "matrix_damaged_gps": int((dm > 0).sum()),
             "contact_force_N": float(f[-1]) if len(f) else 0.0,
+            "peak_force_N": float(f.max()) if len(f) else 0.0,
+            "energy_residual_of_impact_energy": e["residual"] / e["ke0"] if e["ke0"] else 0.0,
             "roofline": {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "algorithmic_bytes_per_launch": nbytes}}
 
