@@ -105,7 +105,7 @@ struct pdn_ctx {
     // call would add host time to it) and read when the times are asked for
     bool timing = false;
     double t_en_ms = 0, t_bk_ms = 0;
-    std::vector<hipEvent_t> tev;       // 3 per step: start, between the two kernels, end
+    std::vector<hipEvent_t> tev;       // per step: its start and the point between its two kernels; one more at the end
     int64_t tev_n = 0;                 // steps of the last timed call not yet read
 };
 
@@ -493,8 +493,8 @@ int timing_collect(pdn_ctx *c)
     double a = 0, b = 0;
     for (int64_t s = 0; s < n; ++s) {
         float t = 0, u = 0;
-        HIPCHK(c, hipEventElapsedTime(&t, c->tev[3 * s], c->tev[3 * s + 1]));
-        HIPCHK(c, hipEventElapsedTime(&u, c->tev[3 * s + 1], c->tev[3 * s + 2]));
+        HIPCHK(c, hipEventElapsedTime(&t, c->tev[2 * s], c->tev[2 * s + 1]));
+        HIPCHK(c, hipEventElapsedTime(&u, c->tev[2 * s + 1], c->tev[2 * s + 2]));
         a += t;
         b += u;
     }
@@ -922,19 +922,20 @@ int pdn_step(pdn_ctx *c, int64_t n)
     }
     if (c->timing && n > 0) {
         if ((rc = timing_collect(c))) return rc;       // the previous call's, before its events are reused
-        if ((rc = timing_pool(c, 3 * n))) return rc;
+        if ((rc = timing_pool(c, 2 * n + 1))) return rc;
     }
     hipEvent_t *ev = c->tev.data();
     // one pass per step: the element/node update of the whole plate with the
     // contact step (Algorithms 1-2) on its top plane, then the books kernel
     for (int64_t s = 0; s < n; ++s) {
         const int pred = 1 - c->cur;
-        if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s], c->stream));
-        if ((rc = launch_en(c, pred, c->cur, 1, c->timing ? ev[3 * s + 1] : nullptr))) return rc;
-        if (c->timing) HIPCHK(c, hipEventRecord(ev[3 * s + 2], c->stream));
+        // a step's books kernel ends where the next step starts (two events per step)
+        if (c->timing) HIPCHK(c, hipEventRecord(ev[2 * s], c->stream));
+        if ((rc = launch_en(c, pred, c->cur, 1, c->timing ? ev[2 * s + 1] : nullptr))) return rc;
         c->cur = pred;
         c->cand_dirty = true;
     }
+    if (c->timing && n > 0) HIPCHK(c, hipEventRecord(ev[2 * n], c->stream));
     if ((rc = sync_globals_from_device(c))) return rc;
     if (c->timing && n > 0) c->tev_n = n;                  // read by pdn_kernel_times
     if (c->gl.flag_unstable) {
@@ -1367,7 +1368,7 @@ int pdn_set_timing(pdn_ctx *c, int32_t on)
     if (!c) return PDN_EINVAL;
     c->timing = on != 0;
     (void)hipSetDevice(c->device);
-    return c->timing ? timing_pool(c, 3 * 1024) : PDN_OK;   // events for calls of up to 1,024 steps
+    return c->timing ? timing_pool(c, 2 * 1024 + 1) : PDN_OK;   // events for calls of up to 1,024 steps
 }
 
 const char *pdn_last_error(const pdn_ctx *c) { return c ? c->err.c_str() : "null context"; }
